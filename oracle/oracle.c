@@ -1,0 +1,480 @@
+/*
+ * FP64 reference oracle for fused lattice field expressions and APE link
+ * smearing.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The HIP library never calls
+ * it, and the two share no source, header, table or helper.
+ *
+ * It is deliberately plain: C99, double precision, explicit real/imaginary
+ * arithmetic written out term by term, one loop over lattice sites (OpenMP
+ * only splits that loop), no blocking or reordering beyond the definitions.
+ * Reductions store one value per site and sum the array serially with
+ * Neumaier compensation, so the result does not depend on the thread count.
+ *
+ * Host canonical layout (shared with the input generators):
+ *   extents L = {Lx, Ly, Lz, Lt}; site = x + Lx*(y + Ly*(z + Lz*t));
+ *   links    double[V][4][3][3][2]  (site, direction mu, row a, column b, re/im)
+ *   fermions double[V][4][3][2]     (site, spin, colour, re/im)
+ * All directions are periodic.
+ *
+ * What is computed, and where it is defined:
+ *   - shift(X, FORWARD, mu)(x) = X(x + mu) and the hop U_mu(x) X(x + mu):
+ *     the paper's Jacobi-smearing listing (expressions E_1/E_2) and the
+ *     hopping term of the smearing operator K in section 7.
+ *   - chi = sum_mu U_mu(x) psi(x+mu) + a phi(x): the forward hop summed over
+ *     mu plus the axpy of expression E_3 (section 7); a*phi is added once.
+ *   - The APE step (staple sum, combination with weight alpha, row
+ *     Gram-Schmidt reunitarisation) and the plaquette are not in the paper;
+ *     they follow the workload definition of one APE step on a periodic
+ *     lattice with all directions smeared from the unsmeared links.
+ *
+ * Parity pins for every function live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct { double re, im; } cplx;
+typedef struct { cplx e[3][3]; } mat3;
+
+/* ------------------------------------------------------------------ */
+/* complex scalar arithmetic                                           */
+/* ------------------------------------------------------------------ */
+static cplx c_make(double re, double im) { cplx z; z.re = re; z.im = im; return z; }
+static cplx c_add(cplx a, cplx b) { return c_make(a.re + b.re, a.im + b.im); }
+static cplx c_sub(cplx a, cplx b) { return c_make(a.re - b.re, a.im - b.im); }
+static cplx c_mul(cplx a, cplx b) { return c_make(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+static cplx c_conj(cplx a) { return c_make(a.re, -a.im); }
+static cplx c_scale(double s, cplx a) { return c_make(s * a.re, s * a.im); }
+static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+/* ------------------------------------------------------------------ */
+/* 3x3 complex matrices                                                */
+/* ------------------------------------------------------------------ */
+static mat3 m_zero(void) { mat3 m; memset(&m, 0, sizeof m); return m; }
+
+/* C = A B */
+static mat3 m_mul(const mat3 *A, const mat3 *B)
+{
+    mat3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = c_make(0.0, 0.0);
+            for (int k = 0; k < 3; ++k) s = c_add(s, c_mul(A->e[i][k], B->e[k][j]));
+            C.e[i][j] = s;
+        }
+    return C;
+}
+
+/* C = A^dagger */
+static mat3 m_dag(const mat3 *A)
+{
+    mat3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C.e[i][j] = c_conj(A->e[j][i]);
+    return C;
+}
+
+static mat3 m_add(const mat3 *A, const mat3 *B)
+{
+    mat3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C.e[i][j] = c_add(A->e[i][j], B->e[i][j]);
+    return C;
+}
+
+static double m_retrace(const mat3 *A) { return A->e[0][0].re + A->e[1][1].re + A->e[2][2].re; }
+
+/* ------------------------------------------------------------------ */
+/* lattice indexing (periodic)                                         */
+/* ------------------------------------------------------------------ */
+typedef struct { int L[4]; long V; } lat;
+
+static lat lat_make(const int *L)
+{
+    lat g;
+    for (int d = 0; d < 4; ++d) g.L[d] = L[d];
+    g.V = (long)L[0] * L[1] * L[2] * L[3];
+    return g;
+}
+
+static void site_coords(const lat *g, long s, int c[4])
+{
+    for (int d = 0; d < 4; ++d) { c[d] = (int)(s % g->L[d]); s /= g->L[d]; }
+}
+
+static long coords_site(const lat *g, const int c[4])
+{
+    return c[0] + (long)g->L[0] * (c[1] + (long)g->L[1] * (c[2] + (long)g->L[2] * c[3]));
+}
+
+/* site reached from s by `step` (+1 or -1) in direction mu, wrapping around */
+static long hop(const lat *g, long s, int mu, int step)
+{
+    int c[4];
+    site_coords(g, s, c);
+    c[mu] = ((c[mu] + step) % g->L[mu] + g->L[mu]) % g->L[mu];
+    return coords_site(g, c);
+}
+
+static mat3 load_link(const double *U, long s, int mu)
+{
+    mat3 m;
+    const double *p = U + ((s * 4 + mu) * 9) * 2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m.e[a][b] = c_make(p[(a * 3 + b) * 2], p[(a * 3 + b) * 2 + 1]);
+    return m;
+}
+
+static void store_link(double *U, long s, int mu, const mat3 *m)
+{
+    double *p = U + ((s * 4 + mu) * 9) * 2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            p[(a * 3 + b) * 2] = m->e[a][b].re;
+            p[(a * 3 + b) * 2 + 1] = m->e[a][b].im;
+        }
+}
+
+static cplx load_fermion(const double *f, long s, int spin, int col)
+{
+    const double *p = f + ((s * 4 + spin) * 3 + col) * 2;
+    return c_make(p[0], p[1]);
+}
+
+static void store_fermion(double *f, long s, int spin, int col, cplx v)
+{
+    double *p = f + ((s * 4 + spin) * 3 + col) * 2;
+    p[0] = v.re;
+    p[1] = v.im;
+}
+
+/* Neumaier-compensated serial sum. */
+double oracle_neumaier_sum(long n, const double *x)
+{
+    double s = 0.0, comp = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double t = s + x[i];
+        if (fabs(s) >= fabs(x[i])) comp += (s - t) + x[i];
+        else comp += (x[i] - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* shift expression                                                    */
+/* ------------------------------------------------------------------ */
+
+/* chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x)   (phi may be NULL).
+ * U acts on colour and is the identity in spin.  If norm2 is not NULL it
+ * receives sum over sites, spins and colours of |chi|^2. */
+void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, const double *phi,
+                           double a, double *chi, double *norm2)
+{
+    lat g = lat_make(L);
+    double *site_norm = norm2 ? (double *)malloc(sizeof(double) * (size_t)g.V) : NULL;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        cplx acc[4][3];
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) acc[sp][c] = c_make(0.0, 0.0);
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3 u = load_link(U, s, mu);
+            long fwd = hop(&g, s, mu, +1);
+            for (int sp = 0; sp < 4; ++sp)
+                for (int ca = 0; ca < 3; ++ca)
+                    for (int cb = 0; cb < 3; ++cb)
+                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
+        }
+        double n2 = 0.0;
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) {
+                cplx v = acc[sp][c];
+                if (phi) v = c_add(v, c_scale(a, load_fermion(phi, s, sp, c)));
+                store_fermion(chi, s, sp, c, v);
+                n2 += c_abs2(v);
+            }
+        if (site_norm) site_norm[s] = n2;
+    }
+    if (norm2) {
+        *norm2 = oracle_neumaier_sum(g.V, site_norm);
+        free(site_norm);
+    }
+}
+
+/* n_iter repetitions of: chi_k = shift_mul_axpy(U, psi_{k-1}, phi, a);
+ *                        psi_k = psi_{k-1} - c * chi_k.
+ * psi is updated in place; norms (may be NULL) receives |chi_k|^2. */
+void oracle_shift_chain(const int *L, const double *U, double *psi, const double *phi, double a,
+                        double c, int n_iter, double *norms)
+{
+    lat g = lat_make(L);
+    size_t nf = (size_t)g.V * 4 * 3 * 2;
+    double *chi = (double *)malloc(sizeof(double) * nf);
+    for (int k = 0; k < n_iter; ++k) {
+        oracle_shift_mul_axpy(L, U, psi, phi, a, chi, norms ? &norms[k] : NULL);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < (long)nf; ++i) psi[i] = psi[i] - c * chi[i];
+    }
+    free(chi);
+}
+
+/* ------------------------------------------------------------------ */
+/* APE smearing                                                        */
+/* ------------------------------------------------------------------ */
+
+/* upper staple of U_mu(x) in the (mu, nu) plane: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dagger */
+static mat3 staple_upper(const lat *g, const double *U, long s, int mu, int nu)
+{
+    mat3 a = load_link(U, s, nu);
+    mat3 b = load_link(U, hop(g, s, nu, +1), mu);
+    mat3 c = load_link(U, hop(g, s, mu, +1), nu);
+    mat3 cd = m_dag(&c);
+    mat3 ab = m_mul(&a, &b);
+    return m_mul(&ab, &cd);
+}
+
+/* lower staple: U_nu(x-nu)^dagger U_mu(x-nu) U_nu(x-nu+mu) */
+static mat3 staple_lower(const lat *g, const double *U, long s, int mu, int nu)
+{
+    long sm = hop(g, s, nu, -1);
+    mat3 a = load_link(U, sm, nu);
+    mat3 b = load_link(U, sm, mu);
+    mat3 c = load_link(U, hop(g, sm, mu, +1), nu);
+    mat3 ad = m_dag(&a);
+    mat3 ab = m_mul(&ad, &b);
+    return m_mul(&ab, &c);
+}
+
+/* Sup(x,mu) = sum_{nu != mu} upper staples, Slo(x,mu) = sum_{nu != mu} lower
+ * staples, nu taken in increasing order.  Either output may be NULL. */
+void oracle_staple_sums(const int *L, const double *U, double *Sup, double *Slo)
+{
+    lat g = lat_make(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3 up = m_zero(), lo = m_zero();
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == mu) continue;
+                mat3 su = staple_upper(&g, U, s, mu, nu);
+                mat3 sl = staple_lower(&g, U, s, mu, nu);
+                up = m_add(&up, &su);
+                lo = m_add(&lo, &sl);
+            }
+            if (Sup) store_link(Sup, s, mu, &up);
+            if (Slo) store_link(Slo, s, mu, &lo);
+        }
+}
+
+/* W_mu(x) = (1-alpha) U_mu(x) + (alpha/6) sum_{nu != mu} [upper + lower staple],
+ * the six staples accumulated for nu = 0..3 (skipping mu), upper before lower. */
+static mat3 ape_w_link(const lat *g, const double *U, long s, int mu, double alpha)
+{
+    mat3 S = m_zero();
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        mat3 su = staple_upper(g, U, s, mu, nu);
+        S = m_add(&S, &su);
+        mat3 sl = staple_lower(g, U, s, mu, nu);
+        S = m_add(&S, &sl);
+    }
+    mat3 u = load_link(U, s, mu);
+    mat3 W;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            W.e[i][j] = c_add(c_scale(1.0 - alpha, u.e[i][j]), c_scale(alpha / 6.0, S.e[i][j]));
+    return W;
+}
+
+/* Reunitarise by rows: u = r1/|r1|; v = r2 - (sum_j conj(u_j) r2_j) u, v /= |v|;
+ * w = conj(u x v).  Returns 0, or 1 if a row norm was zero (the output is then NaN). */
+static int reunitarise(const mat3 *W, mat3 *V)
+{
+    cplx u[3], v[3];
+    double n0 = 0.0;
+    for (int j = 0; j < 3; ++j) n0 += c_abs2(W->e[0][j]);
+    n0 = sqrt(n0);
+    int bad = (n0 == 0.0);
+    for (int j = 0; j < 3; ++j) u[j] = c_scale(1.0 / n0, W->e[0][j]);
+
+    cplx d = c_make(0.0, 0.0);
+    for (int j = 0; j < 3; ++j) d = c_add(d, c_mul(c_conj(u[j]), W->e[1][j]));
+    for (int j = 0; j < 3; ++j) v[j] = c_sub(W->e[1][j], c_mul(d, u[j]));
+    double n1 = 0.0;
+    for (int j = 0; j < 3; ++j) n1 += c_abs2(v[j]);
+    n1 = sqrt(n1);
+    bad |= (n1 == 0.0);
+    for (int j = 0; j < 3; ++j) v[j] = c_scale(1.0 / n1, v[j]);
+
+    for (int j = 0; j < 3; ++j) {
+        V->e[0][j] = u[j];
+        V->e[1][j] = v[j];
+    }
+    V->e[2][0] = c_conj(c_sub(c_mul(u[1], v[2]), c_mul(u[2], v[1])));
+    V->e[2][1] = c_conj(c_sub(c_mul(u[2], v[0]), c_mul(u[0], v[2])));
+    V->e[2][2] = c_conj(c_sub(c_mul(u[0], v[1]), c_mul(u[1], v[0])));
+    if (bad) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) V->e[i][j] = c_make(NAN, NAN);
+    }
+    return bad;
+}
+
+/* Unprojected APE combination W for every link. */
+void oracle_ape_w(const int *L, const double *U, double alpha, double *W)
+{
+    lat g = lat_make(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3 w = ape_w_link(&g, U, s, mu, alpha);
+            store_link(W, s, mu, &w);
+        }
+}
+
+/* Row Gram-Schmidt projection of n_links matrices (layout [n][3][3][2]).
+ * Returns the number of degenerate inputs. */
+long oracle_reunitarise(long n_links, const double *W, double *V)
+{
+    long bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (long i = 0; i < n_links; ++i) {
+        mat3 w, v;
+        const double *p = W + (size_t)i * 18;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) w.e[a][b] = c_make(p[(a * 3 + b) * 2], p[(a * 3 + b) * 2 + 1]);
+        bad += reunitarise(&w, &v);
+        double *q = V + (size_t)i * 18;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                q[(a * 3 + b) * 2] = v.e[a][b].re;
+                q[(a * 3 + b) * 2 + 1] = v.e[a][b].im;
+            }
+    }
+    return bad;
+}
+
+/* One APE step: V_mu(x) = Proj[W_mu(x)] for all links, all from the unsmeared U.
+ * Returns the number of degenerate links. */
+long oracle_ape_step(const int *L, const double *U, double alpha, double *Vout)
+{
+    lat g = lat_make(L);
+    long bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (long s = 0; s < g.V; ++s)
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3 w = ape_w_link(&g, U, s, mu, alpha), v;
+            bad += reunitarise(&w, &v);
+            store_link(Vout, s, mu, &v);
+        }
+    return bad;
+}
+
+/* n_steps APE steps; Vout receives the last step, U is not modified. */
+long oracle_ape_smear(const int *L, const double *U, double alpha, int n_steps, double *Vout)
+{
+    lat g = lat_make(L);
+    size_t nl = (size_t)g.V * 4 * 18;
+    double *cur = (double *)malloc(sizeof(double) * nl);
+    long bad = 0;
+    memcpy(cur, U, sizeof(double) * nl);
+    for (int k = 0; k < n_steps; ++k) {
+        bad += oracle_ape_step(L, cur, alpha, Vout);
+        memcpy(cur, Vout, sizeof(double) * nl);
+    }
+    if (n_steps == 0) memcpy(Vout, U, sizeof(double) * nl);
+    free(cur);
+    return bad;
+}
+
+/* One APE step evaluated only for the listed links (site[i], mu[i]). */
+long oracle_ape_links(const int *L, const double *U, double alpha, long n, const long *site,
+                      const int *mu, double *Vout)
+{
+    lat g = lat_make(L);
+    long bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (long i = 0; i < n; ++i) {
+        mat3 w = ape_w_link(&g, U, site[i], mu[i], alpha), v;
+        bad += reunitarise(&w, &v);
+        double *q = Vout + (size_t)i * 18;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                q[(a * 3 + b) * 2] = v.e[a][b].re;
+                q[(a * 3 + b) * 2 + 1] = v.e[a][b].im;
+            }
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
+/* plaquette                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Re Tr [U_mu(x) U_nu(x+mu) U_mu(x+nu)^dagger U_nu(x)^dagger] */
+static double plaq_site(const lat *g, const double *U, long s, int mu, int nu)
+{
+    mat3 a = load_link(U, s, mu);
+    mat3 b = load_link(U, hop(g, s, mu, +1), nu);
+    mat3 c = load_link(U, hop(g, s, nu, +1), mu);
+    mat3 d = load_link(U, s, nu);
+    mat3 cd = m_dag(&c), dd = m_dag(&d);
+    mat3 ab = m_mul(&a, &b);
+    mat3 abc = m_mul(&ab, &cd);
+    mat3 p = m_mul(&abc, &dd);
+    return m_retrace(&p);
+}
+
+/* out[0] = (1/(18 V)) sum_x sum_{mu<nu} Re Tr P_{mu nu}(x)   (all six planes)
+ * out[1] = (1/(9 V))  sum over the three spatial planes (mu < nu < 3)
+ * out[2] = (1/(9 V))  sum over the three temporal planes (nu = 3)
+ * Unit links give 1 in all three. */
+void oracle_plaquette(const int *L, const double *U, double *out)
+{
+    lat g = lat_make(L);
+    double *sp = (double *)malloc(sizeof(double) * (size_t)g.V);
+    double *tp = (double *)malloc(sizeof(double) * (size_t)g.V);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        double a = 0.0, b = 0.0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                double p = plaq_site(&g, U, s, mu, nu);
+                if (nu == 3) b += p;
+                else a += p;
+            }
+        sp[s] = a;
+        tp[s] = b;
+    }
+    double ssum = oracle_neumaier_sum(g.V, sp);
+    double tsum = oracle_neumaier_sum(g.V, tp);
+    out[0] = (ssum + tsum) / (18.0 * (double)g.V);
+    out[1] = ssum / (9.0 * (double)g.V);
+    out[2] = tsum / (9.0 * (double)g.V);
+    free(sp);
+    free(tp);
+}
