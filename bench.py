@@ -1,0 +1,281 @@
+"""Benchmark: APE link smearing on a 32^3 x 64 lattice on one MI355X.
+
+One timed step = one call of qdpx_ape_smear: 10 APE smearing steps (alpha =
+0.5) of Haar-random SU(3) links, staple products in FP32 with links stored
+as 12 reals, FP64 reunitarisation, and the FP64 plaquette of the input and
+of every step's output.  ``value`` is link updates per second,
+4 * V * 10 * K / elapsed, with the links already resident in HBM.
+
+The same JSON line carries the plain all-FP64 path for comparison, the
+roofline of the dominant kernel (the APE step kernel, timed with HIP events
+on its own stream), the FP64 CPU oracle timed on the host (cpu_baseline), and
+secondary figures for the shift expression.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L = (32, 32, 32, 64)
+N_APE = 10
+ALPHA = 0.5
+
+# Peaks of the MI355X (published): HBM3E 8 TB/s; FP64 vector 78.6 TFLOP/s.
+# FP32 vector is 157.3 TFLOP/s only with packed (two-wide) FP32 FMA; this
+# library is built with packed FP32 disabled, so its FP32 arithmetic issues at
+# the same rate as FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.64
+
+# Algorithmic work per link update of one APE step as implemented (rows 0
+# and 1 of the six staples, combination, FP64 projection, and for LINK12 the
+# rebuild of row 2 of the 15 full links each update loads).
+STAPLE_FLOPS = 6 * 2 * 18 * 8  # 6 staples x 2 products x 18 complex FMA x 8 flop
+COMBINE_FLOPS = 12 * 2 * 3
+PROJECT_FLOPS = 126
+REBUILD_FLOPS = 15 * 42
+FLOPS_PER_LINK = {
+    "f32_12": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + REBUILD_FLOPS,
+    "f64_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS,
+    "f32_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS,
+}
+# Compulsory HBM bytes per link update: read the link once, write it once.
+BYTES_PER_LINK = {"f32_12": 2 * 48, "f64_18": 2 * 144, "f32_18": 2 * 72}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=30)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true")
+    return p.parse_args()
+
+
+def time_calls(torch, fn, k, stream):
+    """HIP-event elapsed milliseconds of k back-to-back calls on `stream`."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(k):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU t-slab design is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import latgen
+    import paper_1105_2279_amd as q
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    ctx = q.Context(0)
+    V = latgen.volume(L)
+    t = time.time()
+    U = latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
+    log(f"generated {L} Haar links in {time.time() - t:.1f} s")
+
+    paths = {"f32_12": (q.F32, q.LINK12), "f64_18": (q.F64, q.LINK18), "f32_18": (q.F32, q.LINK18)}
+    dev_links = {}
+    for name, (prec, fmt) in paths.items():
+        dev_links[name] = q.links_to_device(ctx, L, U, prec, fmt, dev)
+    del U
+    torch.cuda.synchronize()
+
+    def make_call(name, with_plaq=True, n=N_APE):
+        prec, fmt = paths[name]
+        out = q.alloc_links(L, prec, fmt, dev)
+        work = q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev)
+        plaq = torch.zeros(3 * (n + 1), dtype=torch.float64, device=dev) if with_plaq else None
+        src = dev_links[name]
+
+        def call():
+            q.qdpx_ape_smear(ctx, L, prec, fmt, src, out, ALPHA, n, plaq, work, stream)
+
+        return call, out, plaq
+
+    results = {}
+    # ---------------------------------------------------------------- headline
+    head, head_out, head_plaq = make_call("f32_12")
+    for _ in range(args.warmup):
+        head()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps of {N_APE} FP32-12 APE steps + plaquettes")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        head()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = 4.0 * V * N_APE * args.steps / elapsed
+    log(f"headline: {value / 1e9:.2f} G link-updates/s, {1e3 * elapsed / args.steps:.3f} ms/step")
+
+    # ---------------------------------------- per-kernel timing of each path
+    kernel = {}
+    for name in paths:
+        call, _, _ = make_call(name, with_plaq=False)
+        call()
+        reps = max(3, args.steps // 3)
+        ms = time_calls(torch, call, reps, stream)
+        per_kernel_s = ms / 1e3 / (reps * N_APE)
+        kernel[name] = per_kernel_s
+        log(f"{name}: APE kernel {per_kernel_s * 1e6:.1f} us")
+        if name != "f32_12":
+            call_p, _, _ = make_call(name, with_plaq=True)
+            call_p()
+            ms = time_calls(torch, call_p, reps, stream)
+            results[name] = 4.0 * V * N_APE * reps / (ms / 1e3)
+            log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s with plaquettes")
+    results["f32_12"] = value
+
+    def roof(name):
+        t_k = kernel[name]
+        flops = FLOPS_PER_LINK[name] * 4 * V
+        achieved = flops / t_k / 1e12
+        hbm = BYTES_PER_LINK[name] * 4 * V / t_k / 1e9
+        return {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(PEAK_VALU_TFLOPS, 2),
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "k_ape_step<float,2>" if name == "f32_12" else name,
+            "kernel_us": round(t_k * 1e6, 2),
+            "flops_per_link_update": FLOPS_PER_LINK[name],
+            "hbm_gbs_algorithmic": round(hbm, 1),
+            "hbm_frac_algorithmic": round(hbm / PEAK_HBM_GBS, 4),
+        }
+
+    roofline = roof("f32_12")
+
+    # --------------------------------------------------------- extras
+    extras = {
+        "fp64_18_link_updates_per_s": results["f64_18"],
+        "fp32_18_link_updates_per_s": results["f32_18"],
+        "speedup_fp32_12_vs_fp64": results["f32_12"] / results["f64_18"],
+        "ape_kernel_roofline": {k: roof(k) for k in paths},
+        "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
+    }
+    if not args.no_extras:
+        extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(latgen)
+
+    line = {
+        "metric": "APE link-updates/s + HBM GB/s fraction, FP32/batched vs FP64, 32^3x64",
+        "value": value,
+        "unit": "link-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 staples / f64 projection and plaquette",
+        "data": "synthetic: Haar-random SU(3) links, seed 1305",
+        "config": {
+            "workload": "APE smearing, 10 steps alpha=0.5 + FP64 plaquette per step, 32^3x64 periodic, "
+                        "links FP32 12-real",
+            "lattice": list(L),
+            "sites": V,
+            "ape_steps_per_step": N_APE,
+            "parallelism": "1 GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def shift_extras(torch, q, ctx, dev, stream, latgen, np):
+    """Shift expression chi = sum_mu U psi(x+mu) + a phi at 32^3x64 (FP64 and FP32-12)."""
+    Ls = (32, 32, 32, 64)
+    V = latgen.volume(Ls)
+    out = {}
+    seeds = latgen.SEEDS["shift_16x16x16x32"]
+    U = latgen.haar_links(Ls, seeds["links"])
+    psi = latgen.dirac_field(Ls, seeds["psi"])
+    phi = latgen.dirac_field(Ls, seeds["phi"])
+    for name, prec, fmt, bytes_site in (("f64_18", q.F64, q.LINK18, 1152), ("f32_12", q.F32, q.LINK12, 480)):
+        Ud = q.links_to_device(ctx, Ls, U, prec, fmt, dev)
+        pd = q.fermion_to_device(ctx, Ls, psi, prec, dev)
+        fd = q.fermion_to_device(ctx, Ls, phi, prec, dev)
+        chi = q.alloc_fermion(Ls, prec, dev)
+        n2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
+
+        def call():
+            q.qdpx_eval_shift_mul_axpy(ctx, Ls, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work, stream)
+
+        call()
+        reps = 20
+        ms = time_calls(torch, call, reps, stream)
+        t = ms / 1e3 / reps
+        gbs = bytes_site * V / t / 1e9
+        out[f"shift_{name}_32x32x32x64"] = {
+            "sites_per_s": V / t,
+            "us_per_call": t * 1e6,
+            "hbm_gbs_algorithmic": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS,
+        }
+        log(f"shift {name}: {t * 1e6:.1f} us, {gbs:.0f} GB/s")
+        del Ud, pd, fd, chi, work
+    return out
+
+
+def cpu_baseline(latgen):
+    """The FP64 oracle on the host: one APE step over the full 32^3x64 lattice."""
+    import oracle
+
+    U = latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
+    V = latgen.volume(L)
+    threads = oracle.num_threads()
+    log(f"cpu baseline: one oracle APE step on {L} with {threads} threads")
+    t0 = time.perf_counter()
+    oracle.ape_step(U, ALPHA)
+    t = time.perf_counter() - t0
+    log(f"cpu baseline: {t:.1f} s")
+    return {
+        "value": 4.0 * V / t,
+        "unit": "link-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one FP64 APE step over the full {L[0]}^3x{L[3]} lattice ({4 * V} link updates), "
+                  f"{t:.2f} s",
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * qdpx — site-parallel lattice field expressions and APE link smearing on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Background.  The method evaluates lattice-wide expressions of a quantum
+ * field theory code site by site on the GPU (paper: "Accelerating QDP++ using
+ * GPUs", sections 5 and 7).  Its central expression is the nearest-neighbour
+ * hop U_mu(x) psi(x+mu) summed over directions plus an axpy term, the
+ * building block of the Jacobi smearing operator (section 7, equation for K,
+ * and the listing's expressions E_1, E_2, E_3).  This library provides that
+ * expression, an iterated chain of it, one or many APE link-smearing steps
+ * with an SU(3) projection, and the average plaquette.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice: extents L[0..3] = (Lx, Ly, Lz, Lt), 2 <= L[d] <= 4096,
+ *   V = Lx*Ly*Lz*Lt < 2^31; direction mu = 0..3 is x, y, z, t; all
+ *   directions periodic; site = x + Lx*(y + Ly*(z + Lz*t)).
+ * Matrices: U_mu(x) is a 3x3 complex matrix acting on colour,
+ *   (U psi)_a = sum_b U_ab psi_b, identity in spin.  "Row" = first index.
+ * Host canonical layout ("AoS"), FP64, used by the pack/unpack calls:
+ *   links    double[V][4][3][3][2]   (site, mu, row, column, re/im)
+ *   fermions double[V][4][3][2]      (site, spin, colour, re/im)
+ * Library layout ("SoA", opaque to callers, sized by qdpx_links_bytes /
+ *   qdpx_fermion_bytes): one array per matrix entry with the site index
+ *   innermost, padded to a stride S = qdpx_site_stride(geom):
+ *   LINK18: complex[mu][row 0..2][col][S]; LINK12: complex[mu][row 0..1][col][S]
+ *   (row 2 is rebuilt as conj(row0 x row1) on every load, exact for SU(3));
+ *   fermion: complex[spin][colour][S].  "complex" is double2 for QDPX_F64 and
+ *   float2 for QDPX_F32.
+ *
+ * Memory and streams.  Every pointer argument named *_dev, and every field
+ *   argument (U, psi, phi, chi, ...), is a DEVICE pointer owned by the caller.
+ *   The library never allocates, frees or keeps caller memory.  Scratch space
+ *   is a caller-provided device workspace of at least qdpx_workspace_bytes()
+ *   bytes.  Every compute call only enqueues work on `stream` (a hipStream_t
+ *   passed as void*, NULL = the null stream), never synchronises, never
+ *   allocates and issues no memset, so it may be recorded into a HIP graph.
+ *   Scalar results (norms, plaquettes) are written to caller DEVICE buffers
+ *   of doubles.
+ *
+ * Errors.  Every call returns QDPX_OK (0) or a negative qdpx_status.  On a
+ *   validation error nothing is enqueued and no output is written; the
+ *   message is available from qdpx_last_error() (thread-local).  Launch
+ *   errors map to QDPX_EHIP; faults during execution surface at the caller's
+ *   next synchronisation.
+ *
+ * Threading.  A context may be used by one host thread at a time.  Calls
+ *   that overlap on one device must not share a workspace.
+ */
+#ifndef QDPX_H
+#define QDPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QDPX_OK = 0,
+    QDPX_EINVAL = -1,       /* bad extents, sizes, null pointer, n < 1, ... */
+    QDPX_EALIAS = -2,       /* an output overlaps an input it must not overlap */
+    QDPX_ENOMEM = -3,       /* workspace smaller than qdpx_workspace_bytes() */
+    QDPX_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    QDPX_EUNSUPPORTED = -5, /* precision / link format combination not provided */
+    QDPX_ECAPTURE = -6      /* call not allowed while the stream is being captured */
+} qdpx_status;
+
+typedef enum { QDPX_F64 = 0, QDPX_F32 = 1 } qdpx_prec;
+
+/* LINK18 stores all 9 complex entries; LINK12 stores rows 0 and 1 only and
+ * is accepted with QDPX_F32 only. */
+typedef enum { QDPX_LINK18 = 0, QDPX_LINK12 = 1 } qdpx_linkfmt;
+
+typedef struct { int32_t L[4]; } qdpx_geom;
+
+/* Operation ids for qdpx_workspace_bytes() and qdpx_tune(). */
+typedef enum {
+    QDPX_OP_SHIFT = 0,    /* qdpx_eval_shift_mul_axpy */
+    QDPX_OP_CHAIN = 1,    /* qdpx_shift_chain */
+    QDPX_OP_APE = 2,      /* qdpx_ape_smear */
+    QDPX_OP_PLAQ = 3,     /* qdpx_plaquette */
+    QDPX_OP_BATCHED = 4   /* qdpx_ape_smear_batched (n = number of lattices) */
+} qdpx_op;
+
+typedef struct qdpx_ctx qdpx_ctx;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device`.  The context plays the role
+ * of the paper's device storage container (section 5.2): it caches
+ * tuned launch geometries and the per-lattice tables of batched calls.
+ * Returns QDPX_EINVAL for a null `out` or a device that does not exist. */
+int qdpx_create(qdpx_ctx **out, int device);
+
+/* Destroy a context (NULL is accepted).  Frees what the context cached. */
+int qdpx_destroy(qdpx_ctx *ctx);
+
+/* Release every device table cached by the context (the paper's
+ * freeAll of section 6); the context stays usable. */
+int qdpx_free_all(qdpx_ctx *ctx);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *qdpx_last_error(void);
+
+/* Library version string. */
+const char *qdpx_version(void);
+
+/* ------------------------------------------------------------------ sizes */
+
+/* Padded site stride S used by the SoA layout (V rounded up to 256), or -1
+ * for invalid extents. */
+int64_t qdpx_site_stride(const qdpx_geom *geom);
+
+/* Bytes of one SoA link field (all 4 directions) / one SoA Dirac field, or 0
+ * for invalid arguments. */
+size_t qdpx_links_bytes(const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt);
+size_t qdpx_fermion_bytes(const qdpx_geom *geom, qdpx_prec prec);
+
+/* Workspace bytes needed by operation `op` (n = n_steps for APE, n_iter for
+ * the chain, number of lattices for the batched call with `geom` pointing to
+ * that many extents; ignored otherwise).  0 for invalid arguments. */
+size_t qdpx_workspace_bytes(qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, int n);
+
+/* ------------------------------------------------------ pack / unpack (a1)
+ * Conversions between the host canonical AoS layout (already on the device)
+ * and the library SoA layout; the analogue of the paper's push/pop of
+ * lattice objects between memory domains (sections 5.3 and 6).  FP64 -> FP32
+ * rounds to nearest even.  Unpacking LINK12 rebuilds row 2 in FP64. */
+int qdpx_pack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, qdpx_prec prec,
+                    qdpx_linkfmt fmt, void *soa, void *stream);
+int qdpx_unpack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, qdpx_prec prec,
+                      qdpx_linkfmt fmt, double *aos, void *stream);
+int qdpx_pack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, qdpx_prec prec,
+                      void *soa, void *stream);
+int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, qdpx_prec prec,
+                        double *aos, void *stream);
+
+/* ------------------------------------------------- shift expression (a3, a4)
+ * chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a * phi(x)
+ * The forward hop shift(psi, FORWARD, mu) multiplied by the link, summed
+ * over the four directions, plus an axpy term added once (paper section 7:
+ * the hopping term of K and the listing's expressions E_1/E_2 and E_3).
+ *   U: SoA links (prec, fmt); psi, phi: SoA fermions (prec); phi may be NULL
+ *   (then `a` is ignored); chi: SoA fermion output, must not overlap psi, phi
+ *   or U.  norm2 (nullable, device double*) receives sum_x |chi(x)|^2
+ *   accumulated in FP64 for both precisions.  work: workspace of
+ *   work_bytes >= qdpx_workspace_bytes(QDPX_OP_SHIFT, ...). */
+int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                             const void *U, const void *psi, const void *phi, double a, void *chi,
+                             double *norm2, void *work, size_t work_bytes, void *stream);
+
+/* ----------------------------------------------------- expression chain (a5)
+ * n_iter repetitions of  chi_k = sum_mu U_mu(x) psi_{k-1}(x+mu) + a*phi(x);
+ *                        psi_k = psi_{k-1} - c * chi_k
+ * with U and phi fixed (the iteration structure of the paper's smearing
+ * listing).  psi is updated in place; chi is not stored.  norms (nullable,
+ * device double[n_iter]) receives |chi_k|^2 in FP64.  phi may be NULL.
+ * n_iter >= 1.  work: >= qdpx_workspace_bytes(QDPX_OP_CHAIN, ..., n_iter). */
+int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                     const void *U, void *psi, const void *phi, double a, double c, int n_iter,
+                     double *norms, void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------- APE smearing (a6-a10)
+ * n_steps >= 1 APE steps.  One step, for every site x and direction mu,
+ * from the unsmeared links of that step:
+ *   W_mu(x) = (1-alpha) U_mu(x) + (alpha/6) sum_{nu != mu} [
+ *               U_nu(x) U_mu(x+nu) U_nu(x+mu)^dagger
+ *             + U_nu(x-nu)^dagger U_mu(x-nu) U_nu(x-nu+mu) ]
+ *   V_mu(x) = rows (u, v, conj(u x v)) with u = w0/|w0|,
+ *             v = (w1 - (u^dagger w1) u) / |...|   (w0, w1 = rows 0, 1 of W),
+ * the projection always in FP64.  With QDPX_F32 the staple products are
+ * evaluated in FP32.  U_in is not modified; U_out must not overlap U_in.
+ * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
+ * triple (see qdpx_plaquette) of the input and of every step's output.
+ * A W whose row 0 or projected row 1 vanishes gives NaN entries.
+ * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
+int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                   const void *U_in, void *U_out, double alpha, int n_steps, double *plaq,
+                   void *work, size_t work_bytes, void *stream);
+
+/* -------------------------------------------------------------- plaquette (a10)
+ * plaq[0] = (1/(18V)) sum_x sum_{mu<nu} Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]
+ * plaq[1] = the same over the three spatial planes (nu < 3), / (9V)
+ * plaq[2] = the same over the three planes with nu = t,      / (9V)
+ * Products and sums in FP64 for both precisions (FP32 links are widened).
+ * plaq: device double[3].  work: >= qdpx_workspace_bytes(QDPX_OP_PLAQ, ...). */
+int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                   const void *U, double *plaq, void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------ batched APE smearing (a11)
+ * n_lat independent lattices of any extents, each smeared n_steps times as
+ * in qdpx_ape_smear, followed by each lattice's output plaquette triple, in
+ * ONE persistent kernel launch.  geoms: host array [n_lat]; U_in, U_out:
+ * host arrays [n_lat] of device pointers (SoA, prec, fmt; U_out[i] must not
+ * overlap U_in[j] for any i, j); plaq (nullable): device double[n_lat][3].
+ * work: >= qdpx_workspace_bytes(QDPX_OP_BATCHED, geoms, prec, fmt, n_lat),
+ * which holds the per-lattice tables, ping-pong links and counters; it is
+ * re-initialised by a kernel on the stream at every call.
+ * Results are identical, bit for bit, to qdpx_ape_smear on each lattice. */
+int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
+                           qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out,
+                           double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,
+                           void *stream);
+
+/* ----------------------------------------------------------- autotuner (a12)
+ * Time the candidate launch geometries (threads per block, sites per
+ * thread, block-to-tile mapping) of operation `op` on `geom` and remember
+ * the fastest in the context, the analogue of the auto-tuning the paper
+ * proposes in sections 5.4 and 9.  Allocates and frees temporary device
+ * buffers and synchronises the device, so it returns QDPX_ECAPTURE on a
+ * capturing stream.  Every candidate produces bit-identical results.
+ * qdpx_tune_get / qdpx_tune_set read and write the remembered choice
+ * (block threads, sites per thread, xcd mapping flag). */
+int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+              void *stream);
+int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                  int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map);
+int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                  int32_t block, int32_t sites_per_thread, int32_t xcd_map);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QDPX_H */

@@ -1,0 +1,245 @@
+// One APE smearing step and the FP64 plaquette.
+//
+// APE step, per link (x, mu), all from the unsmeared field U:
+//   S = sum_{nu != mu} [ U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu) ]
+//   W = (1-alpha) U_mu(x) + (alpha/6) S,   V = rowwise Gram-Schmidt of W (FP64)
+// The projection reads only rows 0 and 1 of W (row 2 of V is conj(row0 x
+// row1)), so only rows 0 and 1 of every staple are formed: each staple is
+// (2x3) = (2x3)(3x3) then (2x3)(3x3), two thirds of the full products.
+//
+// Thread mapping: a block of 256*k threads (k = 1 or 2) holds k groups of 64 consecutive
+// sites; wave w handles direction mu = w % 4 of group w / 4, so the four
+// links of a site are updated by four waves of the same block, which share
+// the neighbour loads in L1/L2.
+#include "qdpx_impl.hpp"
+#include "su3_device.hpp"
+
+namespace qdpx {
+
+// T = A(rows 0,1) * B
+template <typename R> __device__ __forceinline__ void mul_23_33(const M23<R> &A, const M3<R> &B, M23<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(t, A.e[i][k], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// T = (A^dag)(rows 0,1) * B, i.e. T_ij = sum_k conj(A_ki) B_kj
+template <typename R> __device__ __forceinline__ void mul_dag23_33(const M3<R> &A, const M3<R> &B, M23<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_ca(t, A.e[k][i], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// S += T * C
+template <typename R> __device__ __forceinline__ void acc_23_33(M23<R> &S, const M23<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(S.e[i][j], T.e[i][k], C.e[k][j]);
+}
+// S += T * C^dag
+template <typename R> __device__ __forceinline__ void acc_23_33dag(M23<R> &S, const M23<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
+}
+
+// Staple sum (rows 0 and 1) of link (s, mu).
+template <typename R, int NR>
+__device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
+                                                  M23<R> &S) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
+    const int s = x.s;
+    const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        const int nu = k + (k >= mu);
+        // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+        {
+            M23<R> A;
+            U.rows01(nu, s, A);
+            M3<R> B;
+            U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
+            M23<R> T;
+            mul_23_33(A, B, T);
+            M3<R> C;
+            U.full(nu, s_mu, C);
+            acc_23_33dag(S, T, C);
+        }
+        // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
+        {
+            const int y = hop_bwd(g, s, x.c[nu], nu);
+            M3<R> A;
+            U.full(nu, y, A);
+            M3<R> B;
+            U.full(mu, y, B);
+            M23<R> T;
+            mul_dag23_33(A, B, T);
+            M3<R> C;
+            U.full(nu, hop_fwd(g, y, x.c[mu], mu), C);  // y has the same mu-coordinate as x
+            acc_23_33(S, T, C);
+        }
+    }
+}
+
+template <typename R, int NR, int NS>
+__global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
+                                                  double c2, int xcd) {
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int mu = w & 3;
+    const int gpb = blockDim.x >> 8;  // site groups per block and step of j
+    const int ngroups = (g.V + 63) >> 6;
+#pragma unroll 1
+    for (int j = 0; j < NS; ++j) {
+        const int grp = (tile * NS + j) * gpb + (w >> 2);
+        if (grp >= ngroups) return;
+        const int s = grp * 64 + lane;
+        if (s >= g.V) continue;
+        Site x;
+        x.init(g, s);
+        M23<R> S;
+        staple_sum_rows01(g, U, x, mu, S);
+        M23<R> u0;
+        U.rows01(mu, s, u0);
+        Cx<double> wm[2][3], v[3][3];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                wm[i][jj].re = fma(c2, (double)S.e[i][jj].re, c1 * (double)u0.e[i][jj].re);
+                wm[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u0.e[i][jj].im);
+            }
+        reunitarise(wm, v);
+#pragma unroll
+        for (int a = 0; a < NR; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, (R)v[a][b].re, (R)v[a][b].im);
+    }
+}
+
+hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
+                           const LaunchCfg &cfg, hipStream_t st) {
+    const int groups = (g.V + 63) / 64;
+    const int gpb = cfg.block / 256;
+    const int per_block = gpb * cfg.nsite;
+    const dim3 grid((groups + per_block - 1) / per_block);
+#define QDPX_APE_LAUNCH(R, NR, NS)                                                                              \
+    k_ape_step<R, NR, NS><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},            \
+                                                      LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2, cfg.xcd)
+#define QDPX_APE_NS(R, NR)                        \
+    switch (cfg.nsite) {                          \
+    case 2: QDPX_APE_LAUNCH(R, NR, 2); break;     \
+    case 4: QDPX_APE_LAUNCH(R, NR, 4); break;     \
+    default: QDPX_APE_LAUNCH(R, NR, 1); break;    \
+    }
+    if (prec == 0) {
+        QDPX_APE_NS(double, 3)
+    } else if (nrows == 3) {
+        QDPX_APE_NS(float, 3)
+    } else {
+        QDPX_APE_NS(float, 2)
+    }
+#undef QDPX_APE_NS
+#undef QDPX_APE_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- plaquette
+// Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12.
+template <typename R, int NR>
+__device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s, M3<double> &m) {
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const Cx<R> z = U.ld(mu, a, b, s);
+            m.e[a][b] = Cx<double>{(double)z.re, (double)z.im};
+        }
+    if constexpr (NR == 2) rebuild_row2(m);
+}
+
+// One site per lane, block of 256 threads; the spatial and temporal sums of
+// each 64-site group go to partials[grp] and partials[n + grp].
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_plaquette(Geo g, LinksRO<R, NR> U, double *__restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int grp = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int n = (g.V + 63) >> 6;
+    if (grp >= n) return;
+    const int s = grp * 64 + lane;
+    double sp = 0.0, tp = 0.0;
+    if (s < g.V) {
+        Site x;
+        x.init(g, s);
+#pragma unroll 1
+        for (int mu = 0; mu < 3; ++mu) {
+            M3<double> a;
+            load_f64(U, mu, s, a);
+            const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+#pragma unroll 1
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                M3<double> b, c, d;
+                load_f64(U, nu, s_mu, b);                                // U_nu(x+mu)
+                load_f64(U, mu, hop_fwd(g, s, x.c[nu], nu), c);          // U_mu(x+nu)
+                load_f64(U, nu, s, d);                                   // U_nu(x)
+                // Re Tr[(a b)(d c)^dag]
+                double p = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        Cx<double> xab{0.0, 0.0}, xdc{0.0, 0.0};
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            cmac(xab, a.e[i][k], b.e[k][j]);
+                            cmac(xdc, d.e[i][k], c.e[k][j]);
+                        }
+                        p = fma(xab.re, xdc.re, fma(xab.im, xdc.im, p));
+                    }
+                if (nu == 3) tp += p;
+                else sp += p;
+            }
+        }
+    }
+    sp = wave_sum(sp);
+    tp = wave_sum(tp);
+    if (lane == 0) {
+        partials[grp] = sp;
+        partials[n + grp] = tp;
+    }
+}
+
+int plaquette_num_partials(const Geo &g) { return (g.V + 63) / 64; }
+
+hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st) {
+    const int groups = (g.V + 63) / 64;
+    const dim3 grid((groups + 3) / 4);
+    if (prec == 0)
+        k_plaquette<double, 3><<<grid, 256, 0, st>>>(g, LinksRO<double, 3>{(const double2 *)U, g.S}, partials);
+    else if (nrows == 3)
+        k_plaquette<float, 3><<<grid, 256, 0, st>>>(g, LinksRO<float, 3>{(const float2 *)U, g.S}, partials);
+    else
+        k_plaquette<float, 2><<<grid, 256, 0, st>>>(g, LinksRO<float, 2>{(const float2 *)U, g.S}, partials);
+    return hipGetLastError();
+}
+
+}  // namespace qdpx

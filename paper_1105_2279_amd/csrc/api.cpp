@@ -1,0 +1,511 @@
+// C ABI of the library: argument validation, workspace layout, launch
+// sequencing of the kernels and the launch-geometry tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qdpx.h"
+#include "qdpx_impl.hpp"
+#include "su3_device.hpp"
+
+namespace qdpx {
+int finalize_stage_a_blocks(int n);
+}  // namespace qdpx
+
+using namespace qdpx;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *what) {
+    return fail(QDPX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define QDPX_TRY_HIP(expr, what)               \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+extern "C" const char *qdpx_last_error(void) { return g_err.c_str(); }
+extern "C" const char *qdpx_version(void) { return "qdpx 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ context
+struct TuneKey {
+    int op, prec, fmt, L[4];
+    bool operator<(const TuneKey &o) const {
+        return std::tie(op, prec, fmt, L[0], L[1], L[2], L[3]) <
+               std::tie(o.op, o.prec, o.fmt, o.L[0], o.L[1], o.L[2], o.L[3]);
+    }
+};
+
+struct qdpx_ctx {
+    int device = 0;
+    std::map<TuneKey, LaunchCfg> tuned;
+};
+
+extern "C" int qdpx_create(qdpx_ctx **out, int device) {
+    if (!out) return fail(QDPX_EINVAL, "qdpx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(QDPX_EINVAL, "qdpx_create: device %d not in [0, %d)", device, n);
+    qdpx_ctx *c = new qdpx_ctx;
+    c->device = device;
+    *out = c;
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_destroy(qdpx_ctx *ctx) {
+    delete ctx;
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_free_all(qdpx_ctx *ctx) {
+    if (!ctx) return fail(QDPX_EINVAL, "qdpx_free_all: ctx is NULL");
+    return QDPX_OK;  // no device tables are cached by this version
+}
+
+// --------------------------------------------------------------- validation
+static bool geom_ok(const qdpx_geom *g, const char *fn) {
+    if (!g) {
+        fail(QDPX_EINVAL, "%s: geom is NULL", fn);
+        return false;
+    }
+    int64_t v = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (g->L[d] < 2 || g->L[d] > 4096) {
+            fail(QDPX_EINVAL, "%s: extent L[%d] = %d outside [2, 4096]", fn, d, g->L[d]);
+            return false;
+        }
+        v *= g->L[d];
+    }
+    if (v > 2147483647LL - 256) {
+        fail(QDPX_EINVAL, "%s: volume %lld too large", fn, (long long)v);
+        return false;
+    }
+    return true;
+}
+
+static int check_format(qdpx_prec prec, qdpx_linkfmt fmt, const char *fn) {
+    if (prec != QDPX_F64 && prec != QDPX_F32) return fail(QDPX_EINVAL, "%s: unknown precision %d", fn, (int)prec);
+    if (fmt != QDPX_LINK18 && fmt != QDPX_LINK12) return fail(QDPX_EINVAL, "%s: unknown link format %d", fn, (int)fmt);
+    if (prec == QDPX_F64 && fmt == QDPX_LINK12)
+        return fail(QDPX_EUNSUPPORTED, "%s: LINK12 is provided with QDPX_F32 only", fn);
+    return QDPX_OK;
+}
+
+static int nrows_of(qdpx_linkfmt f) { return f == QDPX_LINK12 ? 2 : 3; }
+static size_t cplx_bytes(qdpx_prec p) { return p == QDPX_F64 ? 16 : 8; }
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b || !na || !nb) return false;
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+extern "C" int64_t qdpx_site_stride(const qdpx_geom *geom) {
+    if (!geom_ok(geom, "qdpx_site_stride")) return -1;
+    return make_geo(geom->L).S;
+}
+
+extern "C" size_t qdpx_links_bytes(const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
+    if (!geom_ok(geom, "qdpx_links_bytes") || check_format(prec, fmt, "qdpx_links_bytes") != QDPX_OK) return 0;
+    const Geo g = make_geo(geom->L);
+    return (size_t)g.S * 4 * nrows_of(fmt) * 3 * cplx_bytes(prec);
+}
+
+extern "C" size_t qdpx_fermion_bytes(const qdpx_geom *geom, qdpx_prec prec) {
+    if (!geom_ok(geom, "qdpx_fermion_bytes") || check_format(prec, QDPX_LINK18, "qdpx_fermion_bytes") != QDPX_OK)
+        return 0;
+    const Geo g = make_geo(geom->L);
+    return (size_t)g.S * 12 * cplx_bytes(prec);
+}
+
+// doubles needed to reduce n partials of ncomp components (partials + stage A)
+static size_t reduce_bytes(int n, int ncomp) {
+    return round256(sizeof(double) * (size_t)ncomp * ((size_t)n + (size_t)finalize_stage_a_blocks(n)));
+}
+
+// Batched tables are defined further below.
+static size_t batched_ws_bytes(int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt, int n_steps);
+
+extern "C" size_t qdpx_workspace_bytes(qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, int n) {
+    if (op == QDPX_OP_BATCHED) return batched_ws_bytes(n, geom, prec, fmt, 1 << 20);
+    if (!geom_ok(geom, "qdpx_workspace_bytes") || check_format(prec, fmt, "qdpx_workspace_bytes") != QDPX_OK) return 0;
+    const Geo g = make_geo(geom->L);
+    switch (op) {
+    case QDPX_OP_SHIFT:
+        return reduce_bytes(shift_num_partials(g), 1);
+    case QDPX_OP_CHAIN:
+        return round256(qdpx_fermion_bytes(geom, prec)) + reduce_bytes(shift_num_partials(g), 1);
+    case QDPX_OP_APE:
+        return (n >= 2 ? round256(qdpx_links_bytes(geom, prec, fmt)) : 0) +
+               reduce_bytes(plaquette_num_partials(g), 2);
+    case QDPX_OP_PLAQ:
+        return reduce_bytes(plaquette_num_partials(g), 2);
+    default:
+        fail(QDPX_EINVAL, "qdpx_workspace_bytes: unknown op %d", (int)op);
+        return 0;
+    }
+}
+
+static bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &s) != hipSuccess) return false;
+    return s == hipStreamCaptureStatusActive;
+}
+
+static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
+    LaunchCfg c;
+    if (ctx) {
+        TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
+        auto it = ctx->tuned.find(k);
+        if (it != ctx->tuned.end()) c = it->second;
+    }
+    return c;
+}
+
+#define QDPX_CHECK_CTX(fn) \
+    if (!ctx) return fail(QDPX_EINVAL, "%s: ctx is NULL", fn)
+
+// ------------------------------------------------------------ pack / unpack
+extern "C" int qdpx_pack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, qdpx_prec prec,
+                               qdpx_linkfmt fmt, void *soa, void *stream) {
+    const char *fn = "qdpx_pack_links";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    const Geo g = make_geo(geom->L);
+    if (overlap(aos, (size_t)g.V * 4 * 18 * 8, soa, qdpx_links_bytes(geom, prec, fmt)))
+        return fail(QDPX_EALIAS, "%s: soa overlaps aos", fn);
+    QDPX_TRY_HIP(launch_pack_links(g, prec, nrows_of(fmt), aos, soa, (hipStream_t)stream), fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_unpack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, qdpx_prec prec,
+                                 qdpx_linkfmt fmt, double *aos, void *stream) {
+    const char *fn = "qdpx_unpack_links";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    const Geo g = make_geo(geom->L);
+    if (overlap(aos, (size_t)g.V * 4 * 18 * 8, soa, qdpx_links_bytes(geom, prec, fmt)))
+        return fail(QDPX_EALIAS, "%s: aos overlaps soa", fn);
+    QDPX_TRY_HIP(launch_unpack_links(g, prec, nrows_of(fmt), soa, aos, (hipStream_t)stream), fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_pack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, qdpx_prec prec,
+                                 void *soa, void *stream) {
+    const char *fn = "qdpx_pack_fermion";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, QDPX_LINK18, fn)) return r;
+    if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    const Geo g = make_geo(geom->L);
+    if (overlap(aos, (size_t)g.V * 24 * 8, soa, qdpx_fermion_bytes(geom, prec)))
+        return fail(QDPX_EALIAS, "%s: soa overlaps aos", fn);
+    QDPX_TRY_HIP(launch_pack_fermion(g, prec, aos, soa, (hipStream_t)stream), fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, qdpx_prec prec,
+                                   double *aos, void *stream) {
+    const char *fn = "qdpx_unpack_fermion";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, QDPX_LINK18, fn)) return r;
+    if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    const Geo g = make_geo(geom->L);
+    if (overlap(aos, (size_t)g.V * 24 * 8, soa, qdpx_fermion_bytes(geom, prec)))
+        return fail(QDPX_EALIAS, "%s: aos overlaps soa", fn);
+    QDPX_TRY_HIP(launch_unpack_fermion(g, prec, soa, aos, (hipStream_t)stream), fn);
+    return QDPX_OK;
+}
+
+// ------------------------------------------------------------ shift / chain
+extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                                        const void *U, const void *psi, const void *phi, double a, void *chi,
+                                        double *norm2, void *work, size_t work_bytes, void *stream) {
+    const char *fn = "qdpx_eval_shift_mul_axpy";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    const size_t need = qdpx_workspace_bytes(QDPX_OP_SHIFT, geom, prec, fmt, 0);
+    if (norm2 && (!work || work_bytes < need))
+        return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
+    if (overlap(chi, fb, psi, fb) || overlap(chi, fb, phi, fb) || overlap(chi, fb, U, lb))
+        return fail(QDPX_EALIAS, "%s: chi overlaps an input", fn);
+    if (norm2 && (overlap(work, need, chi, fb) || overlap(work, need, psi, fb) || overlap(work, need, phi, fb) ||
+                  overlap(work, need, U, lb)))
+        return fail(QDPX_EALIAS, "%s: workspace overlaps a field", fn);
+    const Geo g = make_geo(geom->L);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_SHIFT, geom, prec, fmt);
+    hipStream_t st = (hipStream_t)stream;
+    double *part = norm2 ? (double *)work : nullptr;
+    QDPX_TRY_HIP(launch_shift(g, prec, nrows_of(fmt), U, psi, phi, a, 0, 0.0, chi, part, cfg, st), fn);
+    if (norm2) QDPX_TRY_HIP(launch_finalize(part, shift_num_partials(g), 0, (double)g.V, norm2, st), fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                                const void *U, void *psi, const void *phi, double a, double c, int n_iter,
+                                double *norms, void *work, size_t work_bytes, void *stream) {
+    const char *fn = "qdpx_shift_chain";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U || !psi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
+    const size_t need = qdpx_workspace_bytes(QDPX_OP_CHAIN, geom, prec, fmt, n_iter);
+    if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
+    if (overlap(psi, fb, phi, fb) || overlap(psi, fb, U, lb)) return fail(QDPX_EALIAS, "%s: psi overlaps an input", fn);
+    if (overlap(work, need, psi, fb) || overlap(work, need, phi, fb) || overlap(work, need, U, lb))
+        return fail(QDPX_EALIAS, "%s: workspace overlaps a field", fn);
+    const Geo g = make_geo(geom->L);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_CHAIN, geom, prec, fmt);
+    hipStream_t st = (hipStream_t)stream;
+    void *tmp = work;
+    double *part = (double *)((char *)work + round256(fb));
+    void *buf[2] = {psi, tmp};
+    for (int k = 0; k < n_iter; ++k) {
+        void *src = buf[k & 1], *dst = buf[(k + 1) & 1];
+        QDPX_TRY_HIP(launch_shift(g, prec, nrows_of(fmt), U, src, phi, a, 1, c, dst, norms ? part : nullptr, cfg, st),
+                     fn);
+        if (norms) QDPX_TRY_HIP(launch_finalize(part, shift_num_partials(g), 0, (double)g.V, norms + k, st), fn);
+    }
+    if (n_iter & 1) QDPX_TRY_HIP(launch_copy_fermion(g, prec, tmp, psi, st), fn);
+    return QDPX_OK;
+}
+
+// ---------------------------------------------------------- APE / plaquette
+static int plaquette_into(const Geo &g, qdpx_prec prec, qdpx_linkfmt fmt, const void *U, double *plaq,
+                          double *part, hipStream_t st, const char *fn) {
+    QDPX_TRY_HIP(launch_plaquette(g, prec, nrows_of(fmt), U, part, st), fn);
+    QDPX_TRY_HIP(launch_finalize(part, plaquette_num_partials(g), 1, (double)g.V, plaq, st), fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
+                              double *plaq, void *work, size_t work_bytes, void *stream) {
+    const char *fn = "qdpx_plaquette";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U || !plaq) return fail(QDPX_EINVAL, "%s: NULL pointer", fn);
+    const size_t need = qdpx_workspace_bytes(QDPX_OP_PLAQ, geom, prec, fmt, 0);
+    if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    if (overlap(work, need, U, qdpx_links_bytes(geom, prec, fmt)))
+        return fail(QDPX_EALIAS, "%s: workspace overlaps U", fn);
+    return plaquette_into(make_geo(geom->L), prec, fmt, U, plaq, (double *)work, (hipStream_t)stream, fn);
+}
+
+extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                              const void *U_in, void *U_out, double alpha, int n_steps, double *plaq, void *work,
+                              size_t work_bytes, void *stream) {
+    const char *fn = "qdpx_ape_smear";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U_in || !U_out) return fail(QDPX_EINVAL, "%s: NULL link pointer", fn);
+    if (n_steps < 1) return fail(QDPX_EINVAL, "%s: n_steps = %d < 1", fn, n_steps);
+    const size_t lb = qdpx_links_bytes(geom, prec, fmt);
+    const size_t need = qdpx_workspace_bytes(QDPX_OP_APE, geom, prec, fmt, n_steps);
+    const bool need_work = (n_steps >= 2) || plaq;
+    if (need_work && (!work || work_bytes < need))
+        return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    if (overlap(U_in, lb, U_out, lb)) return fail(QDPX_EALIAS, "%s: U_out overlaps U_in", fn);
+    if (need_work && (overlap(work, need, U_in, lb) || overlap(work, need, U_out, lb)))
+        return fail(QDPX_EALIAS, "%s: workspace overlaps the links", fn);
+    const Geo g = make_geo(geom->L);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_APE, geom, prec, fmt);
+    hipStream_t st = (hipStream_t)stream;
+    void *tmp = (n_steps >= 2) ? work : nullptr;
+    double *part = (double *)((char *)work + (n_steps >= 2 ? round256(lb) : 0));
+    const double c1 = 1.0 - alpha, c2 = alpha / 6.0;
+    if (plaq) {
+        if (int r = plaquette_into(g, prec, fmt, U_in, plaq, part, st, fn)) return r;
+    }
+    const void *src = U_in;
+    for (int k = 0; k < n_steps; ++k) {
+        // the last step always lands in U_out
+        void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, cfg, st), fn);
+        if (plaq) {
+            if (int r = plaquette_into(g, prec, fmt, dst, plaq + 3 * (k + 1), part, st, fn)) return r;
+        }
+        src = dst;
+    }
+    return QDPX_OK;
+}
+
+// ------------------------------------------------------- batched (stub size)
+static size_t batched_ws_bytes(int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt, int n_steps) {
+    (void)n_lat;
+    (void)geoms;
+    (void)prec;
+    (void)fmt;
+    (void)n_steps;
+    fail(QDPX_EUNSUPPORTED, "batched smearing is not built yet");
+    return 0;
+}
+
+extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
+                                      qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out, double alpha,
+                                      int n_steps, double *plaq, void *work, size_t work_bytes, void *stream) {
+    (void)ctx; (void)n_lat; (void)geoms; (void)prec; (void)fmt; (void)U_in; (void)U_out; (void)alpha;
+    (void)n_steps; (void)plaq; (void)work; (void)work_bytes; (void)stream;
+    return fail(QDPX_EUNSUPPORTED, "qdpx_ape_smear_batched: not built yet");
+}
+
+// ------------------------------------------------------------------- tuner
+static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
+    if (c.block < 64 || c.block > 1024 || (c.block % 64)) return false;
+    if (c.xcd != 0 && c.xcd != 1) return false;
+    if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
+    if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
+        return c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8;
+    return false;
+}
+
+extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                             int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map) {
+    const char *fn = "qdpx_tune_get";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    const LaunchCfg c = cfg_for(ctx, op, geom, prec, fmt);
+    if (block) *block = c.block;
+    if (sites_per_thread) *sites_per_thread = c.nsite;
+    if (xcd_map) *xcd_map = c.xcd;
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                             int32_t block, int32_t sites_per_thread, int32_t xcd_map) {
+    const char *fn = "qdpx_tune_set";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    LaunchCfg c;
+    c.block = block;
+    c.nsite = sites_per_thread;
+    c.xcd = xcd_map;
+    if (!cfg_valid(op, c))
+        return fail(QDPX_EINVAL, "%s: geometry (block %d, sites %d, xcd %d) not valid for op %d", fn, block,
+                    sites_per_thread, xcd_map, (int)op);
+    ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = c;
+    return QDPX_OK;
+}
+
+// Times every candidate on temporary buffers filled with a constant byte
+// pattern (the kernels' cost does not depend on the values) and keeps the
+// fastest in the context.
+extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                         void *stream) {
+    const char *fn = "qdpx_tune";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (op != QDPX_OP_APE && op != QDPX_OP_SHIFT && op != QDPX_OP_CHAIN)
+        return fail(QDPX_EUNSUPPORTED, "%s: op %d has a fixed geometry", fn, (int)op);
+    hipStream_t st = (hipStream_t)stream;
+    if (stream_capturing(st)) return fail(QDPX_ECAPTURE, "%s: stream is capturing", fn);
+    const Geo g = make_geo(geom->L);
+    const size_t lb = qdpx_links_bytes(geom, prec, fmt), fb = qdpx_fermion_bytes(geom, prec);
+    std::vector<void *> bufs;
+    auto alloc = [&](size_t n) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        hipMemsetAsync(p, 0x3c, n, st);  // finite values in both precisions
+        return p;
+    };
+    auto release = [&]() {
+        hipStreamSynchronize(st);
+        for (void *p : bufs) hipFree(p);
+    };
+    void *U = alloc(lb), *A = nullptr, *B = nullptr, *C = nullptr, *part = nullptr;
+    if (op == QDPX_OP_APE) {
+        A = alloc(lb);
+    } else {
+        A = alloc(fb);
+        B = alloc(fb);
+        C = alloc(fb);
+        part = alloc(reduce_bytes(shift_num_partials(g), 1));
+    }
+    if (!U || !A || (op != QDPX_OP_APE && (!B || !C || !part))) {
+        release();
+        return fail(QDPX_ENOMEM, "%s: could not allocate tuning buffers", fn);
+    }
+    std::vector<LaunchCfg> cands;
+    const int blocks_ape[] = {256, 512};
+    const int blocks_shift[] = {64, 128, 256, 512, 1024};
+    const int ns_ape[] = {1, 2, 4};
+    const int ns_shift[] = {1, 2, 4, 8};
+    for (int x = 0; x < 2; ++x) {
+        if (op == QDPX_OP_APE) {
+            for (int b : blocks_ape)
+                for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x});
+        } else {
+            for (int b : blocks_shift)
+                for (int n : ns_shift) cands.push_back(LaunchCfg{b, n, x});
+        }
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    LaunchCfg best_cfg;
+    const int nrows = nrows_of(fmt);
+    for (const LaunchCfg &c : cands) {
+        auto run = [&]() -> hipError_t {
+            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, c, st);
+            return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
+                                st);
+        };
+        if (run() != hipSuccess) continue;
+        hipEventRecord(e0, st);
+        const int reps = 5;
+        for (int r = 0; r < reps; ++r) run();
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_cfg = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    release();
+    ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = best_cfg;
+    return QDPX_OK;
+}

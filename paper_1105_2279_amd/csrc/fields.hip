@@ -1,0 +1,305 @@
+// Layout conversion (host canonical AoS <-> library SoA), the shift
+// expression chi = sum_mu U_mu(x) psi(x+mu) + a phi(x) with its fused FP64
+// norm, the chain update psi - c chi, and the deterministic finalisation of
+// FP64 partial sums.
+#include "qdpx_impl.hpp"
+#include "su3_device.hpp"
+
+namespace qdpx {
+
+Geo make_geo(const int32_t L[4]) {
+    Geo g;
+    for (int d = 0; d < 4; ++d) g.L[d] = L[d];
+    g.st[0] = 1;
+    g.st[1] = L[0];
+    g.st[2] = L[0] * L[1];
+    g.st[3] = L[0] * L[1] * L[2];
+    g.V = g.st[3] * L[3];
+    g.S = ((int64_t)g.V + 255) / 256 * 256;
+    return g;
+}
+
+// ------------------------------------------------------------ pack / unpack
+// AoS double[V][4][3][3][2] -> SoA complex[mu][row < NR][col][S].
+// One thread per (component, site); the component is blockIdx.y so the SoA
+// writes of a wave are contiguous.
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_pack_links(Geo g, const double2 *__restrict__ aos,
+                                                    vec2_t<R> *__restrict__ soa) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int comp = blockIdx.y;  // (mu*NR + a)*3 + b
+    if (s >= g.V) return;
+    const int b = comp % 3, a = (comp / 3) % NR, mu = comp / (3 * NR);
+    const double2 v = aos[((int64_t)s * 4 + mu) * 9 + a * 3 + b];
+    vec2_t<R> o;
+    o.x = (R)v.x;  // FP64 -> FP32 conversion rounds to nearest even
+    o.y = (R)v.y;
+    soa[(int64_t)comp * g.S + s] = o;
+}
+
+// SoA -> AoS; one thread per (mu, site), row 2 rebuilt in FP64 for NR == 2.
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_unpack_links(Geo g, const vec2_t<R> *__restrict__ soa,
+                                                      double2 *__restrict__ aos) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (s >= g.V) return;
+    M3<double> m;
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            vec2_t<R> v = soa[(int64_t)((mu * NR + a) * 3 + b) * g.S + s];
+            m.e[a][b] = Cx<double>{(double)v.x, (double)v.y};
+        }
+    if constexpr (NR == 2) rebuild_row2(m);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) aos[((int64_t)s * 4 + mu) * 9 + a * 3 + b] = double2{m.e[a][b].re, m.e[a][b].im};
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_pack_fermion(Geo g, const double2 *__restrict__ aos,
+                                                      vec2_t<R> *__restrict__ soa) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int comp = blockIdx.y;  // spin*3 + colour
+    if (s >= g.V) return;
+    const double2 v = aos[(int64_t)s * 12 + comp];
+    vec2_t<R> o;
+    o.x = (R)v.x;
+    o.y = (R)v.y;
+    soa[(int64_t)comp * g.S + s] = o;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_unpack_fermion(Geo g, const vec2_t<R> *__restrict__ soa,
+                                                        double2 *__restrict__ aos) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int comp = blockIdx.y;
+    if (s >= g.V) return;
+    const vec2_t<R> v = soa[(int64_t)comp * g.S + s];
+    aos[(int64_t)s * 12 + comp] = double2{(double)v.x, (double)v.y};
+}
+
+static dim3 site_grid(const Geo &g, int comps) { return dim3((g.V + 255) / 256, comps, 1); }
+
+hipError_t launch_pack_links(const Geo &g, int prec, int nrows, const double *aos, void *soa, hipStream_t st) {
+    const dim3 grid = site_grid(g, 4 * nrows * 3);
+    const double2 *in = reinterpret_cast<const double2 *>(aos);
+    if (prec == 0) {
+        k_pack_links<double, 3><<<grid, 256, 0, st>>>(g, in, (double2 *)soa);
+    } else if (nrows == 3) {
+        k_pack_links<float, 3><<<grid, 256, 0, st>>>(g, in, (float2 *)soa);
+    } else {
+        k_pack_links<float, 2><<<grid, 256, 0, st>>>(g, in, (float2 *)soa);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_links(const Geo &g, int prec, int nrows, const void *soa, double *aos, hipStream_t st) {
+    const dim3 grid = site_grid(g, 4);
+    double2 *out = reinterpret_cast<double2 *>(aos);
+    if (prec == 0) {
+        k_unpack_links<double, 3><<<grid, 256, 0, st>>>(g, (const double2 *)soa, out);
+    } else if (nrows == 3) {
+        k_unpack_links<float, 3><<<grid, 256, 0, st>>>(g, (const float2 *)soa, out);
+    } else {
+        k_unpack_links<float, 2><<<grid, 256, 0, st>>>(g, (const float2 *)soa, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_fermion(const Geo &g, int prec, const double *aos, void *soa, hipStream_t st) {
+    const dim3 grid = site_grid(g, 12);
+    const double2 *in = reinterpret_cast<const double2 *>(aos);
+    if (prec == 0) k_pack_fermion<double><<<grid, 256, 0, st>>>(g, in, (double2 *)soa);
+    else k_pack_fermion<float><<<grid, 256, 0, st>>>(g, in, (float2 *)soa);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double *aos, hipStream_t st) {
+    const dim3 grid = site_grid(g, 12);
+    double2 *out = reinterpret_cast<double2 *>(aos);
+    if (prec == 0) k_unpack_fermion<double><<<grid, 256, 0, st>>>(g, (const double2 *)soa, out);
+    else k_unpack_fermion<float><<<grid, 256, 0, st>>>(g, (const float2 *)soa, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- shift expression
+// One site per lane.  A wave handles NS consecutive groups of 64 sites; the
+// FP64 |chi|^2 of each 64-site group is reduced by a wave butterfly and
+// written as one partial, so the reduced value does not depend on the block
+// size, NS or the tile mapping.
+template <typename R, int NR, int MODE, int NS>
+__global__ void __launch_bounds__(1024) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
+                                                FermWO<R> out, double *__restrict__ partials, int xcd) {
+    const int nwb = blockDim.x >> 6;
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int ngroups = (g.V + 63) >> 6;
+#pragma unroll 1
+    for (int j = 0; j < NS; ++j) {
+        const int grp = (tile * nwb + (int)(threadIdx.x >> 6)) * NS + j;
+        if (grp >= ngroups) return;  // whole wave leaves together
+        const int s = grp * 64 + lane;
+        double n2 = 0.0;
+        if (s < g.V) {
+            Site x;
+            x.init(g, s);
+            Cx<R> acc[4][3];
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                M3<R> u;
+                U.full(mu, s, u);
+                const int f = hop_fwd(g, s, x.c[mu], mu);
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    Cx<R> p[3];
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, f);
+#pragma unroll
+                    for (int ca = 0; ca < 3; ++ca)
+#pragma unroll
+                        for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], u.e[ca][cb], p[cb]);
+                }
+            }
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Cx<R> v = acc[sp][cc];
+                    if (phi.p) {
+                        const Cx<R> f = phi.ld(sp, cc, s);
+                        v.re = fma(a, f.re, v.re);
+                        v.im = fma(a, f.im, v.im);
+                    }
+                    n2 = fma((double)v.re, (double)v.re, fma((double)v.im, (double)v.im, n2));
+                    if constexpr (MODE == 1) {
+                        const Cx<R> p0 = psi.ld(sp, cc, s);
+                        v.re = fma(-c, v.re, p0.re);
+                        v.im = fma(-c, v.im, p0.im);
+                    }
+                    out.st(sp, cc, s, v);
+                }
+        }
+        if (partials) {
+            const double w = wave_sum(n2);
+            if (lane == 0) partials[grp] = w;
+        }
+    }
+}
+
+int shift_num_partials(const Geo &g) { return (g.V + 63) / 64; }
+
+template <typename R, int NR, int MODE>
+static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, const void *phi, double a, double c,
+                              void *out, double *partials, const LaunchCfg &cfg, hipStream_t st) {
+    using V = vec2_t<R>;
+    LinksRO<R, NR> u{(const V *)U, g.S};
+    FermRO<R> p{(const V *)psi, g.S}, f{(const V *)phi, g.S};
+    FermWO<R> o{(V *)out, g.S};
+    const int groups = (g.V + 63) / 64;
+    const int per_block = (cfg.block / 64) * cfg.nsite;
+    const dim3 grid((groups + per_block - 1) / per_block);
+    switch (cfg.nsite) {
+    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
+    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
+    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
+    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
+    }
+}
+
+template <int MODE>
+static void shift_dispatch(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
+                           double a, double c, void *out, double *partials, const LaunchCfg &cfg, hipStream_t st) {
+    if (prec == 0) shift_dispatch_ns<double, 3, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
+    else if (nrows == 3) shift_dispatch_ns<float, 3, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
+    else shift_dispatch_ns<float, 2, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
+}
+
+hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
+                        double a, int mode, double c, void *out, double *partials, const LaunchCfg &cfg,
+                        hipStream_t st) {
+    if (mode == 0) shift_dispatch<0>(g, prec, nrows, U, psi, phi, a, c, out, partials, cfg, st);
+    else shift_dispatch<1>(g, prec, nrows, U, psi, phi, a, c, out, partials, cfg, st);
+    return hipGetLastError();
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256) k_copy_fermion(Geo g, const V *__restrict__ src, V *__restrict__ dst) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.V) return;
+    const int64_t o = (int64_t)blockIdx.y * g.S + s;
+    dst[o] = src[o];
+}
+
+hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *dst, hipStream_t st) {
+    const dim3 grid = site_grid(g, 12);
+    if (prec == 0) k_copy_fermion<double2><<<grid, 256, 0, st>>>(g, (const double2 *)src, (double2 *)dst);
+    else k_copy_fermion<float2><<<grid, 256, 0, st>>>(g, (const float2 *)src, (float2 *)dst);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ finalisation
+// Stage A: block b sums partials [b*4096, (b+1)*4096) of each component,
+// 16 consecutive values per thread then a fixed block tree.  Stage B: one
+// block sums the stage-A values in index order and applies the mode.
+constexpr int kFinChunk = 16;
+constexpr int kFinPerBlock = kReduceBlock * kFinChunk;
+
+__global__ void __launch_bounds__(kReduceBlock) k_finalize_a(const double *__restrict__ in, int n, int ncomp,
+                                                            double *__restrict__ out) {
+    __shared__ double lds[kReduceBlock / 64];
+    const int nb = gridDim.x;
+    for (int comp = 0; comp < ncomp; ++comp) {
+        const double *p = in + (int64_t)comp * n;
+        const int base = blockIdx.x * kFinPerBlock + threadIdx.x * kFinChunk;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFinChunk; ++k)
+            if (base + k < n) v += p[base + k];
+        v = block_sum<kReduceBlock / 64>(v, lds);
+        if (threadIdx.x == 0) out[comp * nb + blockIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kReduceBlock) k_finalize_b(const double *__restrict__ in, int n, int mode,
+                                                            double volume, double *__restrict__ out) {
+    __shared__ double lds[kReduceBlock / 64];
+    const int ncomp = (mode == 1) ? 2 : 1;
+    double r[2] = {0.0, 0.0};
+    for (int comp = 0; comp < ncomp; ++comp) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < n; i += kReduceBlock) v += in[comp * n + i];
+        r[comp] = block_sum<kReduceBlock / 64>(v, lds);
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            out[0] = r[0];
+        } else {
+            out[0] = (r[0] + r[1]) / (18.0 * volume);
+            out[1] = r[0] / (9.0 * volume);
+            out[2] = r[1] / (9.0 * volume);
+        }
+    }
+}
+
+int finalize_stage_a_blocks(int n) { return (n + kFinPerBlock - 1) / kFinPerBlock; }
+
+hipError_t launch_finalize(const double *partials, int n, int mode, double volume, double *out, hipStream_t st) {
+    // The stage-A results are stored right after the partials (the workspace
+    // reserves room for them: finalize_stage_a_blocks(n) per component).
+    const int ncomp = (mode == 1) ? 2 : 1;
+    const int nb = finalize_stage_a_blocks(n);
+    double *stage = const_cast<double *>(partials) + (int64_t)ncomp * n;
+    k_finalize_a<<<nb, kReduceBlock, 0, st>>>(partials, n, ncomp, stage);
+    k_finalize_b<<<1, kReduceBlock, 0, st>>>(stage, nb, mode, volume, out);
+    return hipGetLastError();
+}
+
+}  // namespace qdpx

@@ -1,0 +1,52 @@
+// Host-side internal interface between the C ABI layer (api.cpp) and the
+// translation units that own the kernels.  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qdpx {
+
+struct Geo;
+
+// Launch geometry of one operation (chosen by the tuner or defaulted).
+struct LaunchCfg {
+    int block = 256;  // threads per block, multiple of 64
+    int nsite = 1;    // consecutive 64-site groups handled per wave
+    int xcd = 1;      // 1: XCD-contiguous tile mapping, 0: identity
+};
+
+// Threads per block of the fixed-shape reduction kernels (plaquette,
+// finalisation).  Kept fixed so that reduced values are bit-identical for
+// every tuned geometry of the other kernels.
+constexpr int kReduceBlock = 256;
+
+Geo make_geo(const int32_t L[4]);
+
+// ---- fields.hip
+hipError_t launch_pack_links(const Geo &g, int prec, int nrows, const double *aos, void *soa, hipStream_t st);
+hipError_t launch_unpack_links(const Geo &g, int prec, int nrows, const void *soa, double *aos, hipStream_t st);
+hipError_t launch_pack_fermion(const Geo &g, int prec, const double *aos, void *soa, hipStream_t st);
+hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double *aos, hipStream_t st);
+
+// Shift expression.  mode 0: out = chi; mode 1: out = psi - c*chi.
+// partials (nullable): one FP64 partial of |chi|^2 per 256-site chunk,
+// shift_num_partials(g) entries.
+int shift_num_partials(const Geo &g);
+hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
+                        double a, int mode, double c, void *out, double *partials, const LaunchCfg &cfg,
+                        hipStream_t st);
+hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *dst, hipStream_t st);
+
+// Deterministic finalisation.  mode 0: out[0] = sum of partials[0..n).
+// mode 1 (plaquette): partials hold n spatial then n temporal sums;
+// out = {(sp+tp)/(18V), sp/(9V), tp/(9V)}.
+hipError_t launch_finalize(const double *partials, int n, int mode, double volume, double *out, hipStream_t st);
+
+// ---- ape.hip
+hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
+                           const LaunchCfg &cfg, hipStream_t st);
+int plaquette_num_partials(const Geo &g);  // per component (2 components)
+hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st);
+
+}  // namespace qdpx

@@ -1,0 +1,231 @@
+// Device-side building blocks: complex numbers, SoA field access, SU(3)
+// products restricted to the rows that are actually needed, periodic
+// neighbour addressing, the FP64 row Gram-Schmidt projection and
+// deterministic wave/block reductions.  gfx950, wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qdpx {
+
+// ---------------------------------------------------------------- geometry
+// Extents, per-direction site strides and the padded SoA stride.
+struct Geo {
+    int L[4];
+    int st[4];  // 1, Lx, Lx*Ly, Lx*Ly*Lz
+    int V;
+    int64_t S;  // SoA component stride (elements)
+};
+
+// Neighbour addressing for one site: coordinates are decoded once, every hop
+// is a stride add with a wrap test (no division in the hot loop).
+struct Site {
+    int s;
+    int c[4];
+    __device__ __forceinline__ void init(const Geo &g, int site) {
+        s = site;
+        int r = site;
+        c[0] = r % g.L[0]; r /= g.L[0];
+        c[1] = r % g.L[1]; r /= g.L[1];
+        c[2] = r % g.L[2];
+        c[3] = r / g.L[2];
+    }
+};
+
+__device__ __forceinline__ int hop_fwd(const Geo &g, int s, int cmu, int mu) {
+    return (cmu == g.L[mu] - 1) ? s - (g.L[mu] - 1) * g.st[mu] : s + g.st[mu];
+}
+__device__ __forceinline__ int hop_bwd(const Geo &g, int s, int cmu, int mu) {
+    return (cmu == 0) ? s + (g.L[mu] - 1) * g.st[mu] : s - g.st[mu];
+}
+
+// ------------------------------------------------------------------ complex
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+template <typename R> using vec2_t = typename V2<R>::T;
+
+template <typename R> struct Cx { R re, im; };
+
+template <typename R> __device__ __forceinline__ Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
+
+// acc += a * b
+template <typename R> __device__ __forceinline__ void cmac(Cx<R> &acc, const Cx<R> &a, const Cx<R> &b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += a * conj(b)
+template <typename R> __device__ __forceinline__ void cmac_cb(Cx<R> &acc, const Cx<R> &a, const Cx<R> &b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.im, b.re, acc.im);
+    acc.im = fma(-a.re, b.im, acc.im);
+}
+// acc += conj(a) * b
+template <typename R> __device__ __forceinline__ void cmac_ca(Cx<R> &acc, const Cx<R> &a, const Cx<R> &b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+}
+// conj(a*d - b*c): one entry of the conjugated cross product
+template <typename R>
+__device__ __forceinline__ Cx<R> conj_cross(const Cx<R> &a, const Cx<R> &d, const Cx<R> &b, const Cx<R> &c) {
+    R re = a.re * d.re;
+    re = fma(-a.im, d.im, re);
+    re = fma(-b.re, c.re, re);
+    re = fma(b.im, c.im, re);
+    R im = a.re * d.im;
+    im = fma(a.im, d.re, im);
+    im = fma(-b.re, c.im, im);
+    im = fma(-b.im, c.re, im);
+    return Cx<R>{re, -im};
+}
+
+template <typename R> struct M3 { Cx<R> e[3][3]; };   // full 3x3
+template <typename R> struct M23 { Cx<R> e[2][3]; };  // rows 0 and 1
+
+// row 2 = conj(row0 x row1)
+template <typename R> __device__ __forceinline__ void rebuild_row2(M3<R> &m) {
+    m.e[2][0] = conj_cross(m.e[0][1], m.e[1][2], m.e[0][2], m.e[1][1]);
+    m.e[2][1] = conj_cross(m.e[0][2], m.e[1][0], m.e[0][0], m.e[1][2]);
+    m.e[2][2] = conj_cross(m.e[0][0], m.e[1][1], m.e[0][1], m.e[1][0]);
+}
+
+// ----------------------------------------------------------- SoA link field
+// NR = stored rows (3: LINK18, 2: LINK12).  Element (mu, a, b) of site s is
+// at p[((mu*NR + a)*3 + b)*S + s].
+template <typename R, int NR> struct LinksRO {
+    const vec2_t<R> *__restrict__ p;
+    int64_t S;
+    __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
+        vec2_t<R> v = p[(int64_t)((mu * NR + a) * 3 + b) * S + s];
+        return Cx<R>{v.x, v.y};
+    }
+    __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m.e[a][b] = ld(mu, a, b, s);
+    }
+    __device__ __forceinline__ void full(int mu, int s, M3<R> &m) const {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m.e[a][b] = ld(mu, a, b, s);
+        if constexpr (NR == 3) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m.e[2][b] = ld(mu, 2, b, s);
+        } else {
+            rebuild_row2(m);
+        }
+    }
+};
+
+template <typename R, int NR> struct LinksWO {
+    vec2_t<R> *__restrict__ p;
+    int64_t S;
+    __device__ __forceinline__ void st(int mu, int a, int b, int s, R re, R im) const {
+        vec2_t<R> v;
+        v.x = re;
+        v.y = im;
+        p[(int64_t)((mu * NR + a) * 3 + b) * S + s] = v;
+    }
+};
+
+// --------------------------------------------------------- SoA Dirac field
+// Element (spin, colour) of site s is at p[(spin*3 + colour)*S + s].
+template <typename R> struct FermRO {
+    const vec2_t<R> *__restrict__ p;
+    int64_t S;
+    __device__ __forceinline__ Cx<R> ld(int sp, int c, int s) const {
+        vec2_t<R> v = p[(int64_t)(sp * 3 + c) * S + s];
+        return Cx<R>{v.x, v.y};
+    }
+};
+template <typename R> struct FermWO {
+    vec2_t<R> *__restrict__ p;
+    int64_t S;
+    __device__ __forceinline__ void st(int sp, int c, int s, const Cx<R> &z) const {
+        vec2_t<R> v;
+        v.x = z.re;
+        v.y = z.im;
+        p[(int64_t)(sp * 3 + c) * S + s] = v;
+    }
+};
+
+// ------------------------------------------------------------ projection
+// Row Gram-Schmidt in FP64: u = w0/|w0|; v = w1 - (u^dag w1) u, v /= |v|;
+// row 2 = conj(u x v).  A vanishing norm gives NaN (0 * inf).
+__device__ __forceinline__ void reunitarise(const Cx<double> w[2][3], Cx<double> v[3][3]) {
+    double n0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 = fma(w[0][j].re, w[0][j].re, fma(w[0][j].im, w[0][j].im, n0));
+    double r0 = 1.0 / sqrt(n0);
+    Cx<double> u[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) u[j] = Cx<double>{w[0][j].re * r0, w[0][j].im * r0};
+    Cx<double> d{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) cmac_ca(d, u[j], w[1][j]);
+    Cx<double> q[3];
+    double n1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        // q = w1 - d*u
+        q[j].re = w[1][j].re - (d.re * u[j].re - d.im * u[j].im);
+        q[j].im = w[1][j].im - (d.re * u[j].im + d.im * u[j].re);
+        n1 = fma(q[j].re, q[j].re, fma(q[j].im, q[j].im, n1));
+    }
+    double r1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) q[j] = Cx<double>{q[j].re * r1, q[j].im * r1};
+    if (!(n0 > 0.0) || !(n1 > 0.0)) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { u[j] = Cx<double>{nan, nan}; q[j] = u[j]; }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { v[0][j] = u[j]; v[1][j] = q[j]; }
+    v[2][0] = conj_cross(u[1], q[2], u[2], q[1]);
+    v[2][1] = conj_cross(u[2], q[0], u[0], q[2]);
+    v[2][2] = conj_cross(u[0], q[1], u[1], q[0]);
+}
+
+// ------------------------------------------------------------- reductions
+// Fixed-shape butterfly over the 64 lanes of a wave: every lane ends with the
+// same sum and the order of additions never changes.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of `v` over a block of NW waves, deterministic; result valid in thread 0.
+template <int NW> __device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) r += lds[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Physical block -> logical tile so that each of the 8 XCDs (which receive
+// blocks round-robin) works on one contiguous range of tiles and its L2
+// sees the neighbouring tiles.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+}  // namespace qdpx

@@ -1,0 +1,289 @@
+"""GPU parity: every kernel through the C ABI against the FP64 oracle.
+
+Tolerances: FP64 paths 1e-12 (links: max |entry difference|; fields:
+normwise and max-abs relative; norms relative; plaquettes absolute), FP32
+paths 1e-5 after one step, both compared with the FP64 oracle evaluated on the
+same FP64 inputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import latgen
+import oracle
+import paper_1105_2279_amd as q
+from gpuhelp import (FORMAT_IDS, FORMATS, ape, chain, ctx, dev, link_err, need_gpu, plaquette, rel_err, shift,
+                     su3_defects, tol)
+from lathelp import gauge_links, pure_gauge
+
+pytestmark = pytest.mark.gpu
+
+RAGGED = (3, 5, 4, 7)  # V = 420: not a multiple of 64, every extent different
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+# ------------------------------------------------------------ pack / unpack
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_pack_unpack_roundtrip(prec, fmt):
+    U = latgen.haar_links(RAGGED, 3)
+    V = q.links_to_host(ctx(), RAGGED, q.links_to_device(ctx(), RAGGED, U, prec, fmt), prec, fmt)
+    if prec == q.F64:
+        assert np.array_equal(V, U)
+    else:
+        r = U.real.astype(np.float32).astype(np.float64) + 1j * U.imag.astype(np.float32).astype(np.float64)
+        if fmt == q.LINK18:
+            assert np.array_equal(V, r)
+        else:
+            assert np.array_equal(V[..., :2, :], r[..., :2, :])
+            assert np.max(np.abs(V[..., 2, :] - U[..., 2, :])) < 1e-6
+    psi = latgen.dirac_field(RAGGED, 4)
+    P = q.fermion_to_host(ctx(), RAGGED, q.fermion_to_device(ctx(), RAGGED, psi, prec), prec)
+    if prec == q.F64:
+        assert np.array_equal(P, psi)
+    else:
+        assert np.max(np.abs(P - psi)) < 1e-6 * np.max(np.abs(psi))
+
+
+# ------------------------------------------------------- shift expression
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("L", [(16, 16, 16, 32), RAGGED, (2, 2, 2, 2)], ids=["16x16x16x32", "ragged", "2^4"])
+def test_shift_mul_axpy(prec, fmt, L):
+    seeds = latgen.SEEDS["shift_16x16x16x32"]
+    U = latgen.haar_links(L, seeds["links"])
+    psi, phi = latgen.dirac_field(L, seeds["psi"]), latgen.dirac_field(L, seeds["phi"])
+    chi, n2 = shift(L, U, psi, phi, 0.3, prec, fmt)
+    ref, n2ref = oracle.shift_mul_axpy(U, psi, phi, 0.3)
+    e_norm, e_max = rel_err(chi, ref)
+    assert e_norm < tol(prec) and e_max < tol(prec), (e_norm, e_max)
+    assert abs(n2 - n2ref) < tol(prec) * n2ref
+
+
+def test_shift_without_phi():
+    L = RAGGED
+    U = latgen.haar_links(L, 5)
+    psi = latgen.dirac_field(L, 6)
+    chi, n2 = shift(L, U, psi, None, 0.3, q.F64, q.LINK18)
+    ref, n2ref = oracle.shift_mul_axpy(U, psi, None, 0.3)
+    assert max(rel_err(chi, ref)) < 1e-12
+    assert abs(n2 - n2ref) < 1e-12 * n2ref
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("n", [1, 8])
+def test_shift_chain(prec, fmt, n):
+    L = (8, 8, 8, 16)
+    U = latgen.haar_links(L, 11)
+    psi, phi = latgen.dirac_field(L, 12), latgen.dirac_field(L, 13)
+    got, norms = chain(L, U, psi, phi, 0.3, 0.1, n, prec, fmt)
+    ref, rnorms = oracle.shift_chain(U, psi, phi, 0.3, 0.1, n)
+    # FP32 rounding compounds over the iterations; the bound grows with n.
+    t = tol(prec) * (1 if prec == q.F64 else max(1, n))
+    assert max(rel_err(got, ref)) < t
+    assert np.max(np.abs(norms - rnorms) / rnorms) < t
+
+
+# -------------------------------------------------------------- plaquette
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), RAGGED, (8, 8, 8, 16)], ids=["4^4", "ragged", "8^3x16"])
+def test_plaquette(prec, fmt, L):
+    U = latgen.haar_links(L, 21)
+    U = oracle.ape_step(U, 0.5)  # a plaquette away from zero
+    got = plaquette(L, U, prec, fmt)
+    ref = oracle.plaquette(U)
+    assert np.max(np.abs(got - ref)) < tol(prec), (got, ref)
+
+
+def test_plaquette_unit_links_exact():
+    L = (4, 4, 4, 8)
+    for prec, fmt in FORMATS:
+        got = plaquette(L, latgen.unit_links(L), prec, fmt)
+        assert np.max(np.abs(got - 1.0)) < 1e-15
+
+
+# ----------------------------------------------------------------- APE
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), RAGGED, (8, 8, 8, 16)], ids=["4^4", "ragged", "8^3x16"])
+def test_ape_one_step(prec, fmt, L):
+    U = latgen.haar_links(L, latgen.SEEDS["ape_4x4x4x4"]["links"])
+    V, plaq = ape(L, U, prec, fmt, 1)
+    Vref = oracle.ape_step(U, 0.5)
+    assert link_err(V, Vref) < tol(prec)
+    assert np.max(np.abs(plaq[0] - oracle.plaquette(U))) < tol(prec)
+    assert np.max(np.abs(plaq[1] - oracle.plaquette(Vref))) < tol(prec)
+    u, d = su3_defects(V)
+    assert u < (1e-14 if prec == q.F64 else 1e-6) and d < (1e-14 if prec == q.F64 else 1e-6)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_ape_multi_step_fp64(n):
+    L = (4, 6, 4, 8)
+    U = latgen.haar_links(L, 31)
+    V, plaq = ape(L, U, q.F64, q.LINK18, n)
+    Vk = U
+    refs = [oracle.plaquette(U)]
+    for _ in range(n):
+        Vk = oracle.ape_step(Vk, 0.5)
+        refs.append(oracle.plaquette(Vk))
+    assert link_err(V, Vk) < 1e-12
+    assert np.max(np.abs(plaq - np.array(refs))) < 1e-12
+    assert np.all(np.diff(plaq[:, 0]) > 0)
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_ape_fixed_points(prec, fmt):
+    L = (4, 4, 6, 4)
+    I = latgen.unit_links(L)
+    V, plaq = ape(L, I, prec, fmt, 2)
+    assert np.max(np.abs(V - I)) < (1e-15 if prec == q.F64 else 1e-7)
+    assert np.max(np.abs(plaq - 1.0)) < (1e-14 if prec == q.F64 else 1e-6)
+    U = pure_gauge(latgen.haar_gauge(L, 41))
+    V, plaq = ape(L, U, prec, fmt, 1)
+    assert np.max(np.abs(V - U)) < (1e-13 if prec == q.F64 else 1e-5)
+
+
+def test_ape_torus_gauge_covariance():
+    L = (4, 4, 4, 6)
+    U = latgen.haar_links(L, 51)
+    g = latgen.torus_gauge(L, 52)
+    V, _ = ape(L, U, q.F64, q.LINK18, 1)
+    Vg, _ = ape(L, gauge_links(U, g), q.F64, q.LINK18, 1)
+    assert np.max(np.abs(Vg - gauge_links(V, g))) < 1e-13
+
+
+# --------------------------------------------- bench-size sampled parity
+@pytest.fixture(scope="module")
+def big_links():
+    L = (32, 32, 32, 64)
+    return L, latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
+
+
+@pytest.mark.parametrize("prec,fmt", [(q.F64, q.LINK18), (q.F32, q.LINK12)], ids=["f64_18", "f32_12"])
+def test_ape_32x32x32x64_sampled(big_links, prec, fmt):
+    L, U = big_links
+    V, plaq = ape(L, U, prec, fmt, 1)
+    rng = np.random.default_rng(99)
+    V4 = V.reshape(-1, 4, 3, 3)
+    n = 4096
+    sites = rng.integers(0, V4.shape[0], n)
+    # include the lattice corners and faces (wrap-around)
+    sites[:4] = [0, V4.shape[0] - 1, 31, 32 * 32 * 32 * 63]
+    mus = rng.integers(0, 4, n)
+    ref = oracle.ape_links(U, 0.5, sites, mus)
+    assert np.max(np.abs(V4[sites, mus] - ref)) < tol(prec)
+    assert abs(plaq[0, 0] - oracle.plaquette(U)[0]) < tol(prec)
+    u, d = su3_defects(V4[sites, mus])
+    assert u < (1e-14 if prec == q.F64 else 1e-6)
+
+
+# ------------------------------------------------ tuning and graph replay
+def test_geometries_are_bit_identical():
+    L = (8, 6, 4, 10)  # V = 1920: partial last tiles for every geometry
+    U = latgen.haar_links(L, 61)
+    psi, phi = latgen.dirac_field(L, 62), latgen.dirac_field(L, 63)
+    c = ctx()
+    results_ape, results_shift = [], []
+    for block, ns, xcd in [(256, 1, 1), (256, 1, 0), (512, 2, 1), (256, 4, 0)]:
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd)
+        results_ape.append(ape(L, U, q.F32, q.LINK12, 2))
+    for block, ns, xcd in [(256, 1, 1), (64, 8, 0), (1024, 2, 1), (128, 4, 0)]:
+        q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, block, ns, xcd)
+        results_shift.append(shift(L, U, psi, phi, 0.3, q.F64, q.LINK18))
+    for V, p in results_ape[1:]:
+        assert np.array_equal(V, results_ape[0][0]) and np.array_equal(p, results_ape[0][1])
+    for chi, n2 in results_shift[1:]:
+        assert np.array_equal(chi, results_shift[0][0]) and n2 == results_shift[0][1]
+    q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, 256, 1, 1)
+    q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, 256, 1, 1)
+
+
+def test_tuner_picks_a_valid_geometry():
+    c = q.Context(0)
+    L = (8, 8, 8, 8)
+    q.qdpx_tune(c, q.OP_APE, L, q.F32, q.LINK12)
+    b, n, x = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
+    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1)
+    q.qdpx_tune(c, q.OP_SHIFT, L, q.F64, q.LINK18)
+    b, n, x = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
+    assert b % 64 == 0 and n in (1, 2, 4, 8)
+    c.close()
+
+
+def test_graph_replay_matches_eager():
+    L = (8, 8, 4, 8)
+    prec, fmt = q.F32, q.LINK12
+    c = ctx()
+    U = latgen.haar_links(L, 71)
+    Ud = q.links_to_device(c, L, U, prec, fmt, dev())
+    out = q.alloc_links(L, prec, fmt, dev())
+    plaq = torch.zeros(9, dtype=torch.float64, device=dev())
+    work = q.alloc_workspace(q.OP_APE, L, prec, fmt, 2, dev())
+    q.qdpx_ape_smear(c, L, prec, fmt, Ud, out, 0.5, 2, plaq, work)
+    torch.cuda.synchronize()
+    eager_out, eager_plaq = out.clone(), plaq.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        q.qdpx_ape_smear(c, L, prec, fmt, Ud, out, 0.5, 2, plaq, work)
+    for _ in range(3):
+        out.zero_()
+        plaq.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager_out)
+        assert torch.equal(plaq, eager_plaq)
+
+
+def test_capture_rejects_tuning():
+    L = (4, 4, 4, 4)
+    c = ctx()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.graph(g, stream=s):
+        try:
+            q.qdpx_tune(c, q.OP_APE, L, q.F64, q.LINK18, stream=s)
+        except q.QdpxError as e:
+            err = e
+    assert err is not None and err.code == -6
+
+
+# ------------------------------------------------------------- validation
+def test_validation_errors():
+    c = ctx()
+    L = (4, 4, 4, 4)
+    U = q.links_to_device(c, L, latgen.haar_links(L, 1), q.F64, q.LINK18)
+    out = q.alloc_links(L, q.F64, q.LINK18)
+    small = q.empty_bytes(16)
+    work = q.alloc_workspace(q.OP_APE, L, q.F64, q.LINK18, 2)
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_ape_smear(c, L, q.F64, q.LINK18, U, U, 0.5, 1, None, work)
+    assert e.value.code == -2  # aliasing
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_ape_smear(c, L, q.F64, q.LINK18, U, out, 0.5, 2, None, small)
+    assert e.value.code == -3  # workspace too small
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_ape_smear(c, L, q.F64, q.LINK18, U, out, 0.5, 0, None, work)
+    assert e.value.code == -1  # n_steps < 1
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_ape_smear(c, L, q.F64, q.LINK12, U, out, 0.5, 1, None, work)
+    assert e.value.code == -5  # LINK12 with FP64
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_ape_smear(c, (1, 4, 4, 4), q.F64, q.LINK18, U, out, 0.5, 1, None, work)
+    assert e.value.code == -1
+    psi = q.alloc_fermion(L, q.F64)
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_eval_shift_mul_axpy(c, L, q.F64, q.LINK18, U, psi, None, 0.3, psi, None, None)
+    assert e.value.code == -2
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_shift_chain(c, L, q.F64, q.LINK18, U, psi, None, 0.3, 0.1, 0, None, work)
+    assert e.value.code == -1
+    with pytest.raises(q.QdpxError) as e:
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1)
+    assert e.value.code == -1
