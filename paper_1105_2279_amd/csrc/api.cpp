@@ -390,7 +390,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (c.xcd != 0 && c.xcd != 1) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
-        return c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8;
+        return c.block <= 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
     return false;
 }
 
@@ -466,7 +466,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     }
     std::vector<LaunchCfg> cands;
     const int blocks_ape[] = {256, 512};
-    const int blocks_shift[] = {64, 128, 256, 512, 1024};
+    const int blocks_shift[] = {64, 128, 256};
     const int ns_ape[] = {1, 2, 4};
     const int ns_shift[] = {1, 2, 4, 8};
     for (int x = 0; x < 2; ++x) {

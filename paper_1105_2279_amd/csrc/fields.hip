@@ -132,7 +132,7 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 // written as one partial, so the reduced value does not depend on the block
 // size, NS or the tile mapping.
 template <typename R, int NR, int MODE, int NS>
-__global__ void __launch_bounds__(1024) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
+__global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
                                                 FermWO<R> out, double *__restrict__ partials, int xcd) {
     const int nwb = blockDim.x >> 6;
     const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(1024) k_shift(Geo g, LinksRO<R, NR> U, FermRO<
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
-#pragma unroll
+#pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 M3<R> u;
                 U.full(mu, s, u);
