@@ -161,7 +161,7 @@ extern "C" size_t qdpx_workspace_bytes(qdpx_op op, const qdpx_geom *geom, qdpx_p
         return round256(qdpx_fermion_bytes(geom, prec)) + reduce_bytes(shift_num_partials(g), 1);
     case QDPX_OP_APE:
         return (n >= 2 ? round256(qdpx_links_bytes(geom, prec, fmt)) : 0) +
-               reduce_bytes(plaquette_num_partials(g), 2);
+               reduce_bytes(std::max(ape_num_partials(g), plaquette_num_partials(g)), 2);
     case QDPX_OP_PLAQ:
         return reduce_bytes(plaquette_num_partials(g), 2);
     default:
@@ -349,18 +349,18 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     void *tmp = (n_steps >= 2) ? work : nullptr;
     double *part = (double *)((char *)work + (n_steps >= 2 ? round256(lb) : 0));
     const double c1 = 1.0 - alpha, c2 = alpha / 6.0;
-    if (plaq) {
-        if (int r = plaquette_into(g, prec, fmt, U_in, plaq, part, st, fn)) return r;
-    }
+    // Step k also reduces the plaquette of its own input (fused into the APE
+    // kernel); only the last output needs the standalone plaquette kernel.
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
         void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, cfg, st), fn);
-        if (plaq) {
-            if (int r = plaquette_into(g, prec, fmt, dst, plaq + 3 * (k + 1), part, st, fn)) return r;
-        }
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, plaq ? part : nullptr, cfg, st), fn);
+        if (plaq) QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
         src = dst;
+    }
+    if (plaq) {
+        if (int r = plaquette_into(g, prec, fmt, U_out, plaq + 3 * n_steps, part, st, fn)) return r;
     }
     return QDPX_OK;
 }
@@ -486,7 +486,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     const int nrows = nrows_of(fmt);
     for (const LaunchCfg &c : cands) {
         auto run = [&]() -> hipError_t {
-            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, c, st);
+            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, nullptr, c, st);
             return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
                                 st);
         };

@@ -44,8 +44,12 @@ hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *ds
 hipError_t launch_finalize(const double *partials, int n, int mode, double volume, double *out, hipStream_t st);
 
 // ---- ape.hip
+// One APE step.  partials (nullable): FP64 plaquette traces of the INPUT
+// links, ape_num_partials(g) per component (spatial, temporal), reduced by
+// launch_finalize(partials, ape_num_partials(g), 1, V, out).
+int ape_num_partials(const Geo &g);
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           const LaunchCfg &cfg, hipStream_t st);
+                           double *partials, const LaunchCfg &cfg, hipStream_t st);
 int plaquette_num_partials(const Geo &g);  // per component (2 components)
 hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st);
 
