@@ -35,7 +35,9 @@
  *   is a caller-provided device workspace of at least qdpx_workspace_bytes()
  *   bytes.  Every compute call only enqueues work on `stream` (a hipStream_t
  *   passed as void*, NULL = the null stream), never synchronises, never
- *   allocates and issues no memset, so it may be recorded into a HIP graph.
+ *   allocates and issues no memset, so it may be recorded into a HIP graph
+ *   (the one exception, the first batched call for a new batch, is described
+ *   at qdpx_ape_smear_batched).
  *   Scalar results (norms, plaquettes) are written to caller DEVICE buffers
  *   of doubles.
  *
@@ -124,7 +126,7 @@ size_t qdpx_fermion_bytes(const qdpx_geom *geom, qdpx_prec prec);
  * that many extents; ignored otherwise).  0 for invalid arguments. */
 size_t qdpx_workspace_bytes(qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, int n);
 
-/* ------------------------------------------------------ pack / unpack (a1)
+/* ------------------------------------------------------------ pack / unpack
  * Conversions between the host canonical AoS layout (already on the device)
  * and the library SoA layout; the analogue of the paper's push/pop of
  * lattice objects between memory domains (sections 5.3 and 6).  FP64 -> FP32
@@ -138,7 +140,7 @@ int qdpx_pack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, q
 int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, qdpx_prec prec,
                         double *aos, void *stream);
 
-/* ------------------------------------------------- shift expression (a3, a4)
+/* ------------------------------------------------------- shift expression
  * chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a * phi(x)
  * The forward hop shift(psi, FORWARD, mu) multiplied by the link, summed
  * over the four directions, plus an axpy term added once (paper section 7:
@@ -152,7 +154,7 @@ int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pre
                              const void *U, const void *psi, const void *phi, double a, void *chi,
                              double *norm2, void *work, size_t work_bytes, void *stream);
 
-/* ----------------------------------------------------- expression chain (a5)
+/* ------------------------------------------------------- expression chain
  * n_iter repetitions of  chi_k = sum_mu U_mu(x) psi_{k-1}(x+mu) + a*phi(x);
  *                        psi_k = psi_{k-1} - c * chi_k
  * with U and phi fixed (the iteration structure of the paper's smearing
@@ -163,7 +165,7 @@ int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_
                      const void *U, void *psi, const void *phi, double a, double c, int n_iter,
                      double *norms, void *work, size_t work_bytes, void *stream);
 
-/* ------------------------------------------------------- APE smearing (a6-a10)
+/* ----------------------------------------------------------- APE smearing
  * n_steps >= 1 APE steps.  One step, for every site x and direction mu,
  * from the unsmeared links of that step:
  *   W_mu(x) = (1-alpha) U_mu(x) + (alpha/6) sum_{nu != mu} [
@@ -174,14 +176,18 @@ int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_
  * the projection always in FP64.  With QDPX_F32 the staple products are
  * evaluated in FP32.  U_in is not modified; U_out must not overlap U_in.
  * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
- * triple (see qdpx_plaquette) of the input and of every step's output.
+ * triple (total, spatial, temporal; normalised as in qdpx_plaquette) of the
+ * input and of every step's output.  These traces are formed in the link
+ * precision inside the smearing kernel and summed in FP64 (qdpx_plaquette
+ * forms them in FP64); the smeared links do not depend on whether plaq is
+ * requested.
  * A W whose row 0 or projected row 1 vanishes gives NaN entries.
  * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
 int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                    const void *U_in, void *U_out, double alpha, int n_steps, double *plaq,
                    void *work, size_t work_bytes, void *stream);
 
-/* -------------------------------------------------------------- plaquette (a10)
+/* -------------------------------------------------------------- plaquette
  * plaq[0] = (1/(18V)) sum_x sum_{mu<nu} Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]
  * plaq[1] = the same over the three spatial planes (nu < 3), / (9V)
  * plaq[2] = the same over the three planes with nu = t,      / (9V)
@@ -190,22 +196,38 @@ int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
 int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                    const void *U, double *plaq, void *work, size_t work_bytes, void *stream);
 
-/* ------------------------------------------------ batched APE smearing (a11)
- * n_lat independent lattices of any extents, each smeared n_steps times as
- * in qdpx_ape_smear, followed by each lattice's output plaquette triple, in
- * ONE persistent kernel launch.  geoms: host array [n_lat]; U_in, U_out:
- * host arrays [n_lat] of device pointers (SoA, prec, fmt; U_out[i] must not
- * overlap U_in[j] for any i, j); plaq (nullable): device double[n_lat][3].
- * work: >= qdpx_workspace_bytes(QDPX_OP_BATCHED, geoms, prec, fmt, n_lat),
- * which holds the per-lattice tables, ping-pong links and counters; it is
- * re-initialised by a kernel on the stream at every call.
- * Results are identical, bit for bit, to qdpx_ape_smear on each lattice. */
+/* ------------------------------------------------------ batched APE smearing
+ * n_lat independent lattices of any extents (each at most 4194304 sites),
+ * each smeared n_steps times (1 <= n_steps <= 1024) as in qdpx_ape_smear,
+ * followed by each lattice's output plaquette triple, in ONE persistent
+ * kernel launch (plus a small kernel that clears its counters).  Work items
+ * (step, lattice, chunk of 64-site groups) are handed out in step order by a
+ * ticket counter and each lattice's steps are ordered by completion
+ * counters; a batch of small and large lattices fills the GPU as one job.
+ *   geoms: host array [n_lat]; U_in, U_out: host arrays [n_lat] of device
+ *   pointers (SoA, prec, fmt; U_out[i] must not overlap any U_in[j] or
+ *   another U_out[j]); plaq (nullable): device double[n_lat][3].
+ *   work: >= qdpx_workspace_bytes(QDPX_OP_BATCHED, geoms, prec, fmt, n_lat)
+ *   bytes; it holds the counters, ping-pong links and plaquette partials.
+ *   Bytes [4, 8) of work receive a uint32 status when the kernel ends: 0, or
+ *   1 if a wait for a previous step exceeded its spin limit (outputs are then
+ *   incomplete; the limit may be lowered with the environment variable
+ *   QDPX_SPIN_LIMIT, read at every call, to exercise this path).
+ * The first call with a given (lattices, pointers, workspace) set copies a
+ * small per-lattice table to the device and keeps it in the context (freed by
+ * qdpx_free_all / qdpx_destroy); that first call synchronises and returns
+ * QDPX_ECAPTURE on a capturing stream.  Later calls, and replays of a graph
+ * that captured one, reuse the table and only enqueue the two kernels.
+ * Links and plaquettes are identical, bit for bit, to qdpx_ape_smear on each
+ * lattice with plaquettes requested.  The number of 64-site groups per work
+ * item is set with qdpx_tune_set(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt,
+ * 256, groups, 0) (default 16). */
 int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
                            qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out,
                            double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,
                            void *stream);
 
-/* ----------------------------------------------------------- autotuner (a12)
+/* -------------------------------------------------------------- autotuner
  * Time the candidate launch geometries (threads per block, sites per
  * thread, block-to-tile mapping) of operation `op` on `geom` and remember
  * the fastest in the context, the analogue of the auto-tuning the paper

@@ -1,264 +1,52 @@
-// One APE smearing step and the FP64 plaquette.
-//
-// APE step, per link (x, mu), all from the unsmeared field U:
-//   S = sum_{nu != mu} [ U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu) ]
-//   W = (1-alpha) U_mu(x) + (alpha/6) S,   V = rowwise Gram-Schmidt of W (FP64)
-// The projection reads only rows 0 and 1 of W (row 2 of V is conj(row0 x
-// row1)), so only rows 0 and 1 of every staple are formed: each staple is
-// (2x3) = (2x3)(3x3) then (2x3)(3x3), two thirds of the full products.
-//
-// Thread mapping: a block of 256*k threads (k = 1 or 2) holds k groups of 64 consecutive
-// sites; wave w handles direction mu = w % 4 of group w / 4, so the four
-// links of a site are updated by four waves of the same block, which share
-// the neighbour loads in L1/L2.
+// Single-lattice kernels: one APE step (optionally with the plaquette of its
+// input), the plaquette-only pass, and the standalone FP64 plaquette.
 #include "qdpx_impl.hpp"
-#include "su3_device.hpp"
+#include "ape_device.hpp"
 
 namespace qdpx {
 
-// T = A(rows 0,1) * B
-template <typename R> __device__ __forceinline__ void mul_23_33(const M23<R> &A, const M3<R> &B, M23<R> &T) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            Cx<R> t{(R)0, (R)0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(t, A.e[i][k], B.e[k][j]);
-            T.e[i][j] = t;
-        }
-}
-// T = (A^dag)(rows 0,1) * B, i.e. T_ij = sum_k conj(A_ki) B_kj
-template <typename R> __device__ __forceinline__ void mul_dag23_33(const M3<R> &A, const M3<R> &B, M23<R> &T) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            Cx<R> t{(R)0, (R)0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_ca(t, A.e[k][i], B.e[k][j]);
-            T.e[i][j] = t;
-        }
-}
-// S += T * C
-template <typename R> __device__ __forceinline__ void acc_23_33(M23<R> &S, const M23<R> &T, const M3<R> &C) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(S.e[i][j], T.e[i][k], C.e[k][j]);
-}
-// S += T * C^dag
-template <typename R> __device__ __forceinline__ void acc_23_33dag(M23<R> &S, const M23<R> &T, const M3<R> &C) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
-}
-
-// Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12.
-template <typename R, int NR>
-__device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s, M3<double> &m) {
-#pragma unroll
-    for (int a = 0; a < NR; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Cx<R> z = U.ld(mu, a, b, s);
-            m.e[a][b] = Cx<double>{(double)z.re, (double)z.im};
-        }
-    if constexpr (NR == 2) rebuild_row2(m);
-}
-
-// Plaquette planes are shared out over the four direction waves so that each
-// of the six planes is counted once and each wave's planes are all spatial or
-// all temporal: wave 0 owns (0,1), (0,2); wave 1 owns (1,2); wave 2 owns
-// (2,3); wave 3 owns (3,0), (3,1).  Ownership is wave-uniform.
-__device__ __forceinline__ bool owns_plane(int mu, int nu) {
-    return (mu == 0 && (nu == 1 || nu == 2)) || (mu == 1 && nu == 2) || (mu == 2 && nu == 3) ||
-           (mu == 3 && nu < 2);
-}
-
-// Row 2 of a link whose rows 0 and 1 are in A (stored row for LINK18,
-// conj(row0 x row1) for LINK12).
-template <typename R, int NR>
-__device__ __forceinline__ void row2_of(const LinksRO<R, NR> &U, int mu, int s, const M23<R> &A, Cx<R> r[3]) {
-    if constexpr (NR == 3) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) r[b] = U.ld(mu, 2, b, s);
-    } else {
-        r[0] = conj_cross(A.e[0][1], A.e[1][2], A.e[0][2], A.e[1][1]);
-        r[1] = conj_cross(A.e[0][2], A.e[1][0], A.e[0][0], A.e[1][2]);
-        r[2] = conj_cross(A.e[0][0], A.e[1][1], A.e[0][1], A.e[1][0]);
-    }
-}
-
-// Staple sum (rows 0 and 1) of link (s, mu).  With PLQ the full upper staples
-// of the planes this wave owns are also summed into Q (all three rows), so
-// that Re Tr[U_mu(x) Q^dag] is the sum of the traces of the owned plaquettes
-// P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag.
-template <typename R, int NR, bool PLQ>
-__device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  M23<R> &S, M3<R> &Q) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
-    if constexpr (PLQ) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Q.e[i][j] = Cx<R>{(R)0, (R)0};
-    }
-    const int s = x.s;
-    const int s_mu = hop_fwd(g, s, x.c[mu], mu);
-#pragma unroll 1
-    for (int k = 0; k < 3; ++k) {
-        const int nu = k + (k >= mu);
-        // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
-        {
-            M23<R> A;
-            U.rows01(nu, s, A);
-            M3<R> B;
-            U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
-            M23<R> T;
-            mul_23_33(A, B, T);
-            M3<R> C;
-            U.full(nu, s_mu, C);
-            if (PLQ && owns_plane(mu, nu)) {
-                M23<R> X;
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
-                acc_23_33dag(X, T, C);
-                Cx<R> a2[3], t2[3];
-                row2_of(U, nu, s, A, a2);
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    t2[j] = Cx<R>{(R)0, (R)0};
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) cmac(t2[j], a2[kk], B.e[kk][j]);
-                }
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) cmac_cb(Q.e[2][j], t2[kk], C.e[j][kk]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        S.e[i][j].re += X.e[i][j].re;
-                        S.e[i][j].im += X.e[i][j].im;
-                        Q.e[i][j].re += X.e[i][j].re;
-                        Q.e[i][j].im += X.e[i][j].im;
-                    }
-            } else {
-                acc_23_33dag(S, T, C);
-            }
-        }
-        // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
-        {
-            const int y = hop_bwd(g, s, x.c[nu], nu);
-            M3<R> A;
-            U.full(nu, y, A);
-            M3<R> B;
-            U.full(mu, y, B);
-            M23<R> T;
-            mul_dag23_33(A, B, T);
-            M3<R> C;
-            U.full(nu, hop_fwd(g, y, x.c[mu], mu), C);  // y has the same mu-coordinate as x
-            acc_23_33(S, T, C);
-        }
-    }
-}
-
-// One APE step.  With PLQ the kernel also writes, for each 64-site group grp
-// and direction mu, the plaquette traces of the planes that wave owns,
-// formed in the link precision and summed in FP64: partials[grp*4 + mu]
-// (spatial planes, waves 0 and 1) and partials[4*ngroups + grp*4 + mu]
-// (temporal planes, waves 2 and 3).  They depend only on the input links.
-template <typename R, int NR, int NS, bool PLQ>
+// One APE step (or, in kPlaqOnly mode, only the plaquette of the input).
+// Thread mapping: a block of 256*k threads (k = 1 or 2) holds k groups of 64
+// consecutive sites per iteration; wave w handles direction mu = w % 4 of
+// group w / 4, so the four links of a site are updated by four waves of the
+// same block, which share the neighbour loads in L1/L2.
+template <typename R, int NR, int NS, int MODE>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
                                                   double c2, double *__restrict__ partials, int xcd) {
     const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mu = w & 3;
-    const int gpb = blockDim.x >> 8;  // site groups per block and step of j
+    const int gpb = blockDim.x >> 8;
     const int ngroups = (g.V + 63) >> 6;
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
         const int grp = (tile * NS + j) * gpb + (w >> 2);
         if (grp >= ngroups) return;
-        const int s = grp * 64 + lane;
-        double p = 0.0;
-        if (s < g.V) {
-            Site x;
-            x.init(g, s);
-            M23<R> S;
-            M3<R> Q;
-            staple_sum_rows01<R, NR, PLQ>(g, U, x, mu, S, Q);
-            M23<R> u0;
-            U.rows01(mu, s, u0);
-            if constexpr (PLQ) {
-                Cx<R> u2[3];
-                row2_of(U, mu, s, u0, u2);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    p = fma((double)u2[b].re, (double)Q.e[2][b].re, fma((double)u2[b].im, (double)Q.e[2][b].im, p));
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-                        p = fma((double)u0.e[a][b].re, (double)Q.e[a][b].re,
-                                fma((double)u0.e[a][b].im, (double)Q.e[a][b].im, p));
-                }
-            }
-            Cx<double> wm[2][3], v[3][3];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) {
-                    wm[i][jj].re = fma(c2, (double)S.e[i][jj].re, c1 * (double)u0.e[i][jj].re);
-                    wm[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u0.e[i][jj].im);
-                }
-            reunitarise(wm, v);
-#pragma unroll
-            for (int a = 0; a < NR; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, (R)v[a][b].re, (R)v[a][b].im);
-        }
-        if constexpr (PLQ) {
-            p = wave_sum(p);
-            if (lane == 0) {
-                const bool temporal = mu >= 2;
-                partials[grp * 4 + mu] = temporal ? 0.0 : p;
-                partials[4 * ngroups + grp * 4 + mu] = temporal ? p : 0.0;
-            }
-        }
+        ape_group<R, NR, MODE>(g, U, out, c1, c2, partials, grp, mu, lane);
     }
 }
 
 int ape_num_partials(const Geo &g) { return 4 * ((g.V + 63) / 64); }
 
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           double *partials, const LaunchCfg &cfg, hipStream_t st) {
+                           double *partials, int mode, const LaunchCfg &cfg, hipStream_t st) {
     const int groups = (g.V + 63) / 64;
     const int gpb = cfg.block / 256;
     const int per_block = gpb * cfg.nsite;
     const dim3 grid((groups + per_block - 1) / per_block);
-#define QDPX_APE_LAUNCH(R, NR, NS, P)                                                                          \
-    k_ape_step<R, NR, NS, P><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},        \
+#define QDPX_APE_LAUNCH(R, NR, NS, M)                                                                          \
+    k_ape_step<R, NR, NS, M><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},        \
                                                          LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,        \
                                                          partials, cfg.xcd)
-#define QDPX_APE_P(R, NR, NS)                                  \
-    if (partials) QDPX_APE_LAUNCH(R, NR, NS, true);            \
-    else QDPX_APE_LAUNCH(R, NR, NS, false);
+#define QDPX_APE_M(R, NR, NS)                                      \
+    if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly);  \
+    else if (mode == kApePlaq) QDPX_APE_LAUNCH(R, NR, NS, kApePlaq); \
+    else QDPX_APE_LAUNCH(R, NR, NS, kApe);
 #define QDPX_APE_NS(R, NR)                         \
     switch (cfg.nsite) {                           \
-    case 2: QDPX_APE_P(R, NR, 2) break;            \
-    case 4: QDPX_APE_P(R, NR, 4) break;            \
-    default: QDPX_APE_P(R, NR, 1) break;           \
+    case 2: QDPX_APE_M(R, NR, 2) break;            \
+    case 4: QDPX_APE_M(R, NR, 4) break;            \
+    default: QDPX_APE_M(R, NR, 1) break;           \
     }
     if (prec == 0) {
         QDPX_APE_NS(double, 3)
@@ -268,7 +56,7 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
         QDPX_APE_NS(float, 2)
     }
 #undef QDPX_APE_NS
-#undef QDPX_APE_P
+#undef QDPX_APE_M
 #undef QDPX_APE_LAUNCH
     return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -56,9 +57,15 @@ struct TuneKey {
     }
 };
 
+struct BatchKey {
+    std::vector<uint64_t> v;
+    bool operator<(const BatchKey &o) const { return v < o.v; }
+};
+
 struct qdpx_ctx {
     int device = 0;
     std::map<TuneKey, LaunchCfg> tuned;
+    std::map<BatchKey, void *> batch_tables;  // device tables of batched calls
 };
 
 extern "C" int qdpx_create(qdpx_ctx **out, int device) {
@@ -75,13 +82,17 @@ extern "C" int qdpx_create(qdpx_ctx **out, int device) {
 }
 
 extern "C" int qdpx_destroy(qdpx_ctx *ctx) {
+    if (ctx) qdpx_free_all(ctx);
     delete ctx;
     return QDPX_OK;
 }
 
+static void batch_cache_free(qdpx_ctx *ctx);
+
 extern "C" int qdpx_free_all(qdpx_ctx *ctx) {
     if (!ctx) return fail(QDPX_EINVAL, "qdpx_free_all: ctx is NULL");
-    return QDPX_OK;  // no device tables are cached by this version
+    batch_cache_free(ctx);
+    return QDPX_OK;
 }
 
 // --------------------------------------------------------------- validation
@@ -178,6 +189,7 @@ static bool stream_capturing(hipStream_t st) {
 
 static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
     LaunchCfg c;
+    if (op == QDPX_OP_BATCHED) c.nsite = 16;  // 64-site groups per work item
     if (ctx) {
         TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
         auto it = ctx->tuned.find(k);
@@ -355,33 +367,164 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
         void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, plaq ? part : nullptr, cfg, st), fn);
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, plaq ? part : nullptr, plaq ? 1 : 0,
+                                     cfg, st),
+                     fn);
         if (plaq) QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
         src = dst;
     }
     if (plaq) {
-        if (int r = plaquette_into(g, prec, fmt, U_out, plaq + 3 * n_steps, part, st, fn)) return r;
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), U_out, nullptr, c1, c2, part, 2, cfg, st), fn);
+        QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * n_steps, st), fn);
     }
     return QDPX_OK;
 }
 
-// ------------------------------------------------------- batched (stub size)
+// ------------------------------------------------------------------ batched
+// Workspace: [counters: 2 + n_lat * (kBatchMaxSteps+1) uint32, 256-aligned]
+// then per lattice [ping-pong links][plaquette partials], each 256-aligned.
+static const int kBatchMaxSteps = 1024;
+static const int kBatchMaxLattices = 4096;
+
+static size_t batched_counter_bytes(int n_lat) { return round256(sizeof(unsigned) * (2 + (size_t)n_lat * (kBatchMaxSteps + 1))); }
+
+static size_t batched_lattice_bytes(const qdpx_geom *g, qdpx_prec prec, qdpx_linkfmt fmt) {
+    const Geo geo = make_geo(g->L);
+    const size_t groups = ((size_t)geo.V + 63) / 64;
+    return round256(qdpx_links_bytes(g, prec, fmt)) + round256(sizeof(double) * 2 * 4 * groups);
+}
+
+static int batched_check_geoms(int n_lat, const qdpx_geom *geoms, const char *fn) {
+    if (n_lat < 1 || n_lat > kBatchMaxLattices)
+        return fail(QDPX_EINVAL, "%s: n_lat = %d outside [1, %d]", fn, n_lat, kBatchMaxLattices);
+    if (!geoms) return fail(QDPX_EINVAL, "%s: geoms is NULL", fn);
+    for (int i = 0; i < n_lat; ++i) {
+        if (!geom_ok(&geoms[i], fn)) return QDPX_EINVAL;
+        const Geo g = make_geo(geoms[i].L);
+        if ((g.V + 63) / 64 > batched_max_stage_groups())
+            return fail(QDPX_EUNSUPPORTED, "%s: lattice %d has %d sites; batched lattices are limited to %d", fn, i,
+                        g.V, batched_max_stage_groups() * 64);
+    }
+    return QDPX_OK;
+}
+
 static size_t batched_ws_bytes(int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt, int n_steps) {
-    (void)n_lat;
-    (void)geoms;
-    (void)prec;
-    (void)fmt;
     (void)n_steps;
-    fail(QDPX_EUNSUPPORTED, "batched smearing is not built yet");
-    return 0;
+    const char *fn = "qdpx_workspace_bytes";
+    if (batched_check_geoms(n_lat, geoms, fn) != QDPX_OK) return 0;
+    if (check_format(prec, fmt, fn) != QDPX_OK) return 0;
+    size_t b = batched_counter_bytes(n_lat);
+    for (int i = 0; i < n_lat; ++i) b += batched_lattice_bytes(&geoms[i], prec, fmt);
+    return b;
+}
+
+// The per-lattice device table is built on the first call with a given set
+// of arguments and kept by the context (like the paper's device storage for
+// shift tables, section 5.2); later calls, and graph replays, reuse it.
+static void batch_cache_free(qdpx_ctx *ctx) {
+    for (auto &kv : ctx->batch_tables) hipFree(kv.second);
+    ctx->batch_tables.clear();
+}
+
+static unsigned spin_limit_from_env() {
+    const char *e = getenv("QDPX_SPIN_LIMIT");
+    if (!e || !*e) return 1u << 24;
+    return (unsigned)strtoul(e, nullptr, 10);
 }
 
 extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
                                       qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out, double alpha,
                                       int n_steps, double *plaq, void *work, size_t work_bytes, void *stream) {
-    (void)ctx; (void)n_lat; (void)geoms; (void)prec; (void)fmt; (void)U_in; (void)U_out; (void)alpha;
-    (void)n_steps; (void)plaq; (void)work; (void)work_bytes; (void)stream;
-    return fail(QDPX_EUNSUPPORTED, "qdpx_ape_smear_batched: not built yet");
+    const char *fn = "qdpx_ape_smear_batched";
+    QDPX_CHECK_CTX(fn);
+    if (int r = batched_check_geoms(n_lat, geoms, fn)) return r;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U_in || !U_out) return fail(QDPX_EINVAL, "%s: NULL pointer array", fn);
+    if (n_steps < 1 || n_steps > kBatchMaxSteps)
+        return fail(QDPX_EINVAL, "%s: n_steps = %d outside [1, %d]", fn, n_steps, kBatchMaxSteps);
+    const size_t need = batched_ws_bytes(n_lat, geoms, prec, fmt, n_steps);
+    if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    std::vector<size_t> lb(n_lat);
+    for (int i = 0; i < n_lat; ++i) {
+        if (!U_in[i] || !U_out[i]) return fail(QDPX_EINVAL, "%s: NULL links for lattice %d", fn, i);
+        lb[i] = qdpx_links_bytes(&geoms[i], prec, fmt);
+    }
+    for (int i = 0; i < n_lat; ++i) {
+        if (overlap(U_out[i], lb[i], work, need)) return fail(QDPX_EALIAS, "%s: U_out[%d] overlaps the workspace", fn, i);
+        if (overlap(U_in[i], lb[i], work, need)) return fail(QDPX_EALIAS, "%s: U_in[%d] overlaps the workspace", fn, i);
+        for (int j = 0; j < n_lat; ++j) {
+            if (overlap(U_out[i], lb[i], U_in[j], lb[j]))
+                return fail(QDPX_EALIAS, "%s: U_out[%d] overlaps U_in[%d]", fn, i, j);
+            if (j != i && overlap(U_out[i], lb[i], U_out[j], lb[j]))
+                return fail(QDPX_EALIAS, "%s: U_out[%d] overlaps U_out[%d]", fn, i, j);
+        }
+    }
+    if (plaq && overlap(plaq, sizeof(double) * 3 * n_lat, work, need))
+        return fail(QDPX_EALIAS, "%s: plaq overlaps the workspace", fn);
+
+    // groups per work item: tuned per (first lattice extents, precision, format)
+    const int group_chunk = std::max(1, cfg_for(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt).nsite);
+    // host table
+    std::vector<BatchLat> tab(n_lat);
+    char *base = (char *)work + batched_counter_bytes(n_lat);
+    int64_t items = 0;
+    for (int i = 0; i < n_lat; ++i) {
+        BatchLat &L = tab[i];
+        memset(&L, 0, sizeof L);
+        L.g = make_geo(geoms[i].L);
+        L.in = U_in[i];
+        L.out = U_out[i];
+        L.tmp = base;
+        L.partials = (double *)(base + round256(lb[i]));
+        base += batched_lattice_bytes(&geoms[i], prec, fmt);
+        L.ngroups = (L.g.V + 63) / 64;
+        L.nitems = (L.ngroups + group_chunk - 1) / group_chunk;
+        L.item_base = (int)items;
+        items += L.nitems;
+    }
+    const int n_phases = n_steps + (plaq ? 1 : 0);
+    if (items * n_phases >= (int64_t)1 << 31) return fail(QDPX_EUNSUPPORTED, "%s: too many work items", fn);
+
+    BatchKey key;
+    key.v = {(uint64_t)n_lat, (uint64_t)prec, (uint64_t)fmt, (uint64_t)(uintptr_t)work, (uint64_t)group_chunk};
+    for (int i = 0; i < n_lat; ++i) {
+        for (int d = 0; d < 4; ++d) key.v.push_back((uint64_t)geoms[i].L[d]);
+        key.v.push_back((uint64_t)(uintptr_t)U_in[i]);
+        key.v.push_back((uint64_t)(uintptr_t)U_out[i]);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    void *dtab = nullptr;
+    auto it = ctx->batch_tables.find(key);
+    if (it != ctx->batch_tables.end()) {
+        dtab = it->second;
+    } else {
+        if (stream_capturing(st))
+            return fail(QDPX_ECAPTURE, "%s: the first call with these lattices must not be captured", fn);
+        QDPX_TRY_HIP(hipMalloc(&dtab, sizeof(BatchLat) * n_lat), fn);
+        hipError_t e = hipMemcpy(dtab, tab.data(), sizeof(BatchLat) * n_lat, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dtab);
+            return hip_fail(e, fn);
+        }
+        ctx->batch_tables[key] = dtab;
+    }
+    BatchArgs a;
+    a.lats = (const BatchLat *)dtab;
+    a.counters = (unsigned *)work;
+    a.plaq = plaq;
+    a.c1 = 1.0 - alpha;
+    a.c2 = alpha / 6.0;
+    a.n_lat = n_lat;
+    a.n_steps = n_steps;
+    a.n_phases = n_phases;
+    a.items_per_phase = (int)items;
+    a.group_chunk = group_chunk;
+    a.spin_limit = spin_limit_from_env();
+    const int resident = batched_resident_blocks(prec, nrows_of(fmt));
+    if (resident <= 0) return fail(QDPX_EHIP, "%s: occupancy query failed", fn);
+    const int grid = (int)std::min<int64_t>(resident, items * n_phases);
+    QDPX_TRY_HIP(launch_ape_batched(a, prec, nrows_of(fmt), grid, st), fn);
+    return QDPX_OK;
 }
 
 // ------------------------------------------------------------------- tuner
@@ -391,6 +534,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
         return c.block <= 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
+    if (op == QDPX_OP_BATCHED) return c.block == 256 && c.nsite >= 1 && c.nsite <= 1024;  // nsite = groups per item
     return false;
 }
 
@@ -486,7 +630,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     const int nrows = nrows_of(fmt);
     for (const LaunchCfg &c : cands) {
         auto run = [&]() -> hipError_t {
-            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, nullptr, c, st);
+            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, nullptr, 0, c, st);
             return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
                                 st);
         };

@@ -3,7 +3,7 @@
 // norm, the chain update psi - c chi, and the deterministic finalisation of
 // FP64 partial sums.
 #include "qdpx_impl.hpp"
-#include "su3_device.hpp"
+#include "reduce_device.hpp"
 
 namespace qdpx {
 
@@ -246,24 +246,16 @@ hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *ds
 }
 
 // ------------------------------------------------------------ finalisation
-// Stage A: block b sums partials [b*4096, (b+1)*4096) of each component,
-// 16 consecutive values per thread then a fixed block tree.  Stage B: one
-// block sums the stage-A values in index order and applies the mode.
-constexpr int kFinChunk = 16;
-constexpr int kFinPerBlock = kReduceBlock * kFinChunk;
-
+// Stage A: block b sums partials [b*4096, (b+1)*4096) of each component;
+// stage B: one block sums the stage-A values and applies the mode.  The
+// arithmetic lives in reduce_device.hpp so the batched kernel can repeat it
+// bit for bit inside one block.
 __global__ void __launch_bounds__(kReduceBlock) k_finalize_a(const double *__restrict__ in, int n, int ncomp,
                                                             double *__restrict__ out) {
     __shared__ double lds[kReduceBlock / 64];
     const int nb = gridDim.x;
     for (int comp = 0; comp < ncomp; ++comp) {
-        const double *p = in + (int64_t)comp * n;
-        const int base = blockIdx.x * kFinPerBlock + threadIdx.x * kFinChunk;
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < kFinChunk; ++k)
-            if (base + k < n) v += p[base + k];
-        v = block_sum<kReduceBlock / 64>(v, lds);
+        const double v = fin_stage_a(in + (int64_t)comp * n, n, blockIdx.x, lds);
         if (threadIdx.x == 0) out[comp * nb + blockIdx.x] = v;
     }
 }
@@ -273,20 +265,8 @@ __global__ void __launch_bounds__(kReduceBlock) k_finalize_b(const double *__res
     __shared__ double lds[kReduceBlock / 64];
     const int ncomp = (mode == 1) ? 2 : 1;
     double r[2] = {0.0, 0.0};
-    for (int comp = 0; comp < ncomp; ++comp) {
-        double v = 0.0;
-        for (int i = threadIdx.x; i < n; i += kReduceBlock) v += in[comp * n + i];
-        r[comp] = block_sum<kReduceBlock / 64>(v, lds);
-    }
-    if (threadIdx.x == 0) {
-        if (mode == 0) {
-            out[0] = r[0];
-        } else {
-            out[0] = (r[0] + r[1]) / (18.0 * volume);
-            out[1] = r[0] / (9.0 * volume);
-            out[2] = r[1] / (9.0 * volume);
-        }
-    }
+    for (int comp = 0; comp < ncomp; ++comp) r[comp] = fin_stage_b(in + comp * n, n, lds);
+    if (threadIdx.x == 0) fin_write(r, mode, volume, out);
 }
 
 int finalize_stage_a_blocks(int n) { return (n + kFinPerBlock - 1) / kFinPerBlock; }

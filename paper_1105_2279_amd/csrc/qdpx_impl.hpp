@@ -5,9 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace qdpx {
+#include "su3_device.hpp"
 
-struct Geo;
+namespace qdpx {
 
 // Launch geometry of one operation (chosen by the tuner or defaulted).
 struct LaunchCfg {
@@ -44,13 +44,41 @@ hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *ds
 hipError_t launch_finalize(const double *partials, int n, int mode, double volume, double *out, hipStream_t st);
 
 // ---- ape.hip
-// One APE step.  partials (nullable): FP64 plaquette traces of the INPUT
-// links, ape_num_partials(g) per component (spatial, temporal), reduced by
-// launch_finalize(partials, ape_num_partials(g), 1, V, out).
+// One APE step.  mode 0: links only; mode 1: also the plaquette traces of
+// the INPUT links into partials; mode 2: only those traces (Uout unused).
+// partials hold ape_num_partials(g) values per component (spatial,
+// temporal), reduced by launch_finalize(partials, ape_num_partials(g), 1, V, out).
 int ape_num_partials(const Geo &g);
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           double *partials, const LaunchCfg &cfg, hipStream_t st);
+                           double *partials, int mode, const LaunchCfg &cfg, hipStream_t st);
 int plaquette_num_partials(const Geo &g);  // per component (2 components)
 hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st);
+
+// ---- batched.hip
+// One lattice of a batch (device table entry).
+struct BatchLat {
+    Geo g;
+    const void *in;    // caller's input links
+    void *out;         // caller's output links
+    void *tmp;         // ping-pong links in the workspace (n_steps >= 2)
+    double *partials;  // 2 * 4 * ngroups plaquette partials in the workspace
+    int ngroups;       // 64-site groups
+    int nitems;        // work items per phase
+    int item_base;     // index of this lattice's first item within a phase
+    int pad;
+};
+
+struct BatchArgs {
+    const BatchLat *lats;  // device table [n_lat]
+    unsigned *counters;    // [0] ticket, [1] status, [2..] done[n_lat][n_phases]
+    double *plaq;          // nullable, [n_lat][3]
+    double c1, c2;
+    int n_lat, n_steps, n_phases, items_per_phase, group_chunk;
+    unsigned spin_limit;
+};
+
+int batched_max_stage_groups();
+int batched_resident_blocks(int prec, int nrows);
+hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int grid, hipStream_t st);
 
 }  // namespace qdpx
