@@ -63,6 +63,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--profile", action="store_true",
+                   help="short run for hardware-counter profiling: one 1 GiB device copy (the calibration "
+                        "kernel of known size), then two timed-step calls of each APE link format; no JSON line")
     return p.parse_args()
 
 
@@ -105,6 +108,13 @@ def main():
     for name, (prec, fmt) in paths.items():
         dev_links[name] = q.links_to_device(ctx, L, U, prec, fmt, dev)
     torch.cuda.synchronize()
+    # launch geometry from the library's autotuner (not timed)
+    tuned = {}
+    for name, (prec, fmt) in paths.items():
+        q.qdpx_tune(ctx, q.OP_APE, L, prec, fmt)
+        tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window"),
+                               q.qdpx_tune_get(ctx, q.OP_APE, L, prec, fmt)))
+        log(f"tuned APE {name}: {tuned[name]}")
 
     def make_call(name, with_plaq=True, n=N_APE):
         prec, fmt = paths[name]
@@ -117,6 +127,21 @@ def main():
             q.qdpx_ape_smear(ctx, L, prec, fmt, src, out, ALPHA, n, plaq, work, stream)
 
         return call, out, plaq
+
+    if args.profile:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+        for name in paths:
+            call, _, _ = make_call(name)
+            call()
+            call()
+        torch.cuda.synchronize()
+        log("profile run done")
+        ctx.close()
+        return
 
     results = {}
     # ---------------------------------------------------------------- headline
@@ -179,10 +204,12 @@ def main():
         "fp32_18_link_updates_per_s": results["f32_18"],
         "speedup_fp32_12_vs_fp64": results["f32_12"] / results["f64_18"],
         "ape_kernel_roofline": {k: roof(k) for k in paths},
+        "tuned_launch": tuned,
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
     }
     if not args.no_extras:
         extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
+        extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -209,6 +236,7 @@ def main():
             "sites": V,
             "ape_steps_per_step": N_APE,
             "parallelism": "1 GPU",
+            "tuned_launch": tuned["f32_12"],
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -234,6 +262,7 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
         chi = q.alloc_fermion(Ls, prec, dev)
         n2 = torch.zeros(1, dtype=torch.float64, device=dev)
         work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
+        q.qdpx_tune(ctx, q.OP_SHIFT, Ls, prec, fmt)
 
         def call():
             q.qdpx_eval_shift_mul_axpy(ctx, Ls, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work, stream)
@@ -244,6 +273,7 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
         t = ms / 1e3 / reps
         gbs = bytes_site * V / t / 1e9
         out[f"shift_{name}_32x32x32x64"] = {
+            "tuned_launch": q.qdpx_tune_get(ctx, q.OP_SHIFT, Ls, prec, fmt),
             "sites_per_s": V / t,
             "us_per_call": t * 1e6,
             "hbm_gbs_algorithmic": gbs,
@@ -252,6 +282,66 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
         log(f"shift {name}: {t * 1e6:.1f} us, {gbs:.0f} GB/s")
         del Ud, pd, fd, chi, work
     return out
+
+
+def batched_extras(torch, q, ctx, dev, stream, latgen):
+    """64 lattices with extents drawn from 8^4, 12^3x24, 16^3x32, 24^3x48; 5 APE
+    steps + final plaquettes, FP32-12: one persistent launch replayed from a
+    captured HIP graph, against the loop of 64 single-lattice calls."""
+    prec, fmt, n = q.F32, q.LINK12, 5
+    Ls = latgen.batch_extents()
+    seed0 = latgen.SEEDS["batch_64"]["first_lattice"]
+    t = time.time()
+    Uds = [q.links_to_device(ctx, L, latgen.haar_links(L, seed0 + i), prec, fmt, dev) for i, L in enumerate(Ls)]
+    log(f"batched: generated 64 lattices in {time.time() - t:.1f} s")
+    sites = sum(latgen.volume(L) for L in Ls)
+    updates = 4.0 * sites * n
+    outs = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
+    plaq = torch.zeros(3 * len(Ls), dtype=torch.float64, device=dev)
+    work = q.alloc_workspace(q.OP_BATCHED, Ls, prec, fmt, len(Ls), dev)
+
+    def batched():
+        q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, stream)
+
+    batched()  # first call builds the device table
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.graph(g, stream=s):
+        q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, s)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 10
+    ms_graph = time_calls(torch, g.replay, reps, stream) / reps
+    status = int(work[4:8].cpu().numpy().view("uint32")[0])
+
+    loop_out = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
+    loop_plaq = [torch.zeros(3 * (n + 1), dtype=torch.float64, device=dev) for _ in Ls]
+    loop_work = [q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev) for L in Ls]
+
+    def loop():
+        for i, L in enumerate(Ls):
+            q.qdpx_ape_smear(ctx, L, prec, fmt, Uds[i], loop_out[i], ALPHA, n, loop_plaq[i], loop_work[i], stream)
+
+    loop()
+    torch.cuda.synchronize()
+    ms_loop = time_calls(torch, loop, reps, stream) / reps
+    same = all(torch.equal(plaq[3 * i:3 * i + 3], loop_plaq[i][3 * n:3 * n + 3]) for i in range(len(Ls)))
+    log(f"batched: graph {ms_graph:.2f} ms, loop {ms_loop:.2f} ms, status {status}, identical plaquettes {same}")
+    return {
+        "batched_64_lattices": {
+            "sites": sites,
+            "ape_steps": n,
+            "link_updates_per_s_persistent_graph": updates / (ms_graph / 1e3),
+            "link_updates_per_s_per_lattice_loop": updates / (ms_loop / 1e3),
+            "ms_persistent_graph": ms_graph,
+            "ms_per_lattice_loop": ms_loop,
+            "speedup_vs_loop": ms_loop / ms_graph,
+            "status": status,
+            "final_plaquettes_identical_to_loop": bool(same),
+        }
+    }
 
 
 def cpu_baseline(U):

@@ -14,7 +14,8 @@
  * Conventions shared by every call
  * --------------------------------
  * Lattice: extents L[0..3] = (Lx, Ly, Lz, Lt), 2 <= L[d] <= 4096,
- *   V = Lx*Ly*Lz*Lt < 2^31; direction mu = 0..3 is x, y, z, t; all
+ *   V = Lx*Ly*Lz*Lt < 2^28 (so every per-component byte offset fits 32
+ *   bits; 2^28 sites of FP64 links are 154 GB); direction mu = 0..3 is x, y, z, t; all
  *   directions periodic; site = x + Lx*(y + Ly*(z + Lz*t)).
  * Matrices: U_mu(x) is a 3x3 complex matrix acting on colour,
  *   (U psi)_a = sum_b U_ab psi_b, identity in spin.  "Row" = first index.
@@ -228,20 +229,25 @@ int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdp
                            void *stream);
 
 /* -------------------------------------------------------------- autotuner
- * Time the candidate launch geometries (threads per block, sites per
- * thread, block-to-tile mapping) of operation `op` on `geom` and remember
- * the fastest in the context, the analogue of the auto-tuning the paper
- * proposes in sections 5.4 and 9.  Allocates and frees temporary device
- * buffers and synchronises the device, so it returns QDPX_ECAPTURE on a
- * capturing stream.  Every candidate produces bit-identical results.
- * qdpx_tune_get / qdpx_tune_set read and write the remembered choice
- * (block threads, sites per thread, xcd mapping flag). */
+ * Time the candidate launch geometries of operation `op` (QDPX_OP_APE,
+ * QDPX_OP_SHIFT or QDPX_OP_CHAIN) on `geom` and remember the fastest in the
+ * context: threads per block, consecutive 64-site groups per wave, the
+ * XCD-contiguous block order, and the number of t planes walked together.
+ * This is the auto-tuning of the thread geometry the paper proposes
+ * (sections 5.4 and 9).  Allocates and frees temporary device buffers and
+ * synchronises the device, so it returns QDPX_ECAPTURE on a capturing
+ * stream.  Every candidate produces bit-identical results.
+ * qdpx_tune_get / qdpx_tune_set read and write the remembered choice;
+ * t_window must divide Lt and only matters when Lx is a multiple of 8 and Ly
+ * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED only
+ * sites_per_thread is used, as the number of 64-site groups per work item,
+ * keyed by the first lattice's extents. */
 int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
               void *stream);
 int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                  int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map);
+                  int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window);
 int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                  int32_t block, int32_t sites_per_thread, int32_t xcd_map);
+                  int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window);
 
 #ifdef __cplusplus
 }

@@ -97,8 +97,10 @@ def lib():
                                          _P, _P, sz, _P]),
         "qdpx_tune": (i32, [_P, i32, _G, i32, i32, _P]),
         "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
-        "qdpx_tune_set": (i32, [_P, i32, _G, i32, i32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)]),
+        "qdpx_tune_set": (i32, [_P, i32, _G, i32, i32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(h, name)
@@ -264,15 +266,16 @@ def qdpx_tune(ctx, op, L, prec, fmt, stream=None):
 
 
 def qdpx_tune_get(ctx, op, L, prec, fmt):
-    b, n, x = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(block, sites_per_thread, xcd_map, t_window) remembered for this case."""
+    b, n, x, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().qdpx_tune_get(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, ctypes.byref(b), ctypes.byref(n),
-                               ctypes.byref(x)), "qdpx_tune_get")
-    return int(b.value), int(n.value), int(x.value)
+                               ctypes.byref(x), ctypes.byref(t)), "qdpx_tune_get")
+    return int(b.value), int(n.value), int(x.value), int(t.value)
 
 
-def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map):
+def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map, t_window=1):
     _check(lib().qdpx_tune_set(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, int(block),
-                               int(sites_per_thread), int(xcd_map)), "qdpx_tune_set")
+                               int(sites_per_thread), int(xcd_map), int(t_window)), "qdpx_tune_set")
 
 
 # ------------------------------------------------- host <-> device conveniences

@@ -263,12 +263,11 @@ __device__ __forceinline__ double retrace_with(const LinksRO<R, NR> &U, int mu, 
 template <typename R, int NR, int MODE>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
                                           double c2, double *__restrict__ partials, int grp, int mu, int lane) {
-    const int ngroups = (g.V + 63) >> 6;
-    const int s = grp * 64 + lane;
+    const int ngroups = num_groups(g);
     double p = 0.0;
-    if (s < g.V) {
-        Site x;
-        x.init(g, s);
+    Site x;
+    if (group_site(g, grp, lane, x)) {
+        const int s = x.s;
         M3<R> Q;
         if constexpr (MODE == kPlaqOnly) {
             owned_upper_staples(g, U, x, mu, Q);

@@ -109,8 +109,8 @@ static bool geom_ok(const qdpx_geom *g, const char *fn) {
         }
         v *= g->L[d];
     }
-    if (v > 2147483647LL - 256) {
-        fail(QDPX_EINVAL, "%s: volume %lld too large", fn, (long long)v);
+    if (v >= (1LL << 28)) {  // keeps every per-component byte offset within 32 bits
+        fail(QDPX_EINVAL, "%s: volume %lld not below 2^28", fn, (long long)v);
         return false;
     }
     return true;
@@ -531,6 +531,7 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
 static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (c.block < 64 || c.block > 1024 || (c.block % 64)) return false;
     if (c.xcd != 0 && c.xcd != 1) return false;
+    if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
         return c.block <= 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
@@ -539,7 +540,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
 }
 
 extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                             int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map) {
+                             int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window) {
     const char *fn = "qdpx_tune_get";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -548,11 +549,12 @@ extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     if (block) *block = c.block;
     if (sites_per_thread) *sites_per_thread = c.nsite;
     if (xcd_map) *xcd_map = c.xcd;
+    if (t_window) *t_window = c.tw;
     return QDPX_OK;
 }
 
 extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                             int32_t block, int32_t sites_per_thread, int32_t xcd_map) {
+                             int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window) {
     const char *fn = "qdpx_tune_set";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -561,9 +563,10 @@ extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     c.block = block;
     c.nsite = sites_per_thread;
     c.xcd = xcd_map;
-    if (!cfg_valid(op, c))
-        return fail(QDPX_EINVAL, "%s: geometry (block %d, sites %d, xcd %d) not valid for op %d", fn, block,
-                    sites_per_thread, xcd_map, (int)op);
+    c.tw = t_window;
+    if (!cfg_valid(op, c) || geom->L[3] % c.tw != 0)
+        return fail(QDPX_EINVAL, "%s: geometry (block %d, sites %d, xcd %d, t window %d) not valid for op %d", fn,
+                    block, sites_per_thread, xcd_map, t_window, (int)op);
     ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = c;
     return QDPX_OK;
 }
@@ -613,15 +616,18 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     const int blocks_shift[] = {64, 128, 256};
     const int ns_ape[] = {1, 2, 4};
     const int ns_shift[] = {1, 2, 4, 8};
-    for (int x = 0; x < 2; ++x) {
-        if (op == QDPX_OP_APE) {
-            for (int b : blocks_ape)
-                for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x});
-        } else {
-            for (int b : blocks_shift)
-                for (int n : ns_shift) cands.push_back(LaunchCfg{b, n, x});
+    const int tws[] = {1, 2, 4, 8, 16};
+    for (int x = 0; x < 2; ++x)
+        for (int tw : tws) {
+            if (geom->L[3] % tw || (tw > 1 && g.bwl == 0)) continue;
+            if (op == QDPX_OP_APE) {
+                for (int b : blocks_ape)
+                    for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x, tw});
+            } else {
+                for (int b : blocks_shift)
+                    for (int n : ns_shift) cands.push_back(LaunchCfg{b, n, x, tw});
+            }
         }
-    }
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);

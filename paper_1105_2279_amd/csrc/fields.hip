@@ -16,6 +16,16 @@ Geo make_geo(const int32_t L[4]) {
     g.st[3] = L[0] * L[1] * L[2];
     g.V = g.st[3] * L[3];
     g.S = ((int64_t)g.V + 255) / 256 * 256;
+    g.bwl = g.P = g.pbx = 0;
+    if (L[0] % 16 == 0 && L[1] % 4 == 0) {
+        g.bwl = 4;
+        g.pbx = L[0] / 16;
+        g.P = g.pbx * (L[1] / 4);
+    } else if (L[0] % 8 == 0 && L[1] % 8 == 0) {
+        g.bwl = 3;
+        g.pbx = L[0] / 8;
+        g.P = g.pbx * (L[1] / 8);
+    }
     return g;
 }
 
@@ -133,20 +143,21 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 // size, NS or the tile mapping.
 template <typename R, int NR, int MODE, int NS>
 __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
-                                                FermWO<R> out, double *__restrict__ partials, int xcd) {
+                                                FermWO<R> out, double *__restrict__ partials, int xcd, int tw) {
     const int nwb = blockDim.x >> 6;
     const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int lane = threadIdx.x & 63;
-    const int ngroups = (g.V + 63) >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ngroups = num_groups(g);
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
-        const int grp = (tile * nwb + (int)(threadIdx.x >> 6)) * NS + j;
-        if (grp >= ngroups) return;  // whole wave leaves together
-        const int s = grp * 64 + lane;
+        const int i = (tile * nwb + wave) * NS + j;
+        if (i >= ngroups) return;  // whole wave leaves together
+        const int grp = traverse(g, i, tw);
         double n2 = 0.0;
-        if (s < g.V) {
-            Site x;
-            x.init(g, s);
+        Site x;
+        if (group_site(g, grp, lane, x)) {
+            const int s = x.s;
             Cx<R> acc[4][3];
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
@@ -204,13 +215,13 @@ static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, cons
     FermRO<R> p{(const V *)psi, g.S}, f{(const V *)phi, g.S};
     FermWO<R> o{(V *)out, g.S};
     const int groups = (g.V + 63) / 64;
-    const int per_block = (cfg.block / 64) * cfg.nsite;
+    const int per_block = (cfg.block / 64) * cfg.nsite;  // 64-site groups per block
     const dim3 grid((groups + per_block - 1) / per_block);
     switch (cfg.nsite) {
-    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
-    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
-    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
-    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd); break;
+    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
+    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
+    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
+    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
     }
 }
 

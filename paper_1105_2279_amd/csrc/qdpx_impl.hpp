@@ -14,6 +14,7 @@ struct LaunchCfg {
     int block = 256;  // threads per block, multiple of 64
     int nsite = 1;    // consecutive 64-site groups handled per wave
     int xcd = 1;      // 1: XCD-contiguous tile mapping, 0: identity
+    int tw = 1;       // t planes walked together (brick mapping only; must divide Lt)
 };
 
 // Threads per block of the fixed-shape reduction kernels (plaquette,

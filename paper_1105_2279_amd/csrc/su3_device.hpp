@@ -10,11 +10,25 @@
 namespace qdpx {
 
 // ---------------------------------------------------------------- geometry
-// Extents, per-direction site strides and the padded SoA stride.
+// Extents, per-direction site strides, the padded SoA stride and the
+// mapping of 64-site groups (one group per wave) to sites.
+//
+// Brick mapping (bwl = 4 or 3): when Lx is a multiple of bw = 2^bwl and Ly a
+// multiple of 64/bw, group g is a bw x (64/bw) brick of one (z, t) plane:
+// g = p + P*(z + Lz*t) with p the brick within the xy plane (P bricks per
+// plane, pbx along x); lane l sits at x = xb*bw + l % bw, y = yb*(64/bw) + l / bw.
+// A wave then touches 64/bw rows of bw consecutive sites (whole cache lines),
+// and the groups of one xy plane are numbered consecutively, so a window of
+// t planes can be walked together (see traverse()).  Otherwise (bwl = 0)
+// group g is the 64 consecutive sites [64 g, 64 g + 64).  The mapping depends
+// only on the extents, so per-group partial sums never depend on the launch.
 struct Geo {
     int L[4];
     int st[4];  // 1, Lx, Lx*Ly, Lx*Ly*Lz
     int V;
+    int bwl;    // log2 of the brick width, 0 for the linear mapping
+    int P;      // bricks per xy plane
+    int pbx;    // bricks along x
     int64_t S;  // SoA component stride (elements)
 };
 
@@ -32,6 +46,43 @@ struct Site {
         c[3] = r / g.L[2];
     }
 };
+
+__device__ __forceinline__ int num_groups(const Geo &g) { return (g.V + 63) >> 6; }
+
+// Site of lane `lane` of group `grp` (grp is wave-uniform, so the divisions
+// run on the scalar unit).  Returns false for the padding lanes of the last
+// linear group.
+__device__ __forceinline__ bool group_site(const Geo &g, int grp, int lane, Site &x) {
+    if (g.bwl) {
+        const int p = grp % g.P, r = grp / g.P;
+        const int z = r % g.L[2], t = r / g.L[2];
+        const int xb = p % g.pbx, yb = p / g.pbx;
+        const int bw = 1 << g.bwl;
+        x.c[0] = xb * bw + (lane & (bw - 1));
+        x.c[1] = yb * (64 >> g.bwl) + (lane >> g.bwl);
+        x.c[2] = z;
+        x.c[3] = t;
+        x.s = x.c[0] + g.L[0] * (x.c[1] + g.L[1] * (z + g.L[2] * t));
+        return true;
+    }
+    const int s = grp * 64 + lane;
+    if (s >= g.V) return false;
+    x.init(g, s);
+    return true;
+}
+
+// Launch order -> group.  With the brick mapping and a window of tw t planes
+// (tw divides Lt), consecutive logical indices walk the tw planes of one
+// (brick, z) column before moving on, so the blocks in flight on one XCD hold
+// each other's t neighbours in L2.  tw = 1 (or the linear mapping) is the
+// identity.  A bijection on [0, num_groups).
+__device__ __forceinline__ int traverse(const Geo &g, int i, int tw) {
+    if (!g.bwl || tw <= 1) return i;
+    const int tin = i % tw, rest = i / tw;
+    const int plane = g.P * g.L[2];
+    const int pz = rest % plane, tc = rest / plane;
+    return pz + plane * (tc * tw + tin);
+}
 
 __device__ __forceinline__ int hop_fwd(const Geo &g, int s, int cmu, int mu) {
     return (cmu == g.L[mu] - 1) ? s - (g.L[mu] - 1) * g.st[mu] : s + g.st[mu];
@@ -101,8 +152,12 @@ template <typename R> __device__ __forceinline__ void rebuild_row2(M3<R> &m) {
 template <typename R, int NR> struct LinksRO {
     const vec2_t<R> *__restrict__ p;
     int64_t S;
+    // The component base is uniform across the wave (mu is wave-uniform, a
+    // and b are constants) and the site offset fits 32 bits (V < 2^28), so
+    // every load is one SGPR base + one 32-bit VGPR offset.
     __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
-        vec2_t<R> v = p[(int64_t)((mu * NR + a) * 3 + b) * S + s];
+        const vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
+        const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
     __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const {
@@ -132,7 +187,8 @@ template <typename R, int NR> struct LinksWO {
         vec2_t<R> v;
         v.x = re;
         v.y = im;
-        p[(int64_t)((mu * NR + a) * 3 + b) * S + s] = v;
+        vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
+        *(vec2_t<R> *)((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>)) = v;
     }
 };
 
@@ -142,7 +198,8 @@ template <typename R> struct FermRO {
     const vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ Cx<R> ld(int sp, int c, int s) const {
-        vec2_t<R> v = p[(int64_t)(sp * 3 + c) * S + s];
+        const vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
+        const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
 };
@@ -153,7 +210,8 @@ template <typename R> struct FermWO {
         vec2_t<R> v;
         v.x = z.re;
         v.y = z.im;
-        p[(int64_t)(sp * 3 + c) * S + s] = v;
+        vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
+        *(vec2_t<R> *)((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>)) = v;
     }
 };
 

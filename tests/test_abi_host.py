@@ -55,7 +55,7 @@ def test_workspace_sizes():
     assert q.qdpx_workspace_bytes(q.OP_CHAIN, L, q.F64, q.LINK18, 8) >= q.qdpx_fermion_bytes(L, q.F64)
 
 
-@pytest.mark.parametrize("L", [(1, 4, 4, 4), (4, 4, 4, 4097), (4096, 4096, 4096, 2)])
+@pytest.mark.parametrize("L", [(1, 4, 4, 4), (4, 4, 4, 4097), (4096, 4096, 4096, 2), (512, 512, 512, 2)])
 def test_invalid_extents(L):
     assert q.qdpx_links_bytes(L, q.F64, q.LINK18) == 0
     assert q.lib().qdpx_last_error().decode()

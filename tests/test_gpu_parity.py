@@ -181,35 +181,41 @@ def test_ape_32x32x32x64_sampled(big_links, prec, fmt):
 
 
 # ------------------------------------------------ tuning and graph replay
-def test_geometries_are_bit_identical():
-    L = (8, 6, 4, 10)  # V = 1920: partial last tiles for every geometry
+@pytest.mark.parametrize("L", [(8, 6, 4, 10), (16, 8, 4, 8)], ids=["linear_groups", "brick_groups"])
+def test_geometries_are_bit_identical(L):
+    # (8, 6, 4, 10): V = 1920, 64-site groups of consecutive sites and partial
+    # last tiles; (16, 8, 4, 8): 16x4 bricks, where the t window reorders groups
     U = latgen.haar_links(L, 61)
     psi, phi = latgen.dirac_field(L, 62), latgen.dirac_field(L, 63)
     c = ctx()
     results_ape, results_shift = [], []
-    for block, ns, xcd in [(256, 1, 1), (256, 1, 0), (512, 2, 1), (256, 4, 0)]:
-        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd)
+    for block, ns, xcd, tw in [(256, 1, 1, 1), (256, 1, 0, 2), (512, 2, 1, 4), (256, 4, 0, 8)]:
+        if L[3] % tw:
+            tw = 2
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd, tw)
         results_ape.append(ape(L, U, q.F32, q.LINK12, 2))
-    for block, ns, xcd in [(256, 1, 1), (64, 8, 0), (128, 2, 1), (128, 4, 0)]:
-        q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, block, ns, xcd)
+    for block, ns, xcd, tw in [(256, 1, 1, 1), (64, 8, 0, 2), (128, 2, 1, 8), (128, 4, 0, 2)]:
+        if L[3] % tw:
+            tw = 1
+        q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, block, ns, xcd, tw)
         results_shift.append(shift(L, U, psi, phi, 0.3, q.F64, q.LINK18))
     for V, p in results_ape[1:]:
         assert np.array_equal(V, results_ape[0][0]) and np.array_equal(p, results_ape[0][1])
     for chi, n2 in results_shift[1:]:
         assert np.array_equal(chi, results_shift[0][0]) and n2 == results_shift[0][1]
-    q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, 256, 1, 1)
-    q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, 256, 1, 1)
+    q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, 256, 1, 1, 1)
+    q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, 256, 1, 1, 1)
 
 
 def test_tuner_picks_a_valid_geometry():
     c = q.Context(0)
     L = (8, 8, 8, 8)
     q.qdpx_tune(c, q.OP_APE, L, q.F32, q.LINK12)
-    b, n, x = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
-    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1)
+    b, n, x, tw = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
+    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1) and tw in (1, 2, 4, 8)
     q.qdpx_tune(c, q.OP_SHIFT, L, q.F64, q.LINK18)
-    b, n, x = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
-    assert b % 64 == 0 and n in (1, 2, 4, 8)
+    b, n, x, tw = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
+    assert b % 64 == 0 and n in (1, 2, 4, 8) and tw in (1, 2, 4, 8)
     c.close()
 
 
@@ -285,5 +291,5 @@ def test_validation_errors():
         q.qdpx_shift_chain(c, L, q.F64, q.LINK18, U, psi, None, 0.3, 0.1, 0, None, work)
     assert e.value.code == -1
     with pytest.raises(q.QdpxError) as e:
-        q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1)
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1, 1)
     assert e.value.code == -1
