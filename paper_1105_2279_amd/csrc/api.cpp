@@ -381,12 +381,15 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
 }
 
 // ------------------------------------------------------------------ batched
-// Workspace: [counters: 2 + n_lat * (kBatchMaxSteps+1) uint32, 256-aligned]
+// Workspace: [counters for up to kBatchMaxSteps + 1 phases, 256-aligned]
 // then per lattice [ping-pong links][plaquette partials], each 256-aligned.
 static const int kBatchMaxSteps = 1024;
 static const int kBatchMaxLattices = 4096;
 
-static size_t batched_counter_bytes(int n_lat) { return round256(sizeof(unsigned) * (2 + (size_t)n_lat * (kBatchMaxSteps + 1))); }
+static size_t batched_counter_bytes(int n_lat) {
+    (void)n_lat;
+    return round256(sizeof(unsigned) * (size_t)batched_counter_words(kBatchMaxSteps + 1));
+}
 
 static size_t batched_lattice_bytes(const qdpx_geom *g, qdpx_prec prec, qdpx_linkfmt fmt) {
     const Geo geo = make_geo(g->L);

@@ -1,14 +1,20 @@
 // Persistent batched APE smearing: many independent lattices of any extents,
 // n_steps APE steps each and the final plaquettes, in one launch.
 //
-// Work items are (phase, lattice, chunk of 64-site groups); phases 0..n-1 are
-// APE steps and phase n (when plaquettes are requested) the plaquette of the
-// output.  A global ticket counter hands items out phase-major, so every item
-// a block waits for was handed to a running block earlier: the wait chain
-// always ends and no co-residency assumption is needed.  Per (lattice, phase)
-// completion counters act as the barrier between the phases of one lattice.
-// Every wait is bounded; on timeout the block records the failure in the
-// status word and leaves, so the grid always drains.
+// The launch walks through phases: the n APE steps, then (with plaquettes)
+// the plaquette traces of the outputs and the per-lattice finalisation.
+// Within a phase, work items (lattice, chunk of 64-site groups) are handed out
+// by that phase's ticket counter, so lattices of any size share the GPU.
+// When a block finds the phase's tickets exhausted it publishes how many items
+// it finished (one release) and waits until the phase's completion counter
+// reaches the item count (one acquire).  Every item it waits for was already
+// taken by a running block, so the wait always ends and no co-residency
+// assumption is needed.  Fencing once per block and phase, rather than per
+// item, matters on the multi-XCD MI355X: an agent-scope acquire invalidates
+// the XCD's L2, and per-item acquires kept wiping the neighbour links that
+// the other blocks of the XCD were reusing.  Every wait is bounded; on
+// timeout the block records the failure in the status word and leaves, so
+// the grid always drains.
 #include "ape_device.hpp"
 #include "qdpx_impl.hpp"
 #include "reduce_device.hpp"
@@ -23,91 +29,96 @@ __global__ void __launch_bounds__(256) k_batched_init(unsigned *__restrict__ cou
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) counters[i] = 0u;
 }
 
+// Reduce lattice L's plaquette partials exactly as the two finalisation
+// kernels of the single-lattice path do.
+__device__ void batched_finalize(const BatchLat &L, double *out, double *lds, double (*stage)[kBatchMaxStage]) {
+    const int n = 4 * L.ngroups;
+    const int nb = (n + kFinPerBlock - 1) / kFinPerBlock;
+    double res[2];
+    for (int comp = 0; comp < 2; ++comp) {
+        for (int b = 0; b < nb; ++b) {
+            const double v = fin_stage_a(L.partials + (int64_t)comp * n, n, b, lds);
+            if (threadIdx.x == 0) stage[comp][b] = v;
+        }
+        __syncthreads();
+        res[comp] = fin_stage_b(stage[comp], nb, lds);
+    }
+    if (threadIdx.x == 0) fin_write(res, 1, (double)L.g.V, out);
+}
+
 template <typename R, int NR>
 __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a) {
     __shared__ unsigned s_ticket;
-    __shared__ int s_flag;
+    __shared__ int s_ok;
     __shared__ double lds[kReduceBlock / 64];
     __shared__ double stage[2][kBatchMaxStage];
     // mu is wave-uniform; readfirstlane lets the compiler keep it in an SGPR
     const int mu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const unsigned total = (unsigned)a.items_per_phase * (unsigned)a.n_phases;
-    unsigned *ticket = a.counters, *status = a.counters + 1, *done = a.counters + 2;
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
-        __syncthreads();
-        const unsigned t = s_ticket;
-        if (t >= total) return;  // block-uniform
-        const int phase = (int)(t / (unsigned)a.items_per_phase);
-        const int r = (int)(t - (unsigned)phase * (unsigned)a.items_per_phase);
-        int lo = 0, hi = a.n_lat - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.lats[mid].item_base <= r) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchLat &L = a.lats[lo];  // read in place: a private copy would live in scratch
-        const int item = r - L.item_base;
-        if (phase > 0) {
-            if (threadIdx.x == 0) {
-                const unsigned *d = done + lo * a.n_phases + (phase - 1);
-                unsigned spins = 0;
-                int ok = 1;
-                while (__hip_atomic_load(d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)L.nitems) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > a.spin_limit) {
-                        ok = 0;
-                        break;
-                    }
-                }
-                if (!ok) atomicOr(status, 1u);
-                s_flag = ok;
-            }
+    const int nph = a.n_phases + (a.plaq ? 1 : 0);  // steps, plaquette traces, finalisation
+    unsigned *status = a.counters + 1;
+    unsigned *tickets = a.counters + 2;
+    unsigned *done = a.counters + 2 + nph;
+    for (int phase = 0; phase < nph; ++phase) {
+        const bool fin = a.plaq && phase == nph - 1;
+        const unsigned nitems = fin ? (unsigned)a.n_lat : (unsigned)a.items_per_phase;
+        unsigned mine = 0;
+        for (;;) {
+            if (threadIdx.x == 0) s_ticket = atomicAdd(tickets + phase, 1u);
             __syncthreads();
-            if (!s_flag) return;  // block-uniform; dependants time out in turn
-            __threadfence();      // acquire the previous phase's links
-        }
-        // phase p reads the output of step p-1: step k writes to U_out when
-        // n_steps-1-k is even, else to the lattice's scratch links.
-        const void *src = (phase == 0) ? L.in : ((((a.n_steps - phase) & 1) == 0) ? L.out : L.tmp);
-        void *dst = (phase < a.n_steps) ? ((((a.n_steps - 1 - phase) & 1) == 0) ? L.out : L.tmp) : nullptr;
-        const LinksRO<R, NR> U{(const vec2_t<R> *)src, L.g.S};
-        const LinksWO<R, NR> O{(vec2_t<R> *)dst, L.g.S};
-        const int g0 = item * a.group_chunk;
-        const int g1 = min(g0 + a.group_chunk, L.ngroups);
-        if (phase < a.n_steps) {
+            const unsigned r = __builtin_amdgcn_readfirstlane(s_ticket);
+            __syncthreads();  // s_ticket is rewritten by the next iteration
+            if (r >= nitems) break;
+            ++mine;
+            if (fin) {
+                batched_finalize(a.lats[r], a.plaq + 3 * r, lds, stage);
+                continue;
+            }
+            int lo = 0, hi = a.n_lat - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.lats[mid].item_base <= (int)r) lo = mid;
+                else hi = mid - 1;
+            }
+            const BatchLat &L = a.lats[lo];  // read in place: a private copy would live in scratch
+            const int item = (int)r - L.item_base;
+            // step p reads the output of step p-1: step k writes to U_out when
+            // n_steps-1-k is even, else to the lattice's scratch links
+            const void *src = (phase == 0) ? L.in : ((((a.n_steps - phase) & 1) == 0) ? L.out : L.tmp);
+            void *dst = (phase < a.n_steps) ? ((((a.n_steps - 1 - phase) & 1) == 0) ? L.out : L.tmp) : nullptr;
+            const LinksRO<R, NR> U{(const vec2_t<R> *)src, L.g.S};
+            const LinksWO<R, NR> O{(vec2_t<R> *)dst, L.g.S};
+            const int g0 = item * a.group_chunk;
+            const int g1 = min(g0 + a.group_chunk, L.ngroups);
+            if (phase < a.n_steps) {
 #pragma unroll 1
-            for (int grp = g0; grp < g1; ++grp) ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, nullptr, grp, mu, lane);
-        } else {
+                for (int grp = g0; grp < g1; ++grp)
+                    ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, nullptr, grp, mu, lane);
+            } else {
 #pragma unroll 1
-            for (int grp = g0; grp < g1; ++grp)
-                ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, L.partials, grp, mu, lane);
+                for (int grp = g0; grp < g1; ++grp)
+                    ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, L.partials, grp, mu, lane);
+            }
         }
+        if (phase + 1 == nph) break;
         __syncthreads();  // every wave of the block has issued its stores
         if (threadIdx.x == 0) {
-            __threadfence();  // release this item's links / partials device-wide
-            const unsigned prev = atomicAdd(done + lo * a.n_phases + phase, 1u);
-            s_flag = (a.plaq != nullptr && phase == a.n_phases - 1 && prev + 1 == (unsigned)L.nitems);
+            __threadfence();  // release this block's links / partials of the phase device-wide
+            atomicAdd(done + phase, mine);
+            unsigned spins = 0;
+            int ok = 1;
+            while (__hip_atomic_load(done + phase, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < nitems) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > a.spin_limit) {
+                    ok = 0;
+                    break;
+                }
+            }
+            if (!ok) atomicOr(status, 1u);
+            s_ok = ok;
         }
         __syncthreads();
-        if (s_flag) {
-            // Last item of this lattice's plaquette phase: reduce its partials
-            // exactly as the two finalisation kernels of the single-lattice path.
-            __threadfence();
-            const int n = 4 * L.ngroups;
-            const int nb = (n + kFinPerBlock - 1) / kFinPerBlock;
-            double res[2];
-            for (int comp = 0; comp < 2; ++comp) {
-                for (int b = 0; b < nb; ++b) {
-                    const double v = fin_stage_a(L.partials + (int64_t)comp * n, n, b, lds);
-                    if (threadIdx.x == 0) stage[comp][b] = v;
-                }
-                __syncthreads();
-                res[comp] = fin_stage_b(stage[comp], nb, lds);
-            }
-            if (threadIdx.x == 0) fin_write(res, 1, (double)L.g.V, a.plaq + 3 * lo);
-        }
-        __syncthreads();  // s_ticket and s_flag are rewritten next iteration
+        if (!s_ok) return;  // block-uniform
+        __threadfence();    // acquire the phase's results
     }
 }
 
@@ -125,8 +136,10 @@ int batched_resident_blocks(int prec, int nrows) {
     return cus * std::max(per_cu, 1);
 }
 
+int batched_counter_words(int max_phases) { return 2 + 2 * (max_phases + 1); }
+
 hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int grid, hipStream_t st) {
-    const int ncount = 2 + a.n_lat * a.n_phases;
+    const int ncount = batched_counter_words(a.n_phases);
     k_batched_init<<<std::min((ncount + 255) / 256, 1024), 256, 0, st>>>(a.counters, ncount);
     if (prec == 0) k_ape_batched<double, 3><<<grid, 256, 0, st>>>(a);
     else if (nrows == 3) k_ape_batched<float, 3><<<grid, 256, 0, st>>>(a);

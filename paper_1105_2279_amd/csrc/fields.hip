@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 M3<R> u;
-                U.full(mu, s, u);
+                U.full_stream(mu, s, u);  // the shift expression reads each link once
                 const int f = hop_fwd(g, s, x.c[mu], mu);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp) {
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
                 for (int cc = 0; cc < 3; ++cc) {
                     Cx<R> v = acc[sp][cc];
                     if (phi.p) {
-                        const Cx<R> f = phi.ld(sp, cc, s);
+                        const Cx<R> f = phi.ld_stream(sp, cc, s);
                         v.re = fma(a, f.re, v.re);
                         v.im = fma(a, f.im, v.im);
                     }

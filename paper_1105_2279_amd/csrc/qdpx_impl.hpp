@@ -64,14 +64,14 @@ struct BatchLat {
     void *tmp;         // ping-pong links in the workspace (n_steps >= 2)
     double *partials;  // 2 * 4 * ngroups plaquette partials in the workspace
     int ngroups;       // 64-site groups
-    int nitems;        // work items per phase
+    int nitems;        // work items per phase (chunks of groups)
     int item_base;     // index of this lattice's first item within a phase
     int pad;
 };
 
 struct BatchArgs {
     const BatchLat *lats;  // device table [n_lat]
-    unsigned *counters;    // [0] ticket, [1] status, [2..] done[n_lat][n_phases]
+    unsigned *counters;    // [1] status, then per phase a ticket and a completion counter
     double *plaq;          // nullable, [n_lat][3]
     double c1, c2;
     int n_lat, n_steps, n_phases, items_per_phase, group_chunk;
@@ -79,6 +79,7 @@ struct BatchArgs {
 };
 
 int batched_max_stage_groups();
+int batched_counter_words(int max_phases);
 int batched_resident_blocks(int prec, int nrows);
 hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int grid, hipStream_t st);
 

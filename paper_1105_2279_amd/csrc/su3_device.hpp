@@ -101,6 +101,20 @@ template <typename R> struct Cx { R re, im; };
 
 template <typename R> __device__ __forceinline__ Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
 
+// Streaming (non-temporal) access to one complex element: the builtins need a
+// native two-wide vector type.
+template <typename R> using nv2_t = R __attribute__((ext_vector_type(2)));
+template <typename R> __device__ __forceinline__ Cx<R> load_stream(const void *addr) {
+    const nv2_t<R> v = __builtin_nontemporal_load((const nv2_t<R> *)addr);
+    return Cx<R>{v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void store_stream(void *addr, R re, R im) {
+    nv2_t<R> v;
+    v.x = re;
+    v.y = im;
+    __builtin_nontemporal_store(v, (nv2_t<R> *)addr);
+}
+
 // acc += a * b
 template <typename R> __device__ __forceinline__ void cmac(Cx<R> &acc, const Cx<R> &a, const Cx<R> &b) {
     acc.re = fma(a.re, b.re, acc.re);
@@ -160,6 +174,18 @@ template <typename R, int NR> struct LinksRO {
         const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
+    __device__ __forceinline__ Cx<R> ld_stream(int mu, int a, int b, int s) const {
+        const vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
+        return load_stream<R>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+    }
+    // full link read once per site (no neighbour reuse): streamed
+    __device__ __forceinline__ void full_stream(int mu, int s, M3<R> &m) const {
+#pragma unroll
+        for (int a = 0; a < NR; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m.e[a][b] = ld_stream(mu, a, b, s);
+        if constexpr (NR == 2) rebuild_row2(m);
+    }
     __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -184,11 +210,10 @@ template <typename R, int NR> struct LinksWO {
     vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ void st(int mu, int a, int b, int s, R re, R im) const {
-        vec2_t<R> v;
-        v.x = re;
-        v.y = im;
         vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
-        *(vec2_t<R> *)((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>)) = v;
+        // outputs are never re-read by the kernel that writes them: stream
+        // them past the caches so L2 keeps the neighbour links
+        store_stream<R>((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>), re, im);
     }
 };
 
@@ -202,16 +227,18 @@ template <typename R> struct FermRO {
         const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
+    // a field read once per site (no neighbour reuse): stream it
+    __device__ __forceinline__ Cx<R> ld_stream(int sp, int c, int s) const {
+        const vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
+        return load_stream<R>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+    }
 };
 template <typename R> struct FermWO {
     vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ void st(int sp, int c, int s, const Cx<R> &z) const {
-        vec2_t<R> v;
-        v.x = z.re;
-        v.y = z.im;
         vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
-        *(vec2_t<R> *)((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>)) = v;
+        store_stream<R>((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>), z.re, z.im);
     }
 };
 
