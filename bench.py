@@ -116,10 +116,13 @@ def main():
                                q.qdpx_tune_get(ctx, q.OP_APE, L, prec, fmt)))
         log(f"tuned APE {name}: {tuned[name]}")
 
+    works = {}
+
     def make_call(name, with_plaq=True, n=N_APE):
         prec, fmt = paths[name]
         out = q.alloc_links(L, prec, fmt, dev)
         work = q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev)
+        works[name] = work
         plaq = torch.zeros(3 * (n + 1), dtype=torch.float64, device=dev) if with_plaq else None
         src = dev_links[name]
 
@@ -145,19 +148,36 @@ def main():
 
     results = {}
     # ---------------------------------------------------------------- headline
+    # One step = one qdpx_ape_smear call (10 APE steps + 11 plaquettes), its
+    # ~32 kernel launches recorded once into a HIP graph and replayed.
     head, head_out, head_plaq = make_call("f32_12")
-    for _ in range(args.warmup):
-        head()
+    head_work = works["f32_12"]
+    head()
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps of {N_APE} FP32-12 APE steps + plaquettes")
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(stream)
+    with torch.cuda.graph(graph, stream=cap):
+        prec_h, fmt_h = paths["f32_12"]
+        q.qdpx_ape_smear(ctx, L, prec_h, fmt_h, dev_links["f32_12"], head_out, ALPHA, N_APE, head_plaq,
+                         head_work, cap)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps of {N_APE} FP32-12 APE steps + plaquettes (graph replay)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        head()
+        graph.replay()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     value = 4.0 * V * N_APE * args.steps / elapsed
     log(f"headline: {value / 1e9:.2f} G link-updates/s, {1e3 * elapsed / args.steps:.3f} ms/step")
+    # the same calls launched eagerly, for comparison
+    for _ in range(2):
+        head()
+    ms_eager = time_calls(torch, head, args.steps, stream) / args.steps
+    log(f"eager launches: {ms_eager:.3f} ms/step")
 
     # ---------------------------------------- per-kernel timing of each path
     kernel = {}
@@ -170,11 +190,19 @@ def main():
         kernel[name] = per_kernel_s
         log(f"{name}: APE kernel {per_kernel_s * 1e6:.1f} us")
         if name != "f32_12":
-            call_p, _, _ = make_call(name, with_plaq=True)
-            call_p()
-            ms = time_calls(torch, call_p, reps, stream)
+            # same timed step as the headline (graph replay), other link format
+            prec, fmt = paths[name]
+            _, out_p, plaq_p = make_call(name, with_plaq=True)
+            work_p = works[name]
+            gr = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(stream)
+            with torch.cuda.graph(gr, stream=cs):
+                q.qdpx_ape_smear(ctx, L, prec, fmt, dev_links[name], out_p, ALPHA, N_APE, plaq_p, work_p, cs)
+            gr.replay()
+            ms = time_calls(torch, gr.replay, reps, stream)
             results[name] = 4.0 * V * N_APE * reps / (ms / 1e3)
-            log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s with plaquettes")
+            log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s with plaquettes (graph replay)")
     results["f32_12"] = value
 
     def roof(name):
@@ -203,6 +231,8 @@ def main():
         "fp64_18_link_updates_per_s": results["f64_18"],
         "fp32_18_link_updates_per_s": results["f32_18"],
         "speedup_fp32_12_vs_fp64": results["f32_12"] / results["f64_18"],
+        "f32_12_eager_ms_per_step": ms_eager,
+        "f32_12_eager_link_updates_per_s": 4.0 * V * N_APE / (ms_eager / 1e3),
         "ape_kernel_roofline": {k: roof(k) for k in paths},
         "tuned_launch": tuned,
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],

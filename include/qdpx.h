@@ -220,9 +220,10 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
  * QDPX_ECAPTURE on a capturing stream.  Later calls, and replays of a graph
  * that captured one, reuse the table and only enqueue the two kernels.
  * Links and plaquettes are identical, bit for bit, to qdpx_ape_smear on each
- * lattice with plaquettes requested.  The number of 64-site groups per work
- * item is set with qdpx_tune_set(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt,
- * 256, groups, 0) (default 16). */
+ * lattice with plaquettes requested.  Work items are runs of t-rows of one
+ * column (one brick of one z plane) of one lattice, queued per XCD by column;
+ * the run length is set with qdpx_tune_set(ctx, QDPX_OP_BATCHED, &geoms[0],
+ * prec, fmt, 256, rows, 0, 1) (default 1). */
 int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
                            qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out,
                            double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,

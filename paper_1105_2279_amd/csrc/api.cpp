@@ -189,7 +189,7 @@ static bool stream_capturing(hipStream_t st) {
 
 static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
     LaunchCfg c;
-    if (op == QDPX_OP_BATCHED) c.nsite = 16;  // 64-site groups per work item
+    if (op == QDPX_OP_BATCHED) c.nsite = 1;  // t-rows of one column per work item
     if (ctx) {
         TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
         auto it = ctx->tuned.find(k);
@@ -467,10 +467,11 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
 
     // groups per work item: tuned per (first lattice extents, precision, format)
     const int group_chunk = std::max(1, cfg_for(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt).nsite);
-    // host table
+    // host table: each lattice's groups as a (column, t-row) grid, columns
+    // dealt to the XCD queues by c % 8, items = runs of group_chunk rows
     std::vector<BatchLat> tab(n_lat);
     char *base = (char *)work + batched_counter_bytes(n_lat);
-    int64_t items = 0;
+    int64_t xtotal[kXcds] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int i = 0; i < n_lat; ++i) {
         BatchLat &L = tab[i];
         memset(&L, 0, sizeof L);
@@ -481,12 +482,25 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
         L.partials = (double *)(base + round256(lb[i]));
         base += batched_lattice_bytes(&geoms[i], prec, fmt);
         L.ngroups = (L.g.V + 63) / 64;
-        L.nitems = (L.ngroups + group_chunk - 1) / group_chunk;
-        L.item_base = (int)items;
-        items += L.nitems;
+        const int per_t = L.g.L[0] * L.g.L[1] * L.g.L[2];
+        if (L.g.bwl || per_t % 64 == 0) {
+            L.ncol = per_t / 64;  // bricks (or runs of 64 sites) of one t plane
+            L.nrow = L.g.L[3];
+        } else {
+            L.ncol = L.ngroups;
+            L.nrow = 1;
+        }
+        L.nchunk = (L.nrow + group_chunk - 1) / group_chunk;
+        for (int x = 0; x < kXcds; ++x) {
+            L.xbase[x] = (int)xtotal[x];
+            const int cols = L.ncol > x ? (L.ncol - x + kXcds - 1) / kXcds : 0;
+            xtotal[x] += (int64_t)cols * L.nchunk;
+        }
     }
+    int64_t items = 0;
+    for (int x = 0; x < kXcds; ++x) items += xtotal[x];
     const int n_phases = n_steps + (plaq ? 1 : 0);
-    if (items * n_phases >= (int64_t)1 << 31) return fail(QDPX_EUNSUPPORTED, "%s: too many work items", fn);
+    if (items >= (int64_t)1 << 31) return fail(QDPX_EUNSUPPORTED, "%s: too many work items", fn);
 
     BatchKey key;
     key.v = {(uint64_t)n_lat, (uint64_t)prec, (uint64_t)fmt, (uint64_t)(uintptr_t)work, (uint64_t)group_chunk};
@@ -521,11 +535,12 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
     a.n_steps = n_steps;
     a.n_phases = n_phases;
     a.items_per_phase = (int)items;
+    for (int x = 0; x < kXcds; ++x) a.xtotal[x] = (int)xtotal[x];
     a.group_chunk = group_chunk;
     a.spin_limit = spin_limit_from_env();
     const int resident = batched_resident_blocks(prec, nrows_of(fmt));
     if (resident <= 0) return fail(QDPX_EHIP, "%s: occupancy query failed", fn);
-    const int grid = (int)std::min<int64_t>(resident, items * n_phases);
+    const int grid = (int)std::min<int64_t>(resident, std::max<int64_t>(items, n_lat));
     QDPX_TRY_HIP(launch_ape_batched(a, prec, nrows_of(fmt), grid, st), fn);
     return QDPX_OK;
 }

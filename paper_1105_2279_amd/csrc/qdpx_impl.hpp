@@ -56,7 +56,14 @@ int plaquette_num_partials(const Geo &g);  // per component (2 components)
 hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st);
 
 // ---- batched.hip
-// One lattice of a batch (device table entry).
+// Number of XCDs of the MI355X: each has its own L2 and its own work queue.
+constexpr int kXcds = 8;
+
+// One lattice of a batch (device table entry).  Its 64-site groups form a
+// (column, t-row) grid, group = col + ncol * row, where a column is one
+// brick (or run of groups) of one z plane and rows step in t; see
+// batch_columns() on the host.  Column c belongs to the queue of XCD c % 8,
+// so a column's t neighbours are always handled, and cached, on one XCD.
 struct BatchLat {
     Geo g;
     const void *in;    // caller's input links
@@ -64,17 +71,19 @@ struct BatchLat {
     void *tmp;         // ping-pong links in the workspace (n_steps >= 2)
     double *partials;  // 2 * 4 * ngroups plaquette partials in the workspace
     int ngroups;       // 64-site groups
-    int nitems;        // work items per phase (chunks of groups)
-    int item_base;     // index of this lattice's first item within a phase
-    int pad;
+    int ncol, nrow;    // group grid
+    int nchunk;        // items per column (rows per item = group_chunk)
+    int xbase[kXcds];  // first item of this lattice in each XCD's queue
 };
 
 struct BatchArgs {
     const BatchLat *lats;  // device table [n_lat]
-    unsigned *counters;    // [1] status, then per phase a ticket and a completion counter
+    unsigned *counters;    // [1] status, then per phase 8 ticket counters and a completion counter
     double *plaq;          // nullable, [n_lat][3]
     double c1, c2;
-    int n_lat, n_steps, n_phases, items_per_phase, group_chunk;
+    int n_lat, n_steps, n_phases, group_chunk;
+    int xtotal[kXcds];     // items in each XCD's queue per phase
+    int items_per_phase;   // sum of xtotal
     unsigned spin_limit;
 };
 

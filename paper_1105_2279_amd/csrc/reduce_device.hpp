@@ -15,10 +15,11 @@ constexpr int kFinPerBlock = kReduceBlock * kFinChunk;
 // in order, then a fixed block tree.  Result valid in thread 0.
 __device__ __forceinline__ double fin_stage_a(const double *__restrict__ p, int n, int b, double *lds) {
     const int base = b * kFinPerBlock + (int)threadIdx.x * kFinChunk;
+    const auto *gp = gptr<double>(p);  // partials always live in global memory
     double v = 0.0;
 #pragma unroll
     for (int k = 0; k < kFinChunk; ++k)
-        if (base + k < n) v += p[base + k];
+        if (base + k < n) v += gp[base + k];
     return block_sum<kReduceBlock / 64>(v, lds);
 }
 

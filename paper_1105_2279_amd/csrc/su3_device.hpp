@@ -101,18 +101,28 @@ template <typename R> struct Cx { R re, im; };
 
 template <typename R> __device__ __forceinline__ Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
 
+// Every field lives in global memory.  Pointers that come out of a device
+// table are generic; converting them to the global address space lets the
+// compiler emit global (not flat) loads and stores.
+template <typename T> __device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const void *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T *gptr_w(void *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Streaming (non-temporal) access to one complex element: the builtins need a
 // native two-wide vector type.
 template <typename R> using nv2_t = R __attribute__((ext_vector_type(2)));
 template <typename R> __device__ __forceinline__ Cx<R> load_stream(const void *addr) {
-    const nv2_t<R> v = __builtin_nontemporal_load((const nv2_t<R> *)addr);
+    const nv2_t<R> v = __builtin_nontemporal_load(gptr<nv2_t<R>>(addr));
     return Cx<R>{v.x, v.y};
 }
 template <typename R> __device__ __forceinline__ void store_stream(void *addr, R re, R im) {
     nv2_t<R> v;
     v.x = re;
     v.y = im;
-    __builtin_nontemporal_store(v, (nv2_t<R> *)addr);
+    __builtin_nontemporal_store(v, gptr_w<nv2_t<R>>(addr));
 }
 
 // acc += a * b
@@ -171,7 +181,7 @@ template <typename R, int NR> struct LinksRO {
     // every load is one SGPR base + one 32-bit VGPR offset.
     __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
         const vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
-        const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
     __device__ __forceinline__ Cx<R> ld_stream(int mu, int a, int b, int s) const {
@@ -224,7 +234,7 @@ template <typename R> struct FermRO {
     int64_t S;
     __device__ __forceinline__ Cx<R> ld(int sp, int c, int s) const {
         const vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
-        const vec2_t<R> v = *(const vec2_t<R> *)((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
         return Cx<R>{v.x, v.y};
     }
     // a field read once per site (no neighbour reuse): stream it
