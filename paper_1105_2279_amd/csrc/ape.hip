@@ -13,7 +13,7 @@ namespace qdpx {
 template <typename R, int NR, int NS, int MODE>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
                                                   double c2, double *__restrict__ partials, int xcd, int tw) {
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mu = w & 3;
     const int gpb = blockDim.x >> 8;
@@ -22,7 +22,8 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
-        ape_group<R, NR, MODE>(g, U, out, c1, c2, partials, traverse(g, i, tw), mu, lane);
+        const int grp = xcd == 2 ? colwalk(g, i, gpb * NS) : traverse(g, i, tw);
+        ape_group<R, NR, MODE>(g, U, out, c1, c2, partials, grp, mu, lane);
     }
 }
 
@@ -34,10 +35,11 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     const int gpb = cfg.block / 256;
     const int per_block = gpb * cfg.nsite;
     const dim3 grid((groups + per_block - 1) / per_block);
+    const int xcd = launch_order(g, cfg, per_block);
 #define QDPX_APE_LAUNCH(R, NR, NS, M)                                                                          \
     k_ape_step<R, NR, NS, M><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},        \
                                                          LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,        \
-                                                         partials, cfg.xcd, cfg.tw)
+                                                         partials, xcd, cfg.tw)
 #define QDPX_APE_M(R, NR, NS)                                      \
     if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly);  \
     else if (mode == kApePlaq) QDPX_APE_LAUNCH(R, NR, NS, kApePlaq); \

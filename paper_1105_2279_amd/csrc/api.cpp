@@ -548,7 +548,7 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
 // ------------------------------------------------------------------- tuner
 static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (c.block < 64 || c.block > 1024 || (c.block % 64)) return false;
-    if (c.xcd != 0 && c.xcd != 1) return false;
+    if (c.xcd < 0 || c.xcd > 2) return false;
     if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
@@ -635,9 +635,9 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     const int ns_ape[] = {1, 2, 4};
     const int ns_shift[] = {1, 2, 4, 8};
     const int tws[] = {1, 2, 4, 8, 16};
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 3; ++x)
         for (int tw : tws) {
-            if (geom->L[3] % tw || (tw > 1 && g.bwl == 0)) continue;
+            if (geom->L[3] % tw || (tw > 1 && (g.bwl == 0 || x == 2))) continue;
             if (op == QDPX_OP_APE) {
                 for (int b : blocks_ape)
                     for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x, tw});

@@ -16,7 +16,7 @@ Geo make_geo(const int32_t L[4]) {
     g.st[3] = L[0] * L[1] * L[2];
     g.V = g.st[3] * L[3];
     g.S = ((int64_t)g.V + 255) / 256 * 256;
-    g.bwl = g.P = g.pbx = 0;
+    g.bwl = g.P = g.pbx = g.ncol = 0;
     if (L[0] % 16 == 0 && L[1] % 4 == 0) {
         g.bwl = 4;
         g.pbx = L[0] / 16;
@@ -26,7 +26,17 @@ Geo make_geo(const int32_t L[4]) {
         g.pbx = L[0] / 8;
         g.P = g.pbx * (L[1] / 8);
     }
+    if (g.bwl || g.st[3] % 64 == 0) g.ncol = g.st[3] / 64;
     return g;
+}
+
+// The block order a launch uses: the XCD column walk (mode 2) only where its
+// preconditions hold, else the identity order.
+int launch_order(const Geo &g, const LaunchCfg &cfg, int groups_per_block) {
+    if (cfg.xcd != 2) return cfg.xcd;
+    const int groups = (g.V + 63) / 64;
+    if (g.ncol && g.ncol % 8 == 0 && groups % (8 * groups_per_block) == 0) return 2;
+    return 0;
 }
 
 // ------------------------------------------------------------ pack / unpack
@@ -145,7 +155,7 @@ template <typename R, int NR, int MODE, int NS>
 __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
                                                 FermWO<R> out, double *__restrict__ partials, int xcd, int tw) {
     const int nwb = blockDim.x >> 6;
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int ngroups = num_groups(g);
@@ -153,7 +163,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * nwb + wave) * NS + j;
         if (i >= ngroups) return;  // whole wave leaves together
-        const int grp = traverse(g, i, tw);
+        const int grp = xcd == 2 ? colwalk(g, i, nwb * NS) : traverse(g, i, tw);
         double n2 = 0.0;
         Site x;
         if (group_site(g, grp, lane, x)) {
@@ -217,11 +227,12 @@ static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, cons
     const int groups = (g.V + 63) / 64;
     const int per_block = (cfg.block / 64) * cfg.nsite;  // 64-site groups per block
     const dim3 grid((groups + per_block - 1) / per_block);
+    const int xcd = launch_order(g, cfg, per_block);
     switch (cfg.nsite) {
-    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
-    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
-    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
-    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, cfg.xcd, cfg.tw); break;
+    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
     }
 }
 

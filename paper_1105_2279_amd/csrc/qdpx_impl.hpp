@@ -13,7 +13,7 @@ namespace qdpx {
 struct LaunchCfg {
     int block = 256;  // threads per block, multiple of 64
     int nsite = 1;    // consecutive 64-site groups handled per wave
-    int xcd = 1;      // 1: XCD-contiguous tile mapping, 0: identity
+    int xcd = 1;      // 0: identity, 1: XCD-contiguous tile ranges, 2: XCD column walk
     int tw = 1;       // t planes walked together (brick mapping only; must divide Lt)
 };
 
@@ -23,6 +23,7 @@ struct LaunchCfg {
 constexpr int kReduceBlock = 256;
 
 Geo make_geo(const int32_t L[4]);
+int launch_order(const Geo &g, const LaunchCfg &cfg, int groups_per_block);
 
 // ---- fields.hip
 hipError_t launch_pack_links(const Geo &g, int prec, int nrows, const double *aos, void *soa, hipStream_t st);

@@ -29,6 +29,7 @@ struct Geo {
     int bwl;    // log2 of the brick width, 0 for the linear mapping
     int P;      // bricks per xy plane
     int pbx;    // bricks along x
+    int ncol;   // groups per t plane when every group lies in one t plane, else 0
     int64_t S;  // SoA component stride (elements)
 };
 
@@ -82,6 +83,19 @@ __device__ __forceinline__ int traverse(const Geo &g, int i, int tw) {
     const int plane = g.P * g.L[2];
     const int pz = rest % plane, tc = rest / plane;
     return pz + plane * (tc * tw + tin);
+}
+
+// Launch order -> group, XCD column walk.  Blocks are dispatched to the 8
+// XCDs round-robin (block b runs on XCD b % 8).  With m groups per block, the
+// groups of XCD x are the columns c = x (mod 8) of the (column, t) grid
+// group = c + ncol * t, walked through t: every t neighbour a block needs is
+// handled on the same XCD just before or after it.  Requires ncol % 8 == 0
+// and num_groups % (8 m) == 0 (checked on the host).  A bijection.
+__device__ __forceinline__ int colwalk(const Geo &g, int i, int m) {
+    const int blk = i / m, within = i - blk * m;
+    const int x = blk & 7, jj = (blk >> 3) * m + within;
+    const int k = jj / g.L[3], t = jj - k * g.L[3];
+    return (x + 8 * k) + g.ncol * t;
 }
 
 __device__ __forceinline__ int hop_fwd(const Geo &g, int s, int cmu, int mu) {

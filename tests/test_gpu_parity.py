@@ -184,17 +184,19 @@ def test_ape_32x32x32x64_sampled(big_links, prec, fmt):
 @pytest.mark.parametrize("L", [(8, 6, 4, 10), (16, 8, 4, 8)], ids=["linear_groups", "brick_groups"])
 def test_geometries_are_bit_identical(L):
     # (8, 6, 4, 10): V = 1920, 64-site groups of consecutive sites and partial
-    # last tiles; (16, 8, 4, 8): 16x4 bricks, where the t window reorders groups
+    # last tiles; (16, 8, 4, 8): 16x4 bricks, where the t window and the XCD
+    # column walk reorder groups
     U = latgen.haar_links(L, 61)
     psi, phi = latgen.dirac_field(L, 62), latgen.dirac_field(L, 63)
     c = ctx()
     results_ape, results_shift = [], []
-    for block, ns, xcd, tw in [(256, 1, 1, 1), (256, 1, 0, 2), (512, 2, 1, 4), (256, 4, 0, 8)]:
+    for block, ns, xcd, tw in [(256, 1, 1, 1), (256, 1, 0, 2), (512, 2, 1, 4), (256, 4, 0, 8), (256, 2, 2, 1),
+                               (512, 1, 2, 1)]:
         if L[3] % tw:
             tw = 2
         q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd, tw)
         results_ape.append(ape(L, U, q.F32, q.LINK12, 2))
-    for block, ns, xcd, tw in [(256, 1, 1, 1), (64, 8, 0, 2), (128, 2, 1, 8), (128, 4, 0, 2)]:
+    for block, ns, xcd, tw in [(256, 1, 1, 1), (64, 8, 0, 2), (128, 2, 1, 8), (128, 4, 0, 2), (128, 2, 2, 1)]:
         if L[3] % tw:
             tw = 1
         q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, block, ns, xcd, tw)
