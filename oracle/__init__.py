@@ -70,6 +70,9 @@ def lib():
         h.oracle_ape_links.argtypes = [_I, _D, ctypes.c_double, ctypes.c_long, _L, _I, _D]
         h.oracle_ape_links.restype = ctypes.c_long
         h.oracle_plaquette.argtypes = [_I, _D, _D]
+        h.oracle_shift_sites.argtypes = [_I, _D, _D, _D, ctypes.c_double, ctypes.c_long, _L, _D]
+        h.oracle_hop.argtypes = [_I, _D, _D, ctypes.c_uint, _D]
+        h.oracle_jacobi_smear.argtypes = [_I, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_uint]
         _lib = h
     return _lib
 
@@ -196,3 +199,33 @@ def plaquette(U):
     out = np.zeros(3, dtype=np.float64)
     lib().oracle_plaquette(_extents(U), _dp(U), _dp(out))
     return out
+
+
+def shift_sites(U, psi, phi, a, sites):
+    """chi at the given flat sites only; (n, 4, 3)."""
+    U, psi = _c(U), _c(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((sites.size, 4, 3), dtype=np.complex128)
+    phi_p = None
+    if phi is not None:
+        phi = _c(phi)
+        phi_p = _dp(phi)
+    lib().oracle_shift_sites(_extents(U), _dp(U), _dp(psi), phi_p, float(a), sites.size, sites.ctypes.data_as(_L),
+                             _dp(out))
+    return out
+
+
+def hop(U, psi, mask=0xF):
+    """(H psi)(x) = sum_{mu in mask} [U_mu(x) psi(x+mu) + U_mu(x-mu)^dag psi(x-mu)]."""
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    lib().oracle_hop(_extents(U), _dp(U), _dp(psi), int(mask), _dp(out))
+    return out
+
+
+def jacobi_smear(U, chi, kappa, n_iter, norm=1.0, mask=0xF):
+    """s0 = chi; n_iter times {psi = chi; chi = s0 + kappa H psi}; chi / norm."""
+    U = _c(U)
+    chi = _c(chi).copy()
+    lib().oracle_jacobi_smear(_extents(U), _dp(U), _dp(chi), float(kappa), int(n_iter), float(norm), int(mask))
+    return chi

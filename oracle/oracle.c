@@ -24,6 +24,8 @@
  *     hopping term of the smearing operator K in section 7.
  *   - chi = sum_mu U_mu(x) psi(x+mu) + a phi(x): the forward hop summed over
  *     mu plus the axpy of expression E_3 (section 7); a*phi is added once.
+ *   - Jacobi smearing: the hop of K in both directions summed over the
+ *     smeared directions, iterated as the paper's listing does (section 7).
  *   - The APE step (staple sum, combination with weight alpha, row
  *     Gram-Schmidt reunitarisation) and the plaquette are not in the paper;
  *     they follow the workload definition of one APE step on a periodic
@@ -188,9 +190,28 @@ void oracle_set_num_threads(int n)
 /* shift expression                                                    */
 /* ------------------------------------------------------------------ */
 
-/* chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x)   (phi may be NULL).
- * U acts on colour and is the identity in spin.  If norm2 is not NULL it
- * receives sum over sites, spins and colours of |chi|^2. */
+/* chi at one site: sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x) (phi may be NULL).
+ * U acts on colour and is the identity in spin. */
+static void shift_site(const lat *g, const double *U, const double *psi, const double *phi, double a, long s,
+                       cplx acc[4][3])
+{
+    for (int sp = 0; sp < 4; ++sp)
+        for (int c = 0; c < 3; ++c) acc[sp][c] = c_make(0.0, 0.0);
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3 u = load_link(U, s, mu);
+        long fwd = hop(g, s, mu, +1);
+        for (int sp = 0; sp < 4; ++sp)
+            for (int ca = 0; ca < 3; ++ca)
+                for (int cb = 0; cb < 3; ++cb)
+                    acc[sp][ca] = c_add(acc[sp][ca], c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
+    }
+    if (phi)
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) acc[sp][c] = c_add(acc[sp][c], c_scale(a, load_fermion(phi, s, sp, c)));
+}
+
+/* chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x) for every site.  If
+ * norm2 is not NULL it receives sum over sites, spins and colours of |chi|^2. */
 void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, const double *phi,
                            double a, double *chi, double *norm2)
 {
@@ -199,23 +220,12 @@ void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, con
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < g.V; ++s) {
         cplx acc[4][3];
-        for (int sp = 0; sp < 4; ++sp)
-            for (int c = 0; c < 3; ++c) acc[sp][c] = c_make(0.0, 0.0);
-        for (int mu = 0; mu < 4; ++mu) {
-            mat3 u = load_link(U, s, mu);
-            long fwd = hop(&g, s, mu, +1);
-            for (int sp = 0; sp < 4; ++sp)
-                for (int ca = 0; ca < 3; ++ca)
-                    for (int cb = 0; cb < 3; ++cb)
-                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
-        }
+        shift_site(&g, U, psi, phi, a, s, acc);
         double n2 = 0.0;
         for (int sp = 0; sp < 4; ++sp)
             for (int c = 0; c < 3; ++c) {
-                cplx v = acc[sp][c];
-                if (phi) v = c_add(v, c_scale(a, load_fermion(phi, s, sp, c)));
-                store_fermion(chi, s, sp, c, v);
-                n2 += c_abs2(v);
+                store_fermion(chi, s, sp, c, acc[sp][c]);
+                n2 += c_abs2(acc[sp][c]);
             }
         if (site_norm) site_norm[s] = n2;
     }
@@ -240,6 +250,79 @@ void oracle_shift_chain(const int *L, const double *U, double *psi, const double
         for (long i = 0; i < (long)nf; ++i) psi[i] = psi[i] - c * chi[i];
     }
     free(chi);
+}
+
+/* Shift expression evaluated only at the listed sites (for sampled checks of
+ * large lattices), written as double[n][4][3][2]. */
+void oracle_shift_sites(const int *L, const double *U, const double *psi, const double *phi, double a, long n,
+                        const long *sites, double *chi)
+{
+    lat g = lat_make(L);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        cplx acc[4][3];
+        shift_site(&g, U, psi, phi, a, sites[i], acc);
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) store_fermion(chi, i, sp, c, acc[sp][c]);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Jacobi smearing (the paper's application, section 7)                */
+/* ------------------------------------------------------------------ */
+
+/* Hopping term of the smearing operator K, over the directions in mask:
+ * (H psi)(x) = sum_{mu in mask} [ U_mu(x) psi(x+mu) + U_mu(x-mu)^dagger psi(x-mu) ]. */
+void oracle_hop(const int *L, const double *U, const double *psi, unsigned mask, double *out)
+{
+    lat g = lat_make(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        cplx acc[4][3];
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) acc[sp][c] = c_make(0.0, 0.0);
+        for (int mu = 0; mu < 4; ++mu) {
+            if (!((mask >> mu) & 1u)) continue;
+            mat3 uf = load_link(U, s, mu);
+            long fwd = hop(&g, s, mu, +1);
+            long bwd = hop(&g, s, mu, -1);
+            mat3 ub = load_link(U, bwd, mu);
+            for (int sp = 0; sp < 4; ++sp)
+                for (int ca = 0; ca < 3; ++ca)
+                    for (int cb = 0; cb < 3; ++cb) {
+                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(uf.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
+                        /* (U^dagger)_{ab} = conj(U_{ba}) */
+                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(c_conj(ub.e[cb][ca]), load_fermion(psi, bwd, sp, cb)));
+                    }
+        }
+        for (int sp = 0; sp < 4; ++sp)
+            for (int c = 0; c < 3; ++c) store_fermion(out, s, sp, c, acc[sp][c]);
+    }
+}
+
+/* Jacobi smearing as the listing of section 7 performs it:
+ *   s0 = chi;  repeat n_iter times { psi = chi; chi = s0 + kappa * H psi };  chi /= norm.
+ * chi is updated in place. */
+void oracle_jacobi_smear(const int *L, const double *U, double *chi, double kappa, int n_iter, double norm,
+                         unsigned mask)
+{
+    lat g = lat_make(L);
+    size_t nf = (size_t)g.V * 4 * 3 * 2;
+    double *s0 = (double *)malloc(sizeof(double) * nf);
+    double *psi = (double *)malloc(sizeof(double) * nf);
+    double *h = (double *)malloc(sizeof(double) * nf);
+    memcpy(s0, chi, sizeof(double) * nf);
+    for (int n = 0; n < n_iter; ++n) {
+        memcpy(psi, chi, sizeof(double) * nf);
+        oracle_hop(L, U, psi, mask, h);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < (long)nf; ++i) chi[i] = s0[i] + kappa * h[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < (long)nf; ++i) chi[i] = chi[i] / norm;
+    free(s0);
+    free(psi);
+    free(h);
 }
 
 /* ------------------------------------------------------------------ */

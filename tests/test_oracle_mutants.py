@@ -17,7 +17,7 @@ import pytest
 import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_FILES = ["tests/test_oracle_ape.py", "tests/test_oracle_shift.py"]
+PIN_FILES = ["tests/test_oracle_ape.py", "tests/test_oracle_shift.py", "tests/test_oracle_jacobi.py"]
 
 MUTANTS = {
     "upper_staple_wrong_shift": ("mat3 b = load_link(U, hop(g, s, nu, +1), mu);",
@@ -37,15 +37,21 @@ MUTANTS = {
                               "mat3 abc = m_mul(&ab, &dd);\n    mat3 p = m_mul(&abc, &cd);"),
     "plaquette_wrong_norm": ("out[0] = (ssum + tsum) / (18.0 * (double)g.V);",
                              "out[0] = (ssum + tsum) / (9.0 * (double)g.V);"),
-    "shift_backward": ("long fwd = hop(&g, s, mu, +1);", "long fwd = hop(&g, s, mu, -1);"),
+    "shift_backward": ("long fwd = hop(g, s, mu, +1);", "long fwd = hop(g, s, mu, -1);"),
     "shift_dagger_link": ("c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb))",
                           "c_mul(c_conj(u.e[cb][ca]), load_fermion(psi, fwd, sp, cb))"),
-    "axpy_per_direction": ("v = c_add(v, c_scale(a, load_fermion(phi, s, sp, c)));",
-                           "v = c_add(v, c_scale(4.0 * a, load_fermion(phi, s, sp, c)));"),
+    "axpy_per_direction": ("acc[sp][c] = c_add(acc[sp][c], c_scale(a, load_fermion(phi, s, sp, c)));",
+                           "acc[sp][c] = c_add(acc[sp][c], c_scale(4.0 * a, load_fermion(phi, s, sp, c)));"),
     "chain_wrong_sign": ("psi[i] = psi[i] - c * chi[i];", "psi[i] = psi[i] + c * chi[i];"),
     "hop_wrong_axis": ("c[mu] = ((c[mu] + step) % g->L[mu] + g->L[mu]) % g->L[mu];",
                        "c[(mu + 1) % 4] = ((c[(mu + 1) % 4] + step) % g->L[(mu + 1) % 4]"
                        " + g->L[(mu + 1) % 4]) % g->L[(mu + 1) % 4];"),
+    "hop_backward_no_dagger": ("c_mul(c_conj(ub.e[cb][ca]), load_fermion(psi, bwd, sp, cb))",
+                               "c_mul(ub.e[ca][cb], load_fermion(psi, bwd, sp, cb))"),
+    "hop_backward_wrong_link_site": ("mat3 ub = load_link(U, bwd, mu);", "mat3 ub = load_link(U, s, mu);"),
+    "jacobi_extra_iteration": ("for (int n = 0; n < n_iter; ++n) {\n        memcpy(psi",
+                               "for (int n = 0; n <= n_iter; ++n) {\n        memcpy(psi"),
+    "jacobi_norm_multiplied": ("chi[i] = chi[i] / norm;", "chi[i] = chi[i] * norm;"),
     "norm_drops_imag": ("static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }",
                         "static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im * 0.0 + 0.0 * a.re; }"),
 }
