@@ -279,6 +279,7 @@ def main():
     if not args.no_extras:
         extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
         extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
+        extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -351,6 +352,75 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
         log(f"shift {name}: {t * 1e6:.1f} us, {gbs:.0f} GB/s")
         del Ud, pd, fd, chi, work
     return out
+
+
+# Jacobi smearing (section 7): flops per site and iteration as counted here:
+# 8 SU(3) x colour-vector products per spin component (4 x 8 x 66), the sum
+# of the 8 hop terms (7 x 12 complex adds) and chi = s0 + kappa h (12 x 4).
+JACOBI_FLOPS_SITE_ITER = 4 * 8 * 66 + 7 * 12 * 2 + 12 * 4  # 2328
+# Sustained GFLOPS of the whole smearing routine in the paper's Table 1
+# (GTX 480 GPU, Xeon E5507 CPU): context only, the flop convention and the
+# number of iterations are not stated there.
+JACOBI_PAPER_GFLOPS = {
+    (8, 8, 8, 16): {"sp_gpu": 1.64, "dp_gpu": 1.49},
+    (12, 12, 12, 24): {"sp_gpu": 6.53, "dp_gpu": 4.41},
+    (16, 16, 16, 32): {"sp_gpu": 11.86, "dp_gpu": 6.26},
+    (20, 20, 20, 40): {"sp_gpu": 16.56, "dp_gpu": 7.51},
+    (24, 24, 24, 48): {"sp_gpu": 19.09, "dp_gpu": 7.91},
+    (32, 32, 32, 64): {"sp_gpu": 21.31, "dp_gpu": None},
+}
+N_JACOBI = 20
+KAPPA_JACOBI = 0.21
+
+
+def jacobi_extras(torch, q, ctx, dev, stream, latgen):
+    """The whole Jacobi routine (copy, N_JACOBI fused hop+axpy iterations,
+    division by the norm) on the lattices of the paper's Table 1, FP32 with
+    12-real and 18-real links and FP64, each call replayed from a HIP graph;
+    plus the hop kernel alone at 32^3x64 against the HBM roofline."""
+    out = {}
+    paths = (("sp_f32_12", q.F32, q.LINK12, 48, 96), ("sp_f32_18", q.F32, q.LINK18, 72, 96),
+             ("dp_f64_18", q.F64, q.LINK18, 144, 192))
+    for L, paper in JACOBI_PAPER_GFLOPS.items():
+        V = latgen.volume(L)
+        U = latgen.haar_links(L, 3000 + L[0])
+        chi = latgen.dirac_field(L, 3001 + L[0])
+        row = {"paper_gtx480_gflops": paper}
+        for name, prec, fmt, link_b, ferm_b in paths:
+            Ud = q.links_to_device(ctx, L, U, prec, fmt, dev)
+            cd = q.fermion_to_device(ctx, L, chi, prec, dev)
+            work = q.alloc_workspace(q.OP_JACOBI, L, prec, fmt, N_JACOBI, dev)
+            q.qdpx_tune(ctx, q.OP_JACOBI, L, prec, fmt)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(stream)
+            with torch.cuda.graph(g, stream=s):
+                q.qdpx_jacobi_smear(ctx, L, prec, fmt, Ud, cd, KAPPA_JACOBI, N_JACOBI, 1.0, 0xF, work, s)
+            g.replay()
+            reps = 10
+            ms = time_calls(torch, g.replay, reps, stream) / reps
+            gflops = JACOBI_FLOPS_SITE_ITER * V * N_JACOBI / (ms / 1e3) / 1e9
+            row[name] = {"ms_per_call": round(ms, 4), "gflops": round(gflops, 1),
+                         "tuned_launch": q.qdpx_tune_get(ctx, q.OP_JACOBI, L, prec, fmt)}
+            if L == (32, 32, 32, 64):
+                h = q.alloc_fermion(L, prec, dev)
+
+                def hop():
+                    q.qdpx_eval_hop(ctx, L, prec, fmt, Ud, cd, h, 0xF, stream)
+
+                hop()
+                t = time_calls(torch, hop, 20, stream) / 20 / 1e3
+                # compulsory bytes: 4 links, psi, out (the iteration adds s0)
+                gbs = (4 * link_b + 2 * ferm_b) * V / t / 1e9
+                row[name]["hop_kernel"] = {"us": round(t * 1e6, 2), "hbm_gbs_algorithmic": round(gbs, 1),
+                                           "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+                del h
+            log(f"jacobi {L} {name}: {ms:.3f} ms / {N_JACOBI} iterations, {gflops:.0f} GFLOPS")
+            del Ud, cd, work, g
+        out["x".join(map(str, L))] = row
+    return {"jacobi_smearing": {"iterations": N_JACOBI, "kappa": KAPPA_JACOBI, "directions": 4,
+                                "flops_per_site_iteration": JACOBI_FLOPS_SITE_ITER, "lattices": out}}
 
 
 def batched_extras(torch, q, ctx, dev, stream, latgen):

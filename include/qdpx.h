@@ -85,7 +85,8 @@ typedef enum {
     QDPX_OP_CHAIN = 1,    /* qdpx_shift_chain */
     QDPX_OP_APE = 2,      /* qdpx_ape_smear */
     QDPX_OP_PLAQ = 3,     /* qdpx_plaquette */
-    QDPX_OP_BATCHED = 4   /* qdpx_ape_smear_batched (n = number of lattices) */
+    QDPX_OP_BATCHED = 4,  /* qdpx_ape_smear_batched (n = number of lattices) */
+    QDPX_OP_JACOBI = 5    /* qdpx_jacobi_smear and qdpx_eval_hop */
 } qdpx_op;
 
 typedef struct qdpx_ctx qdpx_ctx;
@@ -166,6 +167,28 @@ int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_
                      const void *U, void *psi, const void *phi, double a, double c, int n_iter,
                      double *norms, void *work, size_t work_bytes, void *stream);
 
+/* --------------------------------------------------------- Jacobi smearing
+ * The paper's application (section 7): the hopping term of the smearing
+ * operator K = delta - kappa sum_mu [U_mu(x) delta_{x',x+mu} + U_mu(x-mu)^dag
+ * delta_{x',x-mu}] and the iteration of its listing that sums the power series
+ * of K^{-1} up to n_iter terms.
+ *
+ * qdpx_eval_hop: out(x) = sum_{mu in dir_mask} [U_mu(x) psi(x+mu)
+ *   + U_mu(x-mu)^dag psi(x-mu)]  (the listing's expressions E_1/E_2 summed over
+ *   mu).  dir_mask bit mu selects direction mu (0xF: all four, as the
+ *   listing's loop over Nd; 0x7: the three spatial ones).  out must not
+ *   overlap psi or U.
+ * qdpx_jacobi_smear: s0 = chi; n_iter times { psi = chi; chi = s0 + kappa
+ *   (H psi) }; chi = chi / norm  (expressions E_0, E_1/E_2, E_3, E_4), chi
+ *   updated in place; n_iter >= 1, norm != 0.  One kernel per iteration; the
+ *   division by norm is fused into the last one.
+ *   work: >= qdpx_workspace_bytes(QDPX_OP_JACOBI, ...) (two fermion fields). */
+int qdpx_eval_hop(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
+                  const void *psi, void *out, uint32_t dir_mask, void *stream);
+int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
+                      void *chi, double kappa, int n_iter, double norm, uint32_t dir_mask, void *work,
+                      size_t work_bytes, void *stream);
+
 /* ----------------------------------------------------------- APE smearing
  * n_steps >= 1 APE steps.  One step, for every site x and direction mu,
  * from the unsmeared links of that step:
@@ -231,7 +254,7 @@ int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdp
 
 /* -------------------------------------------------------------- autotuner
  * Time the candidate launch geometries of operation `op` (QDPX_OP_APE,
- * QDPX_OP_SHIFT or QDPX_OP_CHAIN) on `geom` and remember the fastest in the
+ * QDPX_OP_SHIFT, QDPX_OP_CHAIN or QDPX_OP_JACOBI) on `geom` and remember the fastest in the
  * context: threads per block, consecutive 64-site groups per wave, the
  * XCD-contiguous block order, and the number of t planes walked together.
  * This is the auto-tuning of the thread geometry the paper proposes

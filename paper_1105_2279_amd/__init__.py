@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqdpx.so")
 
 F64, F32 = 0, 1
 LINK18, LINK12 = 0, 1
-OP_SHIFT, OP_CHAIN, OP_APE, OP_PLAQ, OP_BATCHED = 0, 1, 2, 3, 4
+OP_SHIFT, OP_CHAIN, OP_APE, OP_PLAQ, OP_BATCHED, OP_JACOBI = 0, 1, 2, 3, 4, 5
 
 STATUS = {
     0: "QDPX_OK",
@@ -38,6 +38,7 @@ EXPORTS = (
     "qdpx_pack_links", "qdpx_unpack_links", "qdpx_pack_fermion", "qdpx_unpack_fermion",
     "qdpx_eval_shift_mul_axpy", "qdpx_shift_chain", "qdpx_ape_smear", "qdpx_plaquette",
     "qdpx_ape_smear_batched", "qdpx_tune", "qdpx_tune_get", "qdpx_tune_set",
+    "qdpx_eval_hop", "qdpx_jacobi_smear",
 )
 
 
@@ -96,6 +97,8 @@ def lib():
         "qdpx_ape_smear_batched": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(_P), ctypes.POINTER(_P), dbl, i32,
                                          _P, _P, sz, _P]),
         "qdpx_tune": (i32, [_P, i32, _G, i32, i32, _P]),
+        "qdpx_eval_hop": (i32, [_P, _G, i32, i32, _P, _P, _P, ctypes.c_uint32, _P]),
+        "qdpx_jacobi_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, dbl, ctypes.c_uint32, _P, sz, _P]),
         "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)]),
@@ -259,6 +262,17 @@ def qdpx_ape_smear_batched(ctx, Ls, prec, fmt, U_in, U_out, alpha, n_steps, plaq
     _check(lib().qdpx_ape_smear_batched(ctx.handle, n, garr, prec, fmt, pin, pout, float(alpha), int(n_steps),
                                         _ptr(plaq), _ptr(work), _nbytes(work), _stream(stream)),
            "qdpx_ape_smear_batched")
+
+
+def qdpx_eval_hop(ctx, L, prec, fmt, U, psi, out, dir_mask=0xF, stream=None):
+    _check(lib().qdpx_eval_hop(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(psi), _ptr(out),
+                               int(dir_mask), _stream(stream)), "qdpx_eval_hop")
+
+
+def qdpx_jacobi_smear(ctx, L, prec, fmt, U, chi, kappa, n_iter, norm=1.0, dir_mask=0xF, work=None, stream=None):
+    _check(lib().qdpx_jacobi_smear(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(chi), float(kappa),
+                                   int(n_iter), float(norm), int(dir_mask), _ptr(work), _nbytes(work),
+                                   _stream(stream)), "qdpx_jacobi_smear")
 
 
 def qdpx_tune(ctx, op, L, prec, fmt, stream=None):

@@ -175,6 +175,8 @@ extern "C" size_t qdpx_workspace_bytes(qdpx_op op, const qdpx_geom *geom, qdpx_p
                reduce_bytes(std::max(ape_num_partials(g), plaquette_num_partials(g)), 2);
     case QDPX_OP_PLAQ:
         return reduce_bytes(plaquette_num_partials(g), 2);
+    case QDPX_OP_JACOBI:
+        return 2 * round256(qdpx_fermion_bytes(geom, prec));
     default:
         fail(QDPX_EINVAL, "qdpx_workspace_bytes: unknown op %d", (int)op);
         return 0;
@@ -313,6 +315,60 @@ extern "C" int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec 
         if (norms) QDPX_TRY_HIP(launch_finalize(part, shift_num_partials(g), 0, (double)g.V, norms + k, st), fn);
     }
     if (n_iter & 1) QDPX_TRY_HIP(launch_copy_fermion(g, prec, tmp, psi, st), fn);
+    return QDPX_OK;
+}
+
+// ------------------------------------------------------------------ Jacobi
+extern "C" int qdpx_eval_hop(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
+                             const void *psi, void *out, uint32_t dir_mask, void *stream) {
+    const char *fn = "qdpx_eval_hop";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U || !psi || !out) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
+    const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
+    if (overlap(out, fb, psi, fb) || overlap(out, fb, U, lb)) return fail(QDPX_EALIAS, "%s: out overlaps an input", fn);
+    const Geo g = make_geo(geom->L);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_JACOBI, geom, prec, fmt);
+    QDPX_TRY_HIP(launch_hop(g, prec, nrows_of(fmt), U, psi, nullptr, 1.0, 1.0, false, dir_mask, out, cfg,
+                            (hipStream_t)stream),
+                 fn);
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
+                                 void *chi, double kappa, int n_iter, double norm, uint32_t dir_mask, void *work,
+                                 size_t work_bytes, void *stream) {
+    const char *fn = "qdpx_jacobi_smear";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (!U || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
+    if (norm == 0.0) return fail(QDPX_EINVAL, "%s: norm is 0", fn);
+    if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
+    const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
+    const size_t need = qdpx_workspace_bytes(QDPX_OP_JACOBI, geom, prec, fmt, n_iter);
+    if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    if (overlap(chi, fb, U, lb)) return fail(QDPX_EALIAS, "%s: chi overlaps U", fn);
+    if (overlap(work, need, chi, fb) || overlap(work, need, U, lb))
+        return fail(QDPX_EALIAS, "%s: workspace overlaps a field", fn);
+    const Geo g = make_geo(geom->L);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_JACOBI, geom, prec, fmt);
+    hipStream_t st = (hipStream_t)stream;
+    void *s0 = work;
+    void *tmp = (char *)work + round256(fb);
+    // E_0: s0 = chi.  Iteration k reads the previous iterate (s0 for k = 0)
+    // and the last one lands in chi.
+    QDPX_TRY_HIP(launch_copy_fermion(g, prec, chi, s0, st), fn);
+    const void *src = s0;
+    for (int k = 0; k < n_iter; ++k) {
+        void *dst = (((n_iter - 1 - k) & 1) == 0) ? chi : tmp;
+        const bool last = (k == n_iter - 1);
+        QDPX_TRY_HIP(launch_hop(g, prec, nrows_of(fmt), U, src, s0, kappa, norm, last, dir_mask, dst, cfg, st), fn);
+        src = dst;
+    }
     return QDPX_OK;
 }
 
@@ -551,7 +607,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (c.xcd < 0 || c.xcd > 2) return false;
     if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
-    if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
+    if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN || op == QDPX_OP_JACOBI)
         return c.block <= 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
     if (op == QDPX_OP_BATCHED) return c.block == 256 && c.nsite >= 1 && c.nsite <= 1024;  // nsite = groups per item
     return false;
@@ -598,7 +654,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
-    if (op != QDPX_OP_APE && op != QDPX_OP_SHIFT && op != QDPX_OP_CHAIN)
+    if (op != QDPX_OP_APE && op != QDPX_OP_SHIFT && op != QDPX_OP_CHAIN && op != QDPX_OP_JACOBI)
         return fail(QDPX_EUNSUPPORTED, "%s: op %d has a fixed geometry", fn, (int)op);
     hipStream_t st = (hipStream_t)stream;
     if (stream_capturing(st)) return fail(QDPX_ECAPTURE, "%s: stream is capturing", fn);
@@ -655,6 +711,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     for (const LaunchCfg &c : cands) {
         auto run = [&]() -> hipError_t {
             if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, nullptr, 0, c, st);
+            if (op == QDPX_OP_JACOBI) return launch_hop(g, prec, nrows, U, A, B, 0.1, 1.0, false, 0xFu, C, c, st);
             return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
                                 st);
         };

@@ -252,6 +252,124 @@ hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ Jacobi hop
+// out(x) = [s0(x) + kappa * (H psi)(x)] / norm, with
+// (H psi)(x) = sum_{mu in mask} [U_mu(x) psi(x+mu) + U_mu(x-mu)^dag psi(x-mu)],
+// the hopping term of the smearing operator K.  s0 may be absent (then
+// out = kappa H psi / norm); DIV selects the division by norm.  Same site
+// mapping and launch orders as the shift expression.
+template <typename R, int NR, int NS, bool DIV>
+__global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> s0, R kappa, R norm,
+                                              unsigned mask, FermWO<R> out, int xcd, int tw) {
+    const int nwb = blockDim.x >> 6;
+    const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ngroups = num_groups(g);
+#pragma unroll 1
+    for (int j = 0; j < NS; ++j) {
+        const int i = (tile * nwb + wave) * NS + j;
+        if (i >= ngroups) return;
+        const int grp = xcd == 2 ? colwalk(g, i, nwb * NS) : traverse(g, i, tw);
+        Site x;
+        if (!group_site(g, grp, lane, x)) continue;
+        const int s = x.s;
+        Cx<R> acc[4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            if (!((mask >> mu) & 1u)) continue;  // wave-uniform
+            {
+                M3<R> u;
+                U.full_stream(mu, s, u);  // U_mu(x): read once per site in this pass
+                const int f = hop_fwd(g, s, x.c[mu], mu);
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    Cx<R> p[3];
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, f);
+#pragma unroll
+                    for (int ca = 0; ca < 3; ++ca)
+#pragma unroll
+                        for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], u.e[ca][cb], p[cb]);
+                }
+            }
+            {
+                const int b = hop_bwd(g, s, x.c[mu], mu);
+                M3<R> u;
+                U.full(mu, b, u);  // U_mu(x-mu)
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    Cx<R> p[3];
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, b);
+                    // (U^dag p)_a = sum_b conj(U_ba) p_b
+#pragma unroll
+                    for (int ca = 0; ca < 3; ++ca)
+#pragma unroll
+                        for (int cb = 0; cb < 3; ++cb) cmac_ca(acc[sp][ca], u.e[cb][ca], p[cb]);
+                }
+            }
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Cx<R> v = acc[sp][cc];
+                if (s0.p) {
+                    const Cx<R> z = s0.ld_stream(sp, cc, s);
+                    v.re = fma(kappa, v.re, z.re);
+                    v.im = fma(kappa, v.im, z.im);
+                } else {
+                    v.re *= kappa;
+                    v.im *= kappa;
+                }
+                if constexpr (DIV) {
+                    v.re = v.re / norm;
+                    v.im = v.im / norm;
+                }
+                out.st(sp, cc, s, v);
+            }
+    }
+}
+
+template <typename R, int NR, bool DIV>
+static void hop_dispatch_ns(const Geo &g, const void *U, const void *psi, const void *s0, double kappa, double norm,
+                            unsigned mask, void *out, const LaunchCfg &cfg, hipStream_t st) {
+    using V = vec2_t<R>;
+    LinksRO<R, NR> u{(const V *)U, g.S};
+    FermRO<R> p{(const V *)psi, g.S}, z{(const V *)s0, g.S};
+    FermWO<R> o{(V *)out, g.S};
+    const int groups = (g.V + 63) / 64;
+    const int per_block = (cfg.block / 64) * cfg.nsite;
+    const dim3 grid((groups + per_block - 1) / per_block);
+    const int xcd = launch_order(g, cfg, per_block);
+    switch (cfg.nsite) {
+    case 2: k_hop<R, NR, 2, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    case 4: k_hop<R, NR, 4, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    case 8: k_hop<R, NR, 8, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    default: k_hop<R, NR, 1, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    }
+}
+
+template <bool DIV>
+static void hop_dispatch(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *s0,
+                         double kappa, double norm, unsigned mask, void *out, const LaunchCfg &cfg, hipStream_t st) {
+    if (prec == 0) hop_dispatch_ns<double, 3, DIV>(g, U, psi, s0, kappa, norm, mask, out, cfg, st);
+    else if (nrows == 3) hop_dispatch_ns<float, 3, DIV>(g, U, psi, s0, kappa, norm, mask, out, cfg, st);
+    else hop_dispatch_ns<float, 2, DIV>(g, U, psi, s0, kappa, norm, mask, out, cfg, st);
+}
+
+hipError_t launch_hop(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *s0, double kappa,
+                      double norm, bool divide, unsigned mask, void *out, const LaunchCfg &cfg, hipStream_t st) {
+    if (divide) hop_dispatch<true>(g, prec, nrows, U, psi, s0, kappa, norm, mask, out, cfg, st);
+    else hop_dispatch<false>(g, prec, nrows, U, psi, s0, kappa, norm, mask, out, cfg, st);
+    return hipGetLastError();
+}
+
 template <typename V>
 __global__ void __launch_bounds__(256) k_copy_fermion(Geo g, const V *__restrict__ src, V *__restrict__ dst) {
     const int s = blockIdx.x * 256 + threadIdx.x;

@@ -40,6 +40,11 @@ hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const 
                         hipStream_t st);
 hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *dst, hipStream_t st);
 
+// Jacobi hop: out = [s0 + kappa * H psi] / norm (s0 nullable; division only
+// if `divide`), H summed over the directions in mask, both hop directions.
+hipError_t launch_hop(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *s0, double kappa,
+                      double norm, bool divide, unsigned mask, void *out, const LaunchCfg &cfg, hipStream_t st);
+
 // Deterministic finalisation.  mode 0: out[0] = sum of partials[0..n).
 // mode 1 (plaquette): partials hold n spatial then n temporal sums;
 // out = {(sp+tp)/(18V), sp/(9V), tp/(9V)}.
