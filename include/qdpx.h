@@ -190,26 +190,33 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
                       size_t work_bytes, void *stream);
 
 /* ----------------------------------------------------------- APE smearing
- * n_steps >= 1 APE steps.  One step, for every site x and direction mu,
- * from the unsmeared links of that step:
- *   W_mu(x) = (1-alpha) U_mu(x) + (alpha/6) sum_{nu != mu} [
+ * n_steps >= 1 APE steps.  One step, for every site x and every direction
+ * mu in smear_mask, from the unsmeared links of that step:
+ *   W_mu(x) = (1-alpha) U_mu(x) + alpha/(2(d-1)) sum_{nu in mask, nu != mu} [
  *               U_nu(x) U_mu(x+nu) U_nu(x+mu)^dagger
  *             + U_nu(x-nu)^dagger U_mu(x-nu) U_nu(x-nu+mu) ]
  *   V_mu(x) = rows (u, v, conj(u x v)) with u = w0/|w0|,
  *             v = (w1 - (u^dagger w1) u) / |...|   (w0, w1 = rows 0, 1 of W),
- * the projection always in FP64.  With QDPX_F32 the staple products are
- * evaluated in FP32.  U_in is not modified; U_out must not overlap U_in.
+ * d = number of directions in smear_mask, so alpha weighs the mean of the
+ * link's staples (alpha/6 with all four directions, alpha/4 with the three
+ * spatial ones).  Links of directions outside smear_mask are copied
+ * unchanged.  smear_mask: bit mu = direction mu; 0xF smears all four, 0x7
+ * leaves the time direction alone (the role of the no-smear direction
+ * argument of the smearing routine of section 7).  The projection is always
+ * FP64.  With QDPX_F32 the staple products are evaluated in FP32.  U_in is
+ * not modified; U_out must not overlap U_in.
  * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
- * triple (total, spatial, temporal; normalised as in qdpx_plaquette) of the
- * input and of every step's output.  These traces are formed in the link
- * precision inside the smearing kernel and summed in FP64 (qdpx_plaquette
- * forms them in FP64); the smeared links do not depend on whether plaq is
- * requested.
+ * triple (total, spatial, temporal; normalised as in qdpx_plaquette; all six
+ * planes whatever the mask) of the input and of every step's output.  These
+ * traces are formed in the link precision and summed in FP64 (qdpx_plaquette
+ * forms them in FP64); with smear_mask 0xF they are fused into the smearing
+ * kernel, otherwise each is a pass of its own with the same arithmetic.  The
+ * smeared links do not depend on whether plaq is requested.
  * A W whose row 0 or projected row 1 vanishes gives NaN entries.
  * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
 int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                   const void *U_in, void *U_out, double alpha, int n_steps, double *plaq,
-                   void *work, size_t work_bytes, void *stream);
+                   const void *U_in, void *U_out, double alpha, int n_steps, uint32_t smear_mask,
+                   double *plaq, void *work, size_t work_bytes, void *stream);
 
 /* -------------------------------------------------------------- plaquette
  * plaq[0] = (1/(18V)) sum_x sum_{mu<nu} Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]
@@ -222,12 +229,14 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
 
 /* ------------------------------------------------------ batched APE smearing
  * n_lat independent lattices of any extents (each at most 4194304 sites),
- * each smeared n_steps times (1 <= n_steps <= 1024) as in qdpx_ape_smear,
- * followed by each lattice's output plaquette triple, in ONE persistent
- * kernel launch (plus a small kernel that clears its counters).  Work items
- * (step, lattice, chunk of 64-site groups) are handed out in step order by a
- * ticket counter and each lattice's steps are ordered by completion
- * counters; a batch of small and large lattices fills the GPU as one job.
+ * each smeared n_steps times (1 <= n_steps <= 1024) as in qdpx_ape_smear
+ * with smear_mask 0xF, followed by each lattice's output plaquette triple, in
+ * ONE persistent kernel launch (plus a small kernel that clears its
+ * counters).  The launch runs in phases (step 1 .. n_steps, then the
+ * plaquettes); within a phase the work items of every lattice are shared by
+ * all blocks through per-XCD ticket queues, and a phase starts once every
+ * block has finished the previous one, so a batch of small and large
+ * lattices fills the GPU as one job.
  *   geoms: host array [n_lat]; U_in, U_out: host arrays [n_lat] of device
  *   pointers (SoA, prec, fmt; U_out[i] must not overlap any U_in[j] or
  *   another U_out[j]); plaq (nullable): device double[n_lat][3].

@@ -373,24 +373,44 @@ void oracle_staple_sums(const int *L, const double *U, double *Sup, double *Slo)
         }
 }
 
-/* W_mu(x) = (1-alpha) U_mu(x) + (alpha/6) sum_{nu != mu} [upper + lower staple],
- * the six staples accumulated for nu = 0..3 (skipping mu), upper before lower. */
-static mat3 ape_w_link(const lat *g, const double *U, long s, int mu, double alpha)
+static int reunitarise(const mat3 *W, mat3 *V);
+
+/* W_mu(x) = (1-alpha) U_mu(x) + alpha * (mean of the staples of U_mu(x) in
+ * the planes (mu, nu), nu in mask, nu != mu): with all four directions that
+ * is alpha/6 times the sum of six staples, with the three spatial ones
+ * alpha/4 times the sum of four.  The staples are accumulated for
+ * nu = 0..3 in increasing order, upper before lower. */
+static mat3 ape_w_link(const lat *g, const double *U, long s, int mu, double alpha, unsigned mask)
 {
     mat3 S = m_zero();
+    int n = 0;
     for (int nu = 0; nu < 4; ++nu) {
-        if (nu == mu) continue;
+        if (nu == mu || !((mask >> nu) & 1u)) continue;
         mat3 su = staple_upper(g, U, s, mu, nu);
         S = m_add(&S, &su);
         mat3 sl = staple_lower(g, U, s, mu, nu);
         S = m_add(&S, &sl);
+        n += 2;
     }
+    const double wt = n > 0 ? alpha / n : 0.0;
     mat3 u = load_link(U, s, mu);
     mat3 W;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            W.e[i][j] = c_add(c_scale(1.0 - alpha, u.e[i][j]), c_scale(alpha / 6.0, S.e[i][j]));
+            W.e[i][j] = c_add(c_scale(1.0 - alpha, u.e[i][j]), c_scale(wt, S.e[i][j]));
     return W;
+}
+
+/* One smeared link: directions outside the mask keep U_mu(x) unchanged,
+ * the others are Proj[W_mu(x)].  Returns 1 for a degenerate W. */
+static int ape_link(const lat *g, const double *U, long s, int mu, double alpha, unsigned mask, mat3 *V)
+{
+    if (!((mask >> mu) & 1u)) {
+        *V = load_link(U, s, mu);
+        return 0;
+    }
+    mat3 w = ape_w_link(g, U, s, mu, alpha, mask);
+    return reunitarise(&w, V);
 }
 
 /* Reunitarise by rows: u = r1/|r1|; v = r2 - (sum_j conj(u_j) r2_j) u, v /= |v|;
@@ -427,14 +447,15 @@ static int reunitarise(const mat3 *W, mat3 *V)
     return bad;
 }
 
-/* Unprojected APE combination W for every link. */
-void oracle_ape_w(const int *L, const double *U, double alpha, double *W)
+/* Unprojected APE combination W for every link (every direction, with the
+ * staples of the directions in mask). */
+void oracle_ape_w(const int *L, const double *U, double alpha, unsigned mask, double *W)
 {
     lat g = lat_make(L);
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < g.V; ++s)
         for (int mu = 0; mu < 4; ++mu) {
-            mat3 w = ape_w_link(&g, U, s, mu, alpha);
+            mat3 w = ape_w_link(&g, U, s, mu, alpha, mask);
             store_link(W, s, mu, &w);
         }
 }
@@ -461,24 +482,25 @@ long oracle_reunitarise(long n_links, const double *W, double *V)
     return bad;
 }
 
-/* One APE step: V_mu(x) = Proj[W_mu(x)] for all links, all from the unsmeared U.
+/* One APE step: V_mu(x) = Proj[W_mu(x)] for the links of the directions in
+ * mask, all from the unsmeared U; the other links are copied.
  * Returns the number of degenerate links. */
-long oracle_ape_step(const int *L, const double *U, double alpha, double *Vout)
+long oracle_ape_step(const int *L, const double *U, double alpha, unsigned mask, double *Vout)
 {
     lat g = lat_make(L);
     long bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (long s = 0; s < g.V; ++s)
         for (int mu = 0; mu < 4; ++mu) {
-            mat3 w = ape_w_link(&g, U, s, mu, alpha), v;
-            bad += reunitarise(&w, &v);
+            mat3 v;
+            bad += ape_link(&g, U, s, mu, alpha, mask, &v);
             store_link(Vout, s, mu, &v);
         }
     return bad;
 }
 
 /* n_steps APE steps; Vout receives the last step, U is not modified. */
-long oracle_ape_smear(const int *L, const double *U, double alpha, int n_steps, double *Vout)
+long oracle_ape_smear(const int *L, const double *U, double alpha, unsigned mask, int n_steps, double *Vout)
 {
     lat g = lat_make(L);
     size_t nl = (size_t)g.V * 4 * 18;
@@ -486,7 +508,7 @@ long oracle_ape_smear(const int *L, const double *U, double alpha, int n_steps, 
     long bad = 0;
     memcpy(cur, U, sizeof(double) * nl);
     for (int k = 0; k < n_steps; ++k) {
-        bad += oracle_ape_step(L, cur, alpha, Vout);
+        bad += oracle_ape_step(L, cur, alpha, mask, Vout);
         memcpy(cur, Vout, sizeof(double) * nl);
     }
     if (n_steps == 0) memcpy(Vout, U, sizeof(double) * nl);
@@ -495,15 +517,15 @@ long oracle_ape_smear(const int *L, const double *U, double alpha, int n_steps, 
 }
 
 /* One APE step evaluated only for the listed links (site[i], mu[i]). */
-long oracle_ape_links(const int *L, const double *U, double alpha, long n, const long *site,
+long oracle_ape_links(const int *L, const double *U, double alpha, unsigned mask, long n, const long *site,
                       const int *mu, double *Vout)
 {
     lat g = lat_make(L);
     long bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (long i = 0; i < n; ++i) {
-        mat3 w = ape_w_link(&g, U, site[i], mu[i], alpha), v;
-        bad += reunitarise(&w, &v);
+        mat3 v;
+        bad += ape_link(&g, U, site[i], mu[i], alpha, mask, &v);
         double *q = Vout + (size_t)i * 18;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {

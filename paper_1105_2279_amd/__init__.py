@@ -92,7 +92,7 @@ def lib():
         "qdpx_unpack_fermion": (i32, [_P, _G, _P, i32, _P, _P]),
         "qdpx_eval_shift_mul_axpy": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, _P, _P, _P, sz, _P]),
         "qdpx_shift_chain": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, dbl, i32, _P, _P, sz, _P]),
-        "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, _P, _P, sz, _P]),
+        "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, ctypes.c_uint32, _P, _P, sz, _P]),
         "qdpx_plaquette": (i32, [_P, _G, i32, i32, _P, _P, _P, sz, _P]),
         "qdpx_ape_smear_batched": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(_P), ctypes.POINTER(_P), dbl, i32,
                                          _P, _P, sz, _P]),
@@ -243,10 +243,11 @@ def qdpx_shift_chain(ctx, L, prec, fmt, U, psi, phi, a, c, n_iter, norms=None, w
                                   _stream(stream)), "qdpx_shift_chain")
 
 
-def qdpx_ape_smear(ctx, L, prec, fmt, U_in, U_out, alpha, n_steps, plaq=None, work=None, stream=None):
+def qdpx_ape_smear(ctx, L, prec, fmt, U_in, U_out, alpha, n_steps, plaq=None, work=None, stream=None,
+                   smear_mask=0xF):
     _check(lib().qdpx_ape_smear(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U_in), _ptr(U_out),
-                                float(alpha), int(n_steps), _ptr(plaq), _ptr(work), _nbytes(work),
-                                _stream(stream)), "qdpx_ape_smear")
+                                float(alpha), int(n_steps), int(smear_mask), _ptr(plaq), _ptr(work),
+                                _nbytes(work), _stream(stream)), "qdpx_ape_smear")
 
 
 def qdpx_plaquette(ctx, L, prec, fmt, U, plaq, work, stream=None):

@@ -12,7 +12,8 @@ namespace qdpx {
 // same block, which share the neighbour loads in L1/L2.
 template <typename R, int NR, int NS, int MODE>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
-                                                  double c2, double *__restrict__ partials, int xcd, int tw) {
+                                                  double c2, unsigned mask, double *__restrict__ partials, int xcd,
+                                                  int tw) {
     const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mu = w & 3;
@@ -23,14 +24,15 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
         const int grp = xcd == 2 ? colwalk(g, i, gpb * NS) : traverse(g, i, tw);
-        ape_group<R, NR, MODE>(g, U, out, c1, c2, partials, grp, mu, lane);
+        ape_group<R, NR, MODE>(g, U, out, c1, c2, mask, partials, grp, mu, lane);
     }
 }
 
 int ape_num_partials(const Geo &g) { return 4 * ((g.V + 63) / 64); }
 
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           double *partials, int mode, const LaunchCfg &cfg, hipStream_t st) {
+                           unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st) {
+    if (mode == kApePlaq && mask != 0xFu) return hipErrorInvalidValue;  // owned planes need every staple
     const int groups = (g.V + 63) / 64;
     const int gpb = cfg.block / 256;
     const int per_block = gpb * cfg.nsite;
@@ -38,7 +40,7 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     const int xcd = launch_order(g, cfg, per_block);
 #define QDPX_APE_LAUNCH(R, NR, NS, M)                                                                          \
     k_ape_step<R, NR, NS, M><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},        \
-                                                         LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,        \
+                                                         LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2, mask,  \
                                                          partials, xcd, cfg.tw)
 #define QDPX_APE_M(R, NR, NS)                                      \
     if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly);  \

@@ -93,13 +93,14 @@ __device__ __forceinline__ void row2_of(const LinksRO<R, NR> &U, int mu, int s, 
     }
 }
 
-// Staple sum (rows 0 and 1) of link (s, mu).  With PLQ the full upper staples
+// Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
+// in mask (bits 0..3; all four for the fused plaquette).  With PLQ the full upper staples
 // of the planes this wave owns are also summed into Q (all three rows), so
 // that Re Tr[U_mu(x) Q^dag] is the sum of the traces of the owned plaquettes
 // P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag.
 template <typename R, int NR, bool PLQ>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  M23<R> &S, M3<R> &Q) {
+                                                  unsigned mask, M23<R> &S, M3<R> &Q) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -115,6 +116,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         const int nu = k + (k >= mu);
+        if (!((mask >> nu) & 1u)) continue;  // wave-uniform
         // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
         {
             M23<R> A;
@@ -255,14 +257,16 @@ __device__ __forceinline__ double retrace_with(const LinksRO<R, NR> &U, int mu, 
 }
 
 // One wave's share of a step: direction mu of the 64 sites of group grp.
-// Writes the smeared links (modes kApe, kApePlaq) and, in the plaquette
+// Writes the smeared links (modes kApe, kApePlaq; a direction outside mask
+// is copied unchanged, mask is 0xF in kApePlaq) and, in the plaquette
 // modes, the owned planes' trace sum of the INPUT links for (grp, mu):
 // partials[grp*4 + mu] (spatial planes, waves 0 and 1) and
 // partials[4*ngroups + grp*4 + mu] (temporal planes, waves 2 and 3).
 // Depends only on (grp, mu), never on the launch geometry.
 template <typename R, int NR, int MODE>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
-                                          double c2, double *__restrict__ partials, int grp, int mu, int lane) {
+                                          double c2, unsigned mask, double *__restrict__ partials, int grp, int mu,
+                                          int lane) {
     const int ngroups = num_groups(g);
     double p = 0.0;
     Site x;
@@ -274,9 +278,16 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             M23<R> u0;
             U.rows01(mu, s, u0);
             p = retrace_with(U, mu, s, u0, Q);
+        } else if (!((mask >> mu) & 1u)) {  // wave-uniform: not smeared
+            M3<R> u;
+            U.full(mu, s, u);
+#pragma unroll
+            for (int a = 0; a < NR; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, u.e[a][b].re, u.e[a][b].im);
         } else {
             M23<R> S;
-            staple_sum_rows01<R, NR, MODE == kApePlaq>(g, U, x, mu, S, Q);
+            staple_sum_rows01<R, NR, MODE == kApePlaq>(g, U, x, mu, mask, S, Q);
             M23<R> u0;
             U.rows01(mu, s, u0);
             if constexpr (MODE == kApePlaq) p = retrace_with(U, mu, s, u0, Q);

@@ -395,14 +395,16 @@ extern "C" int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
 }
 
 extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                              const void *U_in, void *U_out, double alpha, int n_steps, double *plaq, void *work,
-                              size_t work_bytes, void *stream) {
+                              const void *U_in, void *U_out, double alpha, int n_steps, uint32_t smear_mask,
+                              double *plaq, void *work, size_t work_bytes, void *stream) {
     const char *fn = "qdpx_ape_smear";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U_in || !U_out) return fail(QDPX_EINVAL, "%s: NULL link pointer", fn);
     if (n_steps < 1) return fail(QDPX_EINVAL, "%s: n_steps = %d < 1", fn, n_steps);
+    if (smear_mask & ~0xFu)
+        return fail(QDPX_EINVAL, "%s: smear_mask 0x%x has bits beyond the 4 directions", fn, smear_mask);
     const size_t lb = qdpx_links_bytes(geom, prec, fmt);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_APE, geom, prec, fmt, n_steps);
     const bool need_work = (n_steps >= 2) || plaq;
@@ -416,21 +418,29 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     hipStream_t st = (hipStream_t)stream;
     void *tmp = (n_steps >= 2) ? work : nullptr;
     double *part = (double *)((char *)work + (n_steps >= 2 ? round256(lb) : 0));
-    const double c1 = 1.0 - alpha, c2 = alpha / 6.0;
-    // Step k also reduces the plaquette of its own input (fused into the APE
-    // kernel); only the last output needs the standalone plaquette kernel.
+    // A smeared link mixes in alpha times the mean of its 2 (d - 1) staples,
+    // d = number of smeared directions (alpha/6 for all four).
+    const int d = __builtin_popcount(smear_mask);
+    const double c1 = 1.0 - alpha, c2 = d > 1 ? alpha / (2.0 * (d - 1)) : 0.0;
+    // With every direction smeared, step k also reduces the plaquette of its
+    // own input (fused into the APE kernel) and only the last output needs the
+    // plaquette-only pass; with a partial mask every plaquette is its own pass
+    // (the same per-plane arithmetic, so the values agree bit for bit).
+    const bool fused = (smear_mask == 0xFu);
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
         void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, plaq ? part : nullptr, plaq ? 1 : 0,
-                                     cfg, st),
+        if (plaq && !fused)
+            QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, smear_mask,
+                                     (plaq && fused) ? part : nullptr, (plaq && fused) ? 1 : 0, cfg, st),
                      fn);
         if (plaq) QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
         src = dst;
     }
     if (plaq) {
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), U_out, nullptr, c1, c2, part, 2, cfg, st), fn);
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), U_out, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
         QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * n_steps, st), fn);
     }
     return QDPX_OK;
@@ -710,7 +720,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     const int nrows = nrows_of(fmt);
     for (const LaunchCfg &c : cands) {
         auto run = [&]() -> hipError_t {
-            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, nullptr, 0, c, st);
+            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, 0xFu, nullptr, 0, c, st);
             if (op == QDPX_OP_JACOBI) return launch_hop(g, prec, nrows, U, A, B, 0.1, 1.0, false, 0xFu, C, c, st);
             return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
                                 st);

@@ -119,11 +119,11 @@ __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat
                     if (ape) {
 #pragma unroll 1
                         for (int row = row0; row < row1; ++row)
-                            ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, nullptr, col + L.ncol * row, mu, lane);
+                            ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, col + L.ncol * row, mu, lane);
                     } else {
 #pragma unroll 1
                         for (int row = row0; row < row1; ++row)
-                            ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, L.partials, col + L.ncol * row, mu,
+                            ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, 0xFu, L.partials, col + L.ncol * row, mu,
                                                         lane);
                     }
                 }

@@ -91,38 +91,89 @@ def _abelian(L, seed):
     return ang, U
 
 
-@pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 3, 4, 5)])
-def test_abelian_closed_form(L):
+@pytest.mark.parametrize("L,mask", [((4, 4, 4, 4), 0xF), ((2, 3, 4, 5), 0xF), ((4, 4, 4, 4), 0x7),
+                                    ((2, 3, 4, 5), 0xB)])
+def test_abelian_closed_form(L, mask):
     # For diagonal links each colour component is a U(1) field with angle
-    # th_mu(x); the staples become phases of sums of angles.
+    # th_mu(x); the staples become phases of sums of angles.  A smeared link
+    # mixes (1 - alpha) of itself with alpha times the average of its staples
+    # in the smeared directions; the other links are left alone.
     ang, U = _abelian(L, 55)
-    W = oracle.ape_w(U, ALPHA)
+    W = oracle.ape_w(U, ALPHA, mask)
+    V = oracle.ape_step(U, ALPHA, mask)
+    dirs = [nu for nu in range(4) if (mask >> nu) & 1]
     Wexp = np.zeros(U.shape[:5] + (3,), dtype=np.complex128)
     for mu in range(4):
         th_mu = ang[..., mu, :]
-        s = np.zeros_like(th_mu, dtype=np.complex128)
-        for nu in range(4):
+        staples = []
+        for nu in dirs:
             if nu == mu:
                 continue
             th_nu = ang[..., nu, :]
             up = th_nu + fwd(th_mu, nu) - fwd(th_nu, mu)
             lo = -bwd(th_nu, nu) + bwd(th_mu, nu) + fwd(bwd(th_nu, nu), mu)
-            s += np.exp(1j * up) + np.exp(1j * lo)
-        Wexp[..., mu, :] = (1 - ALPHA) * np.exp(1j * th_mu) + ALPHA / 6 * s
+            staples += [np.exp(1j * up), np.exp(1j * lo)]
+        Wexp[..., mu, :] = (1 - ALPHA) * np.exp(1j * th_mu) + ALPHA * np.mean(staples, axis=0)
     diag = np.diagonal(W, axis1=-2, axis2=-1)
     assert max_abs(diag - Wexp) < 1e-14
     off = W.copy()
     for k in range(3):
         off[..., k, k] = 0
     assert max_abs(off) == 0.0
-    V = oracle.ape_step(U, ALPHA)
     v0 = Wexp[..., 0] / np.abs(Wexp[..., 0])
     v1 = Wexp[..., 1] / np.abs(Wexp[..., 1])
     v2 = np.exp(-1j * (np.angle(Wexp[..., 0]) + np.angle(Wexp[..., 1])))
     vd = np.diagonal(V, axis1=-2, axis2=-1)
-    assert max_abs(vd[..., 0] - v0) < 1e-14
-    assert max_abs(vd[..., 1] - v1) < 1e-14
-    assert max_abs(vd[..., 2] - v2) < 1e-14
+    for mu in range(4):
+        if mu in dirs:
+            assert max_abs(vd[..., mu, 0] - v0[..., mu]) < 1e-14
+            assert max_abs(vd[..., mu, 1] - v1[..., mu]) < 1e-14
+            assert max_abs(vd[..., mu, 2] - v2[..., mu]) < 1e-14
+        else:
+            assert np.array_equal(V[..., mu, :, :], U[..., mu, :, :])
+
+
+# ------------------------------------------------- spatial-only smearing
+def test_spatial_smearing_leaves_temporal_links_and_ignores_them():
+    # With the three spatial directions smeared, temporal links are copied,
+    # and spatial links depend on spatial links only.
+    L = (4, 3, 2, 5)
+    U = latgen.haar_links(L, 80)
+    V = oracle.ape_step(U, ALPHA, 0x7)
+    assert np.array_equal(V[..., 3, :, :], U[..., 3, :, :])
+    U2 = U.copy()
+    U2[..., 3, :, :] = latgen.haar_links(L, 81)[..., 3, :, :]
+    V2 = oracle.ape_step(U2, ALPHA, 0x7)
+    assert np.array_equal(V2[..., :3, :, :], V[..., :3, :, :])
+
+
+def test_spatial_smearing_is_per_time_slice():
+    # Each t-slice smears on its own: the slice taken as an Lt = 1 lattice
+    # gives the same spatial links.
+    L = (3, 4, 2, 3)
+    U = latgen.haar_links(L, 82)
+    V = oracle.ape_step(U, ALPHA, 0x7)
+    for t in range(L[3]):
+        Vt = oracle.ape_step(U[t:t + 1].copy(), ALPHA, 0x7)
+        assert np.array_equal(Vt[0, ..., :3, :, :], V[t, ..., :3, :, :])
+
+
+def test_masked_step_gauge_covariant_torus():
+    U = small_haar()
+    g = latgen.torus_gauge((4, 4, 4, 4), 83)
+    for mask in (0x7, 0x5):
+        V = oracle.ape_step(U, ALPHA, mask)
+        Vg = oracle.ape_step(gauge_links(U, g), ALPHA, mask)
+        assert max_abs(Vg - gauge_links(V, g)) < 1e-13
+
+
+def test_single_direction_mask_only_projects():
+    # One smeared direction has no staples: W = (1 - alpha) U, which projects
+    # back to U.
+    U = small_haar((2, 3, 2, 2), 84)
+    V = oracle.ape_step(U, ALPHA, 0x2)
+    assert max_abs(V - U) < 1e-14
+    assert np.array_equal(oracle.ape_step(U, ALPHA, 0x0), U)
 
 
 def test_abelian_plaquette_closed_form():

@@ -28,7 +28,10 @@ MUTANTS = {
                                     "mat3 c = load_link(U, hop(g, s, mu, +1), nu);"),
     "lower_staple_transposed_product": ("mat3 ab = m_mul(&ad, &b);", "mat3 ab = m_mul(&b, &ad);"),
     "lower_staple_dropped": ("S = m_add(&S, &sl);", "S = m_add(&S, &su);"),
-    "combine_wrong_weight": ("c_scale(alpha / 6.0, S.e[i][j])", "c_scale(alpha / 4.0, S.e[i][j])"),
+    "combine_wrong_weight": ("alpha / n : 0.0", "alpha / (n + 2) : 0.0"),
+    "mask_ignored_in_staples": ("if (nu == mu || !((mask >> nu) & 1u)) continue;", "if (nu == mu) continue;"),
+    "masked_direction_smeared": ("if (!((mask >> mu) & 1u)) {\n        *V = load_link(U, s, mu);",
+                                 "if (0) {\n        *V = load_link(U, s, mu);"),
     "row3_missing_conj": ("V->e[2][1] = c_conj(c_sub(c_mul(u[2], v[0]), c_mul(u[0], v[2])));",
                           "V->e[2][1] = c_sub(c_mul(u[2], v[0]), c_mul(u[0], v[2]));"),
     "gram_schmidt_no_conj": ("d = c_add(d, c_mul(c_conj(u[j]), W->e[1][j]));",
