@@ -98,7 +98,8 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--profile", action="store_true",
                    help="short run for hardware-counter profiling: one 1 GiB device copy (the calibration "
-                        "kernel of known size), then two timed-step calls of each APE link format; no JSON line")
+                        "kernel of known size), then two plaquette-free and two timed-step calls of each APE link "
+                        "format, then four Jacobi hop launches per format; no JSON line")
     return p.parse_args()
 
 
@@ -125,6 +126,7 @@ def main():
 
     import latgen
     import paper_1105_2279_amd as q
+    from paper_1105_2279_amd import tuning
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -141,13 +143,14 @@ def main():
     for name, (prec, fmt) in paths.items():
         dev_links[name] = q.links_to_device(ctx, L, U, prec, fmt, dev)
     torch.cuda.synchronize()
-    # launch geometry from the library's autotuner (not timed)
+    # launch geometry: the stored table of autotuner results, or the
+    # autotuner now for shapes it lacks (not timed)
+    table = tuning.load(ctx)
     tuned = {}
     for name, (prec, fmt) in paths.items():
-        q.qdpx_tune(ctx, q.OP_APE, L, prec, fmt)
-        tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window"),
-                               q.qdpx_tune_get(ctx, q.OP_APE, L, prec, fmt)))
-        log(f"tuned APE {name}: {tuned[name]}")
+        cfg, src = tuning.ensure(ctx, q.OP_APE, prec, fmt, L, table)
+        tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window"), cfg), source=src)
+        log(f"APE {name} launch: {tuned[name]}")
 
     works = {}
 
@@ -179,6 +182,16 @@ def main():
             call, _, _ = make_call(name)
             call()
             call()
+        # then, per format, the tuned Jacobi hop kernel, four launches
+        psi = latgen.dirac_field(L, latgen.SEEDS["ape_32x32x32x64"]["links"] + 1)
+        for name, (prec, fmt) in paths.items():
+            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L, table)
+            pd = q.fermion_to_device(ctx, L, psi, prec, dev)
+            h = q.alloc_fermion(L, prec, dev)
+            for _ in range(4):
+                q.qdpx_eval_hop(ctx, L, prec, fmt, dev_links[name], pd, h, 0xF, stream)
+            torch.cuda.synchronize()
+            del pd, h
         torch.cuda.synchronize()
         log("profile run done")
         ctx.close()
@@ -277,9 +290,9 @@ def main():
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
     }
     if not args.no_extras:
-        extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
+        extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np, table))
         extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
-        extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen))
+        extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen, table))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -316,8 +329,10 @@ def main():
     ctx.close()
 
 
-def shift_extras(torch, q, ctx, dev, stream, latgen, np):
+def shift_extras(torch, q, ctx, dev, stream, latgen, np, table):
     """Shift expression chi = sum_mu U psi(x+mu) + a phi at 32^3x64 (FP64 and FP32-12)."""
+    from paper_1105_2279_amd import tuning
+
     Ls = (32, 32, 32, 64)
     V = latgen.volume(Ls)
     out = {}
@@ -332,7 +347,7 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
         chi = q.alloc_fermion(Ls, prec, dev)
         n2 = torch.zeros(1, dtype=torch.float64, device=dev)
         work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
-        q.qdpx_tune(ctx, q.OP_SHIFT, Ls, prec, fmt)
+        tuning.ensure(ctx, q.OP_SHIFT, prec, fmt, Ls, table)
 
         def call():
             q.qdpx_eval_shift_mul_axpy(ctx, Ls, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work, stream)
@@ -373,11 +388,13 @@ N_JACOBI = 20
 KAPPA_JACOBI = 0.21
 
 
-def jacobi_extras(torch, q, ctx, dev, stream, latgen):
+def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
     """The whole Jacobi routine (copy, N_JACOBI fused hop+axpy iterations,
     division by the norm) on the lattices of the paper's Table 1, FP32 with
     12-real and 18-real links and FP64, each call replayed from a HIP graph;
     plus the hop kernel alone at 32^3x64 against the HBM roofline."""
+    from paper_1105_2279_amd import tuning
+
     out = {}
     paths = (("sp_f32_12", q.F32, q.LINK12, 48, 96), ("sp_f32_18", q.F32, q.LINK18, 72, 96),
              ("dp_f64_18", q.F64, q.LINK18, 144, 192))
@@ -390,7 +407,7 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen):
             Ud = q.links_to_device(ctx, L, U, prec, fmt, dev)
             cd = q.fermion_to_device(ctx, L, chi, prec, dev)
             work = q.alloc_workspace(q.OP_JACOBI, L, prec, fmt, N_JACOBI, dev)
-            q.qdpx_tune(ctx, q.OP_JACOBI, L, prec, fmt)
+            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L, table)
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream()

@@ -263,9 +263,12 @@ int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdp
 
 /* -------------------------------------------------------------- autotuner
  * Time the candidate launch geometries of operation `op` (QDPX_OP_APE,
- * QDPX_OP_SHIFT, QDPX_OP_CHAIN or QDPX_OP_JACOBI) on `geom` and remember the fastest in the
- * context: threads per block, consecutive 64-site groups per wave, the
- * XCD-contiguous block order, and the number of t planes walked together.
+ * QDPX_OP_SHIFT, QDPX_OP_CHAIN or QDPX_OP_JACOBI) on `geom` and remember the
+ * fastest in the context: threads per block, consecutive 64-site groups per
+ * wave, the block order over the 8 XCDs (xcd_map 0: dispatch order; 1: each
+ * XCD a contiguous range of groups; 2: each XCD a slab of z planes walked t
+ * plane by t plane, used where the groups of a t plane split evenly over the
+ * XCDs, else order 0), and the number of t planes walked together.
  * This is the auto-tuning of the thread geometry the paper proposes
  * (sections 5.4 and 9).  Allocates and frees temporary device buffers and
  * synchronises the device, so it returns QDPX_ECAPTURE on a capturing

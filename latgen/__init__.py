@@ -20,6 +20,9 @@ the same bits.
 
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 __all__ = [
@@ -52,6 +55,20 @@ BATCH_CHOICES = ((8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32), (24, 24, 24, 
 def volume(L) -> int:
     Lx, Ly, Lz, Lt = (int(v) for v in L)
     return Lx * Ly * Lz * Lt
+
+
+def _slices(Lt, fill):
+    """Call fill(t) for every t-slice.  Each slice draws from its own
+    generator, so the result does not depend on the order or on the number of
+    threads; large lattices are filled by a thread pool (numpy releases the
+    interpreter lock inside its array operations)."""
+    workers = min(16, os.cpu_count() or 1, Lt)
+    if workers <= 1 or Lt < 8:
+        for t in range(Lt):
+            fill(t)
+        return
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(fill, range(Lt)))
 
 
 def _check_extents(L):
@@ -94,9 +111,11 @@ def haar_links(L, seed: int) -> np.ndarray:
     Lx, Ly, Lz, Lt = _check_extents(L)
     out = np.empty((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=np.complex128)
     per_slice = Lz * Ly * Lx * 4
-    for t in range(Lt):
-        rng = np.random.default_rng([seed, t])
-        out[t] = haar_su3(rng, per_slice).reshape(Lz, Ly, Lx, 4, 3, 3)
+
+    def fill(t):
+        out[t] = haar_su3(np.random.default_rng([seed, t]), per_slice).reshape(Lz, Ly, Lx, 4, 3, 3)
+
+    _slices(Lt, fill)
     return out
 
 
@@ -116,20 +135,23 @@ def _gell_mann() -> np.ndarray:
 def near_unit_links(L, seed: int, eps: float = 0.1) -> np.ndarray:
     """Links ``exp(i*eps*H)`` with ``H = sum_a w_a lambda_a / 2``, ``w_a ~ N(0,1)``.
 
-    The exponential of the Hermitian traceless H is taken through its
-    eigen-decomposition.
+    The matrix exponential is the library routine (torch.linalg.matrix_exp,
+    on the CPU, one call per t-slice).
     """
+    import torch
+
     Lx, Ly, Lz, Lt = _check_extents(L)
     lam_half = _gell_mann() / 2.0
     out = np.empty((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=np.complex128)
     per_slice = Lz * Ly * Lx * 4
-    for t in range(Lt):
-        rng = np.random.default_rng([seed, t])
-        w = rng.standard_normal((per_slice, 8))
+
+    def fill(t):
+        w = np.random.default_rng([seed, t]).standard_normal((per_slice, 8))
         h = np.einsum("na,aij->nij", w, lam_half)
-        evals, evecs = np.linalg.eigh(h)
-        u = np.einsum("nij,nj,nkj->nik", evecs, np.exp(1j * eps * evals), evecs.conj())
+        u = torch.linalg.matrix_exp(torch.from_numpy(1j * eps * h)).numpy()
         out[t] = u.reshape(Lz, Ly, Lx, 4, 3, 3)
+
+    _slices(Lt, fill)
     return out
 
 
@@ -144,9 +166,11 @@ def dirac_field(L, seed: int) -> np.ndarray:
     """Dirac field with 4 spins x 3 colours, re/im parts i.i.d. N(0,1)."""
     Lx, Ly, Lz, Lt = _check_extents(L)
     out = np.empty((Lt, Lz, Ly, Lx, 4, 3), dtype=np.complex128)
-    for t in range(Lt):
-        rng = np.random.default_rng([seed, t])
-        out[t] = _complex_gaussian(rng, (Lz, Ly, Lx, 4, 3))
+
+    def fill(t):
+        out[t] = _complex_gaussian(np.random.default_rng([seed, t]), (Lz, Ly, Lx, 4, 3))
+
+    _slices(Lt, fill)
     return out
 
 
@@ -154,9 +178,11 @@ def haar_gauge(L, seed: int) -> np.ndarray:
     """One Haar SU(3) matrix per site, shape (Lt, Lz, Ly, Lx, 3, 3)."""
     Lx, Ly, Lz, Lt = _check_extents(L)
     out = np.empty((Lt, Lz, Ly, Lx, 3, 3), dtype=np.complex128)
-    for t in range(Lt):
-        rng = np.random.default_rng([seed, t])
-        out[t] = haar_su3(rng, Lz * Ly * Lx).reshape(Lz, Ly, Lx, 3, 3)
+
+    def fill(t):
+        out[t] = haar_su3(np.random.default_rng([seed, t]), Lz * Ly * Lx).reshape(Lz, Ly, Lx, 3, 3)
+
+    _slices(Lt, fill)
     return out
 
 

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
-        const int grp = xcd == 2 ? colwalk(g, i, gpb * NS) : traverse(g, i, tw);
+        const int grp = xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
         ape_group<R, NR, MODE>(g, U, out, c1, c2, mask, partials, grp, mu, lane);
     }
 }

@@ -715,29 +715,42 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    float best = 1e30f;
-    LaunchCfg best_cfg;
     const int nrows = nrows_of(fmt);
-    for (const LaunchCfg &c : cands) {
-        auto run = [&]() -> hipError_t {
-            if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, 0xFu, nullptr, 0, c, st);
-            if (op == QDPX_OP_JACOBI) return launch_hop(g, prec, nrows, U, A, B, 0.1, 1.0, false, 0xFu, C, c, st);
-            return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c,
-                                st);
-        };
-        if (run() != hipSuccess) continue;
+    auto run = [&](const LaunchCfg &c) -> hipError_t {
+        if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, 0xFu, nullptr, 0, c, st);
+        if (op == QDPX_OP_JACOBI) return launch_hop(g, prec, nrows, U, A, B, 0.1, 1.0, false, 0xFu, C, c, st);
+        return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c, st);
+    };
+    // milliseconds per launch over `reps` back-to-back launches
+    auto time_cfg = [&](const LaunchCfg &c, int reps) -> float {
         hipEventRecord(e0, st);
-        const int reps = 5;
-        for (int r = 0; r < reps; ++r) run();
+        for (int r = 0; r < reps; ++r) run(c);
         hipEventRecord(e1, st);
         hipEventSynchronize(e1);
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
-            best_cfg = c;
-        }
+        return ms / reps;
+    };
+    // Round 1: every candidate once (after one warm-up launch).  Round 2: the
+    // six fastest again, interleaved over five passes, keeping each one's
+    // best pass, so that a single slow or fast sample does not decide.
+    std::vector<std::pair<float, int>> r1;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        if (run(cands[i]) != hipSuccess) continue;
+        r1.push_back({time_cfg(cands[i], 5), (int)i});
     }
+    std::sort(r1.begin(), r1.end());
+    const size_t keep = std::min<size_t>(6, r1.size());
+    std::vector<float> best_ms(keep, 1e30f);
+    for (int pass = 0; pass < 5; ++pass)
+        for (size_t k = 0; k < keep; ++k) best_ms[k] = std::min(best_ms[k], time_cfg(cands[r1[k].second], 10));
+    LaunchCfg best_cfg;
+    float best = 1e30f;
+    for (size_t k = 0; k < keep; ++k)
+        if (best_ms[k] < best) {
+            best = best_ms[k];
+            best_cfg = cands[r1[k].second];
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     release();

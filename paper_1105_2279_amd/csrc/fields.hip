@@ -30,7 +30,7 @@ Geo make_geo(const int32_t L[4]) {
     return g;
 }
 
-// The block order a launch uses: the XCD column walk (mode 2) only where its
+// The block order a launch uses: the XCD slab walk (mode 2) only where its
 // preconditions hold, else the identity order.
 int launch_order(const Geo &g, const LaunchCfg &cfg, int groups_per_block) {
     if (cfg.xcd != 2) return cfg.xcd;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * nwb + wave) * NS + j;
         if (i >= ngroups) return;  // whole wave leaves together
-        const int grp = xcd == 2 ? colwalk(g, i, nwb * NS) : traverse(g, i, tw);
+        const int grp = xcd == 2 ? slabwalk(g, i, nwb * NS) : traverse(g, i, tw);
         double n2 = 0.0;
         Site x;
         if (group_site(g, grp, lane, x)) {
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * nwb + wave) * NS + j;
         if (i >= ngroups) return;
-        const int grp = xcd == 2 ? colwalk(g, i, nwb * NS) : traverse(g, i, tw);
+        const int grp = xcd == 2 ? slabwalk(g, i, nwb * NS) : traverse(g, i, tw);
         Site x;
         if (!group_site(g, grp, lane, x)) continue;
         const int s = x.s;
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
             if (!((mask >> mu) & 1u)) continue;  // wave-uniform
             {
                 M3<R> u;
-                U.full_stream(mu, s, u);  // U_mu(x): read once per site in this pass
+                U.full(mu, s, u);  // U_mu(x), read again as the backward link of x+mu
                 const int f = hop_fwd(g, s, x.c[mu], mu);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp) {

@@ -13,7 +13,7 @@ namespace qdpx {
 struct LaunchCfg {
     int block = 256;  // threads per block, multiple of 64
     int nsite = 1;    // consecutive 64-site groups handled per wave
-    int xcd = 1;      // 0: identity, 1: XCD-contiguous tile ranges, 2: XCD column walk
+    int xcd = 1;      // 0: identity, 1: XCD-contiguous tile ranges, 2: XCD slab walk
     int tw = 1;       // t planes walked together (brick mapping only; must divide Lt)
 };
 

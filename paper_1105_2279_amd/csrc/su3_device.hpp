@@ -85,17 +85,22 @@ __device__ __forceinline__ int traverse(const Geo &g, int i, int tw) {
     return pz + plane * (tc * tw + tin);
 }
 
-// Launch order -> group, XCD column walk.  Blocks are dispatched to the 8
-// XCDs round-robin (block b runs on XCD b % 8).  With m groups per block, the
-// groups of XCD x are the columns c = x (mod 8) of the (column, t) grid
-// group = c + ncol * t, walked through t: every t neighbour a block needs is
-// handled on the same XCD just before or after it.  Requires ncol % 8 == 0
-// and num_groups % (8 m) == 0 (checked on the host).  A bijection.
-__device__ __forceinline__ int colwalk(const Geo &g, int i, int m) {
+// Launch order -> group, XCD slab walk.  Blocks are dispatched to the 8
+// XCDs round-robin (block b runs on XCD b % 8).  The ncol groups of a t plane
+// (column index c = brick + P z) are split into 8 contiguous ranges of
+// ncol / 8 columns, a slab of z planes, and XCD x takes range x in every t
+// plane, walking its slab t plane by t plane.  A group's x, y and z
+// neighbours then lie in the same slab a few groups away, and its t
+// neighbours ncol / 8 groups away, all handled on the same XCD close together
+// in time, so they are served from that XCD's L2.  Requires ncol % 8 == 0 and
+// num_groups % (8 m) == 0 for m groups per block (checked on the host).
+// A bijection.
+__device__ __forceinline__ int slabwalk(const Geo &g, int i, int m) {
     const int blk = i / m, within = i - blk * m;
     const int x = blk & 7, jj = (blk >> 3) * m + within;
-    const int k = jj / g.L[3], t = jj - k * g.L[3];
-    return (x + 8 * k) + g.ncol * t;
+    const int cx = g.ncol >> 3;
+    const int t = jj / cx, k = jj - t * cx;
+    return (x * cx + k) + g.ncol * t;
 }
 
 __device__ __forceinline__ int hop_fwd(const Geo &g, int s, int cmu, int mu) {
@@ -123,6 +128,21 @@ template <typename T> __device__ __forceinline__ const __attribute__((address_sp
 }
 template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T *gptr_w(void *p) {
     return (__attribute__((address_space(1))) T *)p;
+}
+
+// Component bases are wave-uniform.  Passing one through an empty asm with an
+// SGPR constraint makes it an opaque scalar value, so the compiler keeps
+// base + 32-bit site offset as one SGPR-base / VGPR-offset global access
+// instead of re-associating the sum into 64-bit per-lane address arithmetic.
+template <typename T> __device__ __forceinline__ T *sbase(T *p) {
+    asm("" : "+s"(p));
+    return p;
+}
+// The per-lane byte offset likewise stays an opaque 32-bit value, so it is
+// never widened into a 64-bit multiply before the address is formed.
+__device__ __forceinline__ uint32_t voff(uint32_t o) {
+    asm("" : "+v"(o));
+    return o;
 }
 
 // Streaming (non-temporal) access to one complex element: the builtins need a
@@ -194,13 +214,13 @@ template <typename R, int NR> struct LinksRO {
     // and b are constants) and the site offset fits 32 bits (V < 2^28), so
     // every load is one SGPR base + one 32-bit VGPR offset.
     __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
-        const vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
-        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
+        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
         return Cx<R>{v.x, v.y};
     }
     __device__ __forceinline__ Cx<R> ld_stream(int mu, int a, int b, int s) const {
-        const vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
-        return load_stream<R>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
+        return load_stream<R>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
     }
     // full link read once per site (no neighbour reuse): streamed
     __device__ __forceinline__ void full_stream(int mu, int s, M3<R> &m) const {
@@ -234,10 +254,10 @@ template <typename R, int NR> struct LinksWO {
     vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ void st(int mu, int a, int b, int s, R re, R im) const {
-        vec2_t<R> *base = p + (int64_t)((mu * NR + a) * 3 + b) * S;
+        vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
         // outputs are never re-read by the kernel that writes them: stream
         // them past the caches so L2 keeps the neighbour links
-        store_stream<R>((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>), re, im);
+        store_stream<R>((char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), re, im);
     }
 };
 
@@ -247,22 +267,22 @@ template <typename R> struct FermRO {
     const vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ Cx<R> ld(int sp, int c, int s) const {
-        const vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
-        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
+        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
         return Cx<R>{v.x, v.y};
     }
     // a field read once per site (no neighbour reuse): stream it
     __device__ __forceinline__ Cx<R> ld_stream(int sp, int c, int s) const {
-        const vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
-        return load_stream<R>((const char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>));
+        const vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
+        return load_stream<R>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
     }
 };
 template <typename R> struct FermWO {
     vec2_t<R> *__restrict__ p;
     int64_t S;
     __device__ __forceinline__ void st(int sp, int c, int s, const Cx<R> &z) const {
-        vec2_t<R> *base = p + (int64_t)(sp * 3 + c) * S;
-        store_stream<R>((char *)base + (uint32_t)s * (uint32_t)sizeof(vec2_t<R>), z.re, z.im);
+        vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
+        store_stream<R>((char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), z.re, z.im);
     }
 };
 

@@ -1,0 +1,206 @@
+"""The large single lattice, 48^3 x 96 (10,616,832 sites), on the GPU.
+
+At this size the oracle evaluates sampled outputs one by one, and properties
+that hold at any size are checked on the whole lattice:
+
+* one APE step, Haar and near-unit links, FP64-18 and FP32-12: 4000 sampled
+  links against the oracle (1e-12 / 1e-5);
+* 20 APE steps of unit links stay unit links (fixed point), plaquette 1;
+* 20 APE steps, FP32-12 against the plain FP64 GPU path, Haar links: the
+  largest entry difference per the stated 1e-5 per step, unitarity and
+  determinant defects of the FP32 result, rising plaquette;
+* the shift expression on Haar links and fields: 4000 sampled sites against
+  the oracle;
+* the chain psi <- psi - c (sum_mu U_mu(x) psi(x+mu) + a phi), 8 iterations,
+  on pure-gauge links U_mu(x) = g(x) g(x+mu)^dag with psi and phi the gauge
+  transform of one plane wave: every iterate is that plane wave times a
+  scalar that follows from a two-term recurrence, so the whole field and
+  the eight norms are known in closed form.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import latgen
+import oracle
+import paper_1105_2279_amd as q
+from gpuhelp import ctx, dev, need_gpu, tol
+
+pytestmark = pytest.mark.gpu
+
+L = (48, 48, 48, 96)
+V = 48 * 48 * 48 * 96
+SEEDS = latgen.SEEDS["large_48x48x48x96"]
+N_SAMPLE = 4000
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.fixture(scope="module")
+def haar():
+    print("generating 48^3x96 Haar links", flush=True)
+    return latgen.haar_links(L, SEEDS["links_haar"])
+
+
+@pytest.fixture(scope="module")
+def near_unit():
+    print("generating 48^3x96 near-unit links", flush=True)
+    return latgen.near_unit_links(L, SEEDS["links_near_unit"])
+
+
+def unpack_device(c, soa, prec, fmt):
+    """SoA links -> device AoS complex128 tensor (V, 4, 3, 3)."""
+    aos = torch.empty((V, 4, 3, 3, 2), dtype=torch.float64, device=dev())
+    q.qdpx_unpack_links(c, L, soa, prec, fmt, aos)
+    return torch.view_as_complex(aos)
+
+
+def smear(c, Ud, prec, fmt, n, plaq=None):
+    out = q.alloc_links(L, prec, fmt, dev())
+    work = q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev())
+    q.qdpx_ape_smear(c, L, prec, fmt, Ud, out, 0.5, n, plaq, work)
+    del work
+    return out
+
+
+def su3_defects_device(Vm, chunk=1 << 22):
+    """(max ||V^dag V - 1||_F, max |det V - 1|) over (n, 3, 3) complex128 on the device, in chunks, by
+    explicit sums (no batched library products)."""
+    eye = torch.eye(3, dtype=torch.complex128, device=Vm.device)
+    u = d = 0.0
+    for i in range(0, Vm.shape[0], chunk):
+        m = Vm[i:i + chunk]
+        gram = (m.conj().unsqueeze(-1) * m.unsqueeze(-2)).sum(-3) - eye  # sum_k conj(m_ki) m_kj
+        u = max(u, float(gram.abs().square().sum((-1, -2)).sqrt().max()))
+        det = (m[:, 0, 0] * (m[:, 1, 1] * m[:, 2, 2] - m[:, 1, 2] * m[:, 2, 1])
+               - m[:, 0, 1] * (m[:, 1, 0] * m[:, 2, 2] - m[:, 1, 2] * m[:, 2, 0])
+               + m[:, 0, 2] * (m[:, 1, 0] * m[:, 2, 1] - m[:, 1, 1] * m[:, 2, 0]))
+        d = max(d, float((det - 1.0).abs().max()))
+    return u, d
+
+
+def samples(seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, V, N_SAMPLE), rng.integers(0, 4, N_SAMPLE)
+
+
+@pytest.mark.parametrize("prec,fmt", [(q.F64, q.LINK18), (q.F32, q.LINK12)], ids=["f64_18", "f32_12"])
+@pytest.mark.parametrize("kind", ["haar", "near_unit"])
+def test_one_step_sampled(request, kind, prec, fmt):
+    U = request.getfixturevalue(kind)
+    c = ctx()
+    Ud = q.links_to_device(c, L, U, prec, fmt, dev())
+    out = smear(c, Ud, prec, fmt, 1)
+    sites, mus = samples(11)
+    got = unpack_device(c, out, prec, fmt)[torch.from_numpy(sites).to(dev()), torch.from_numpy(mus).to(dev())]
+    ref = oracle.ape_links(U, 0.5, sites, mus)
+    err = float(np.max(np.abs(got.cpu().numpy() - ref)))
+    print(f"{kind} {prec}/{fmt}: max |dV| over {N_SAMPLE} sampled links {err:.2e}", flush=True)
+    assert err < tol(prec)
+
+
+def test_unit_links_fixed_point_20_steps():
+    c = ctx()
+    for prec, fmt, bound in ((q.F64, q.LINK18, 1e-14), (q.F32, q.LINK12, 1e-6)):
+        Ud = q.links_to_device(c, L, latgen.unit_links(L), prec, fmt, dev())
+        plaq = torch.zeros(3 * 21, dtype=torch.float64, device=dev())
+        out = smear(c, Ud, prec, fmt, 20, plaq)
+        Vd = unpack_device(c, out, prec, fmt)
+        eye = torch.eye(3, dtype=torch.complex128, device=dev())
+        assert float((Vd - eye).abs().max()) <= bound
+        assert float((plaq - 1.0).abs().max()) <= bound
+        del Ud, out, Vd
+
+
+def test_20_steps_fp32_12_against_fp64_path(haar):
+    c = ctx()
+    res = {}
+    for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        Ud = q.links_to_device(c, L, haar, prec, fmt, dev())
+        plaq = torch.zeros(3 * 21, dtype=torch.float64, device=dev())
+        out = smear(c, Ud, prec, fmt, 20, plaq)
+        del Ud
+        res[fmt] = (unpack_device(c, out, prec, fmt), plaq.cpu().numpy().reshape(-1, 3))
+        del out
+    V64, p64 = res[q.LINK18]
+    V32, p32 = res[q.LINK12]
+    d = float((V32 - V64).abs().max())
+    udef, ddef = su3_defects_device(V32.reshape(-1, 3, 3))
+    dp = float(np.max(np.abs(p32 - p64)))
+    print(f"20 steps 48^3x96: max |V32 - V64| {d:.2e}; FP32 unitarity defect {udef:.2e}, det defect {ddef:.2e}; "
+          f"max plaquette difference {dp:.2e}; plaquette {p64[0, 0]:.6f} -> {p64[-1, 0]:.6f}", flush=True)
+    assert d < 20 * tol(q.F32)
+    assert udef < 1e-6 and ddef < 1e-6
+    assert dp < 20 * tol(q.F32)
+    assert np.all(np.diff(p64[:, 0]) > 0)  # the plaquette rises at every step
+
+
+def test_shift_sampled(haar):
+    psi = latgen.dirac_field(L, SEEDS["psi"])
+    phi = latgen.dirac_field(L, SEEDS["phi"])
+    sites, _ = samples(12)
+    ref = oracle.shift_sites(haar, psi, phi, 0.3, sites)
+    c = ctx()
+    for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        Ud = q.links_to_device(c, L, haar, prec, fmt, dev())
+        pd = q.fermion_to_device(c, L, psi, prec, dev())
+        fd = q.fermion_to_device(c, L, phi, prec, dev())
+        chi = q.alloc_fermion(L, prec, dev())
+        n2 = torch.zeros(1, dtype=torch.float64, device=dev())
+        work = q.alloc_workspace(q.OP_SHIFT, L, prec, fmt, 1, dev())
+        q.qdpx_eval_shift_mul_axpy(c, L, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work)
+        aos = torch.empty((V, 4, 3, 2), dtype=torch.float64, device=dev())
+        q.qdpx_unpack_fermion(c, L, chi, prec, aos)
+        got = torch.view_as_complex(aos)[torch.from_numpy(sites).to(dev())].cpu().numpy()
+        rel = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        print(f"shift {prec}/{fmt}: sampled max rel error {rel:.2e}", flush=True)
+        assert rel < tol(prec)
+        del Ud, pd, fd, chi, work, aos
+
+
+def test_chain_pure_gauge_plane_wave_closed_form():
+    a, cc, n = 0.3, 0.1, 8
+    k = 2 * np.pi * np.array([1 / 48, 2 / 48, 5 / 48, 3 / 96])
+    beta = 0.7 - 0.2j
+    g = latgen.haar_gauge(L, 1509)
+    # U_mu(x) = g(x) g(x+mu)^dag
+    U = np.empty(g.shape[:4] + (4, 3, 3), dtype=np.complex128)
+    for mu, ax in enumerate((3, 2, 1, 0)):
+        U[..., mu, :, :] = g @ np.conj(np.swapaxes(np.roll(g, -1, axis=ax), -1, -2))
+    # psi_0(x) = g(x) e^{i k.x} v, phi = beta psi_0
+    rng = np.random.default_rng(1510)
+    v = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    t, z, y, x = np.meshgrid(*(np.arange(e) for e in (96, 48, 48, 48)), indexing="ij")
+    phase = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z + k[3] * t))
+    psi0 = np.einsum("...ab,sb->...sa", g, v) * phase[..., None, None]
+    del g, t, z, y, x, phase
+    h = np.sum(np.exp(1j * k))
+    # chi_j = h alpha_{j-1} psi_0 + a beta psi_0; alpha_j = alpha_{j-1} - c (h alpha_{j-1} + a beta)
+    alpha, norms = 1.0 + 0j, []
+    n0 = float(np.sum(np.abs(psi0) ** 2))
+    for _ in range(n):
+        coef = h * alpha + a * beta
+        norms.append(abs(coef) ** 2 * n0)
+        alpha = alpha - cc * coef
+    c = ctx()
+    for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        Ud = q.links_to_device(c, L, U, prec, fmt, dev())
+        pd = q.fermion_to_device(c, L, psi0, prec, dev())
+        fd = q.fermion_to_device(c, L, beta * psi0, prec, dev())
+        nd = torch.zeros(n, dtype=torch.float64, device=dev())
+        work = q.alloc_workspace(q.OP_CHAIN, L, prec, fmt, n, dev())
+        q.qdpx_shift_chain(c, L, prec, fmt, Ud, pd, fd, a, cc, n, nd, work)
+        aos = torch.empty((V, 4, 3, 2), dtype=torch.float64, device=dev())
+        q.qdpx_unpack_fermion(c, L, pd, prec, aos)
+        got = torch.view_as_complex(aos)
+        exp = torch.from_numpy(alpha * psi0.reshape(V, 4, 3)).to(dev())
+        rel = float(torch.linalg.vector_norm(got - exp) / torch.linalg.vector_norm(exp))
+        nrel = float(np.max(np.abs(nd.cpu().numpy() - norms) / np.array(norms)))
+        print(f"chain {prec}/{fmt}: field rel error {rel:.2e}, norm rel error {nrel:.2e}", flush=True)
+        assert rel < n * tol(prec)
+        assert nrel < n * tol(prec)
+        del Ud, pd, fd, nd, work, aos, got, exp

@@ -185,7 +185,7 @@ def test_ape_32x32x32x64_sampled(big_links, prec, fmt):
 def test_geometries_are_bit_identical(L):
     # (8, 6, 4, 10): V = 1920, 64-site groups of consecutive sites and partial
     # last tiles; (16, 8, 4, 8): 16x4 bricks, where the t window and the XCD
-    # column walk reorder groups
+    # slab walk reorder groups
     U = latgen.haar_links(L, 61)
     psi, phi = latgen.dirac_field(L, 62), latgen.dirac_field(L, 63)
     c = ctx()
