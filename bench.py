@@ -56,34 +56,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources of the APE step kernel; the counter summary in profiles/ records
+# Sources of each counted kernel; a counter summary in profiles/ records
 # their hash, and its HBM traffic is reported only while they are unchanged.
-KERNEL_SOURCES = ["su3_device.hpp", "ape_device.hpp", "ape.hip", "qdpx_impl.hpp"]
-COUNTERS_MD = os.path.join(ROOT, "profiles", "ape_step_32x32x32x64_counters.md")
+APE_SOURCES = ["su3_device.hpp", "ape_device.hpp", "ape.hip", "qdpx_impl.hpp"]
+HOP_SOURCES = ["su3_device.hpp", "fields.hip", "qdpx_impl.hpp"]
+APE_COUNTERS_MD = os.path.join(ROOT, "profiles", "ape_step_32x32x32x64_counters.md")
+HOP_COUNTERS_MD = os.path.join(ROOT, "profiles", "jacobi_hop_32x32x32x64_counters.md")
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1105_2279_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of the roofline kernel from the committed counter
-    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None if the summary is
-    missing or was taken on different kernel sources."""
+def measured_traffic(md, sources, name):
+    """HBM bytes per launch of one kernel from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None
+    if the summary is missing or was taken on different kernel sources."""
     try:
-        text = open(COUNTERS_MD).read()
+        text = open(md).read()
     except OSError:
         return None
     import re
 
     m = re.search(r"source hash: `([0-9a-f]+)`", text)
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(sources):
         return None
     m = re.search(r"traffic %s: ([0-9.eE+]+) bytes per launch" % re.escape(name), text)
     return float(m.group(1)) if m else None
@@ -267,7 +269,7 @@ def main():
             "peak": round(PEAK_VALU_TFLOPS, 2),
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
-            "traffic": measured_traffic(name),
+            "traffic": measured_traffic(APE_COUNTERS_MD, APE_SOURCES, name),
             "kernel": {"f32_12": "k_ape_step<float,2>", "f64_18": "k_ape_step<double,3>",
                        "f32_18": "k_ape_step<float,3>"}[name],
             "kernel_us": round(t_k * 1e6, 2),
@@ -431,7 +433,9 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
                 # compulsory bytes: 4 links, psi, out (the iteration adds s0)
                 gbs = (4 * link_b + 2 * ferm_b) * V / t / 1e9
                 row[name]["hop_kernel"] = {"us": round(t * 1e6, 2), "hbm_gbs_algorithmic": round(gbs, 1),
-                                           "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+                                           "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                                           "traffic": measured_traffic(HOP_COUNTERS_MD, HOP_SOURCES,
+                                                                       name.split("_", 1)[1])}
                 del h
             log(f"jacobi {L} {name}: {ms:.3f} ms / {N_JACOBI} iterations, {gflops:.0f} GFLOPS")
             del Ud, cd, work, g

@@ -256,36 +256,43 @@ hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const 
 // out(x) = [s0(x) + kappa * (H psi)(x)] / norm, with
 // (H psi)(x) = sum_{mu in mask} [U_mu(x) psi(x+mu) + U_mu(x-mu)^dag psi(x-mu)],
 // the hopping term of the smearing operator K.  s0 may be absent (then
-// out = kappa H psi / norm); DIV selects the division by norm.  Same site
-// mapping and launch orders as the shift expression.
+// out = kappa H psi / norm); DIV selects the division by norm.
+//
+// A block of 256 threads holds one 64-site group per iteration and wave w
+// computes direction mu = w: its forward and backward hop for all 12 spinor
+// components, so the four directions' loads are in flight at once rather
+// than one direction after another.  The four partial sums meet in LDS:
+// every wave writes its twelve components and, after a barrier, wave w adds
+// the four partials of spin w in direction order, applies s0, kappa and
+// norm, and stores spin w.  The order of every sum is fixed,
+// so each site's result does not depend on the launch geometry.
 template <typename R, int NR, int NS, bool DIV>
 __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> s0, R kappa, R norm,
                                               unsigned mask, FermWO<R> out, int xcd, int tw) {
-    const int nwb = blockDim.x >> 6;
+    __shared__ vec2_t<R> part[4][12][64];  // [direction][component][lane]
     const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int mu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int ngroups = num_groups(g);
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
-        const int i = (tile * nwb + wave) * NS + j;
+        const int i = tile * NS + j;  // the same for the four waves
         if (i >= ngroups) return;
-        const int grp = xcd == 2 ? slabwalk(g, i, nwb * NS) : traverse(g, i, tw);
+        const int grp = xcd == 2 ? slabwalk(g, i, NS) : traverse(g, i, tw);
         Site x;
-        if (!group_site(g, grp, lane, x)) continue;
+        const bool live = group_site(g, grp, lane, x);
         const int s = x.s;
         Cx<R> acc[4][3];
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
-#pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
-            if (!((mask >> mu) & 1u)) continue;  // wave-uniform
+        const int cmu = coord(x, mu);
+        if (live && ((mask >> mu) & 1u)) {
             {
                 M3<R> u;
-                U.full(mu, s, u);  // U_mu(x), read again as the backward link of x+mu
-                const int f = hop_fwd(g, s, x.c[mu], mu);
+                U.full(mu, s, u);  // U_mu(x), also the backward link of x+mu
+                const int f = hop_fwd(g, s, cmu, mu);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp) {
                     Cx<R> p[3];
@@ -298,7 +305,7 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
                 }
             }
             {
-                const int b = hop_bwd(g, s, x.c[mu], mu);
+                const int b = hop_bwd(g, s, cmu, mu);
                 M3<R> u;
                 U.full(mu, b, u);  // U_mu(x-mu)
 #pragma unroll
@@ -314,13 +321,37 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
                 }
             }
         }
+        if (j > 0) __syncthreads();  // the previous group's partials have been read
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                Cx<R> v = acc[sp][cc];
+                vec2_t<R> v;
+                v.x = acc[sp][cc].re;
+                v.y = acc[sp][cc].im;
+                part[mu][3 * sp + cc][lane] = v;
+            }
+        __syncthreads();
+        // spin mu's component bases, formed outside the per-lane branch
+        const vec2_t<R> *zb[3];
+        vec2_t<R> *ob[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            zb[cc] = s0.p ? s0.base(mu, cc) : nullptr;
+            ob[cc] = out.base(mu, cc);
+        }
+        if (live) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Cx<R> v{(R)0, (R)0};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {  // directions in order
+                    const vec2_t<R> q = part[w][3 * mu + cc][lane];
+                    v.re += q.x;
+                    v.im += q.y;
+                }
                 if (s0.p) {
-                    const Cx<R> z = s0.ld_stream(sp, cc, s);
+                    const Cx<R> z = s0.ld_at(zb[cc], s);
                     v.re = fma(kappa, v.re, z.re);
                     v.im = fma(kappa, v.im, z.im);
                 } else {
@@ -331,8 +362,9 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
                     v.re = v.re / norm;
                     v.im = v.im / norm;
                 }
-                out.st(sp, cc, s, v);
+                out.st_at(ob[cc], s, v);
             }
+        }
     }
 }
 
@@ -344,14 +376,14 @@ static void hop_dispatch_ns(const Geo &g, const void *U, const void *psi, const 
     FermRO<R> p{(const V *)psi, g.S}, z{(const V *)s0, g.S};
     FermWO<R> o{(V *)out, g.S};
     const int groups = (g.V + 63) / 64;
-    const int per_block = (cfg.block / 64) * cfg.nsite;
+    const int per_block = cfg.nsite;  // one 64-site group per iteration, four waves
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
     switch (cfg.nsite) {
-    case 2: k_hop<R, NR, 2, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
-    case 4: k_hop<R, NR, 4, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
-    case 8: k_hop<R, NR, 8, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
-    default: k_hop<R, NR, 1, DIV><<<grid, cfg.block, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    case 2: k_hop<R, NR, 2, DIV><<<grid, 256, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    case 4: k_hop<R, NR, 4, DIV><<<grid, 256, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    case 8: k_hop<R, NR, 8, DIV><<<grid, 256, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
+    default: k_hop<R, NR, 1, DIV><<<grid, 256, 0, st>>>(g, u, p, z, (R)kappa, (R)norm, mask, o, xcd, cfg.tw); break;
     }
 }
 

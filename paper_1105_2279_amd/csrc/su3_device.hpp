@@ -103,6 +103,12 @@ __device__ __forceinline__ int slabwalk(const Geo &g, int i, int m) {
     return (x * cx + k) + g.ncol * t;
 }
 
+// x.c[mu] for a wave-uniform but run-time mu, by selects: indexing the
+// per-lane array directly would place it in scratch memory.
+__device__ __forceinline__ int coord(const Site &x, int mu) {
+    return mu == 0 ? x.c[0] : mu == 1 ? x.c[1] : mu == 2 ? x.c[2] : x.c[3];
+}
+
 __device__ __forceinline__ int hop_fwd(const Geo &g, int s, int cmu, int mu) {
     return (cmu == g.L[mu] - 1) ? s - (g.L[mu] - 1) * g.st[mu] : s + g.st[mu];
 }
@@ -271,6 +277,12 @@ template <typename R> struct FermRO {
         const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
         return Cx<R>{v.x, v.y};
     }
+    // component base, for accesses whose component index is only wave-uniform
+    __device__ __forceinline__ const vec2_t<R> *base(int sp, int c) const { return sbase(p + (int64_t)(sp * 3 + c) * S); }
+    __device__ __forceinline__ Cx<R> ld_at(const vec2_t<R> *b, int s) const {
+        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
+        return Cx<R>{v.x, v.y};
+    }
     // a field read once per site (no neighbour reuse): stream it
     __device__ __forceinline__ Cx<R> ld_stream(int sp, int c, int s) const {
         const vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
@@ -283,6 +295,10 @@ template <typename R> struct FermWO {
     __device__ __forceinline__ void st(int sp, int c, int s, const Cx<R> &z) const {
         vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
         store_stream<R>((char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), z.re, z.im);
+    }
+    __device__ __forceinline__ vec2_t<R> *base(int sp, int c) const { return sbase(p + (int64_t)(sp * 3 + c) * S); }
+    __device__ __forceinline__ void st_at(vec2_t<R> *b, int s, const Cx<R> &z) const {
+        store_stream<R>((char *)b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), z.re, z.im);
     }
 };
 

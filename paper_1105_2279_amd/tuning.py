@@ -84,7 +84,7 @@ def main():
         print(f"{op} {prec} {fmt} {L}: {cfg}", flush=True)
     ctx.close()
     with open(args.out, "w") as fh:
-        json.dump({"device": torch.cuda.get_device_name(0), "entries": rows}, fh, indent=1)
+        json.dump({"device": torch.cuda.get_device_properties(0).gcnArchName, "entries": rows}, fh, indent=1)
         fh.write("\n")
     print(f"wrote {args.out}", flush=True)
 

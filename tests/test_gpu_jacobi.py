@@ -146,7 +146,7 @@ def test_jacobi_launch_geometry_bit_identical():
     c = q.Context(0)
     prec, fmt = q.F32, q.LINK12
     outs = []
-    for cfg in [(256, 1, 0, 1), (64, 2, 1, 1), (128, 4, 1, 2), (256, 1, 1, 4), (128, 1, 2, 1)]:
+    for cfg in [(256, 1, 0, 1), (256, 2, 1, 1), (256, 4, 1, 2), (256, 1, 1, 4), (256, 1, 2, 1), (256, 8, 0, 8)]:
         q.qdpx_tune_set(c, q.OP_JACOBI, L, prec, fmt, *cfg)
         Ud = q.links_to_device(c, L, U, prec, fmt, dev())
         cd = q.fermion_to_device(c, L, chi, prec, dev())
@@ -164,7 +164,7 @@ def test_jacobi_tune_and_graph_replay():
     prec, fmt = q.F32, q.LINK12
     q.qdpx_tune(c, q.OP_JACOBI, L, prec, fmt)
     cfg = q.qdpx_tune_get(c, q.OP_JACOBI, L, prec, fmt)
-    assert cfg[0] in (64, 128, 256)
+    assert cfg[0] == 256
     Ud = q.links_to_device(c, L, U, prec, fmt, dev())
     base = q.fermion_to_device(c, L, chi, prec, dev())
     cd = base.clone()
