@@ -402,8 +402,9 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
              ("dp_f64_18", q.F64, q.LINK18, 144, 192))
     for L, paper in JACOBI_PAPER_GFLOPS.items():
         V = latgen.volume(L)
-        U = latgen.haar_links(L, 3000 + L[0])
-        chi = latgen.dirac_field(L, 3001 + L[0])
+        seeds = latgen.SEEDS["jacobi_table1"]
+        U = latgen.haar_links(L, seeds["links"] + L[0])
+        chi = latgen.dirac_field(L, seeds["chi"] + L[0])
         row = {"paper_gtx480_gflops": paper}
         for name, prec, fmt, link_b, ferm_b in paths:
             Ud = q.links_to_device(ctx, L, U, prec, fmt, dev)

@@ -45,7 +45,9 @@ SEEDS = {
     "shift_16x16x16x32": {"links": 1205, "psi": 1206, "phi": 1207},
     "ape_32x32x32x64": {"links": 1305},
     "batch_64": {"extents": 1400, "first_lattice": 1405},
-    "large_48x48x48x96": {"links_haar": 1505, "links_near_unit": 1506, "psi": 1507, "phi": 1508},
+    "large_48x48x48x96": {"links_haar": 1505, "links_near_unit": 1506, "psi": 1507, "phi": 1508, "gauge": 1509},
+    # Jacobi smearing on the Table 1 lattices: seed + Lx
+    "jacobi_table1": {"links": 3000, "chi": 3001},
 }
 
 # Extents drawn for the 64-lattice batch (Lx, Ly, Lz, Lt).

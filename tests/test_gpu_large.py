@@ -166,7 +166,7 @@ def test_chain_pure_gauge_plane_wave_closed_form():
     a, cc, n = 0.3, 0.1, 8
     k = 2 * np.pi * np.array([1 / 48, 2 / 48, 5 / 48, 3 / 96])
     beta = 0.7 - 0.2j
-    g = latgen.haar_gauge(L, 1509)
+    g = latgen.haar_gauge(L, SEEDS["gauge"])
     # U_mu(x) = g(x) g(x+mu)^dag
     U = np.empty(g.shape[:4] + (4, 3, 3), dtype=np.complex128)
     for mu, ax in enumerate((3, 2, 1, 0)):
