@@ -288,37 +288,50 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
         const int cmu = coord(x, mu);
+        // spin mu's component bases (this wave stores spin mu), formed outside
+        // the per-lane branches; s0 of spin mu is fetched now so that its
+        // latency overlaps the hops and the exchange
+        const vec2_t<R> *zb[3];
+        vec2_t<R> *ob[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            zb[cc] = s0.p ? s0.base(mu, cc) : nullptr;
+            ob[cc] = out.base(mu, cc);
+        }
+        Cx<R> z[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) z[cc] = Cx<R>{(R)0, (R)0};
+        if (live && s0.p) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) z[cc] = s0.ld_at(zb[cc], s);
+        }
         if (live && ((mask >> mu) & 1u)) {
-            {
-                M3<R> u;
-                U.full(mu, s, u);  // U_mu(x), also the backward link of x+mu
-                const int f = hop_fwd(g, s, cmu, mu);
+            // every load of this direction first, then the arithmetic: one
+            // memory round trip per group
+            const int f = hop_fwd(g, s, cmu, mu), bk = hop_bwd(g, s, cmu, mu);
+            M3<R> uf, ub;
+            U.full(mu, s, uf);   // U_mu(x), also the backward link of x+mu
+            U.full(mu, bk, ub);  // U_mu(x-mu)
+            Cx<R> pf[4][3], pb[4][3];
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp) {
-                    Cx<R> p[3];
+            for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, f);
-#pragma unroll
-                    for (int ca = 0; ca < 3; ++ca)
-#pragma unroll
-                        for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], u.e[ca][cb], p[cb]);
+                for (int cb = 0; cb < 3; ++cb) {
+                    pf[sp][cb] = psi.ld(sp, cb, f);
+                    pb[sp][cb] = psi.ld(sp, cb, bk);
                 }
-            }
-            {
-                const int b = hop_bwd(g, s, cmu, mu);
-                M3<R> u;
-                U.full(mu, b, u);  // U_mu(x-mu)
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp) {
-                    Cx<R> p[3];
+            for (int sp = 0; sp < 4; ++sp) {
 #pragma unroll
-                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, b);
-                    // (U^dag p)_a = sum_b conj(U_ba) p_b
+                for (int ca = 0; ca < 3; ++ca)
 #pragma unroll
-                    for (int ca = 0; ca < 3; ++ca)
+                    for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], uf.e[ca][cb], pf[sp][cb]);
+                // (U^dag p)_a = sum_b conj(U_ba) p_b
 #pragma unroll
-                        for (int cb = 0; cb < 3; ++cb) cmac_ca(acc[sp][ca], u.e[cb][ca], p[cb]);
-                }
+                for (int ca = 0; ca < 3; ++ca)
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) cmac_ca(acc[sp][ca], ub.e[cb][ca], pb[sp][cb]);
             }
         }
         if (j > 0) __syncthreads();  // the previous group's partials have been read
@@ -332,14 +345,6 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
                 part[mu][3 * sp + cc][lane] = v;
             }
         __syncthreads();
-        // spin mu's component bases, formed outside the per-lane branch
-        const vec2_t<R> *zb[3];
-        vec2_t<R> *ob[3];
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            zb[cc] = s0.p ? s0.base(mu, cc) : nullptr;
-            ob[cc] = out.base(mu, cc);
-        }
         if (live) {
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
@@ -351,9 +356,8 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
                     v.im += q.y;
                 }
                 if (s0.p) {
-                    const Cx<R> z = s0.ld_at(zb[cc], s);
-                    v.re = fma(kappa, v.re, z.re);
-                    v.im = fma(kappa, v.im, z.im);
+                    v.re = fma(kappa, v.re, z[cc].re);
+                    v.im = fma(kappa, v.im, z[cc].im);
                 } else {
                     v.re *= kappa;
                     v.im *= kappa;
