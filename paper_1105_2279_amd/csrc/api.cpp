@@ -617,9 +617,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (c.xcd < 0 || c.xcd > 2) return false;
     if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
-    if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN)
-        return c.block <= 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
-    if (op == QDPX_OP_JACOBI)  // four waves per 64-site group, one per direction
+    if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN || op == QDPX_OP_JACOBI)  // four waves per group, one per direction
         return c.block == 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
     if (op == QDPX_OP_BATCHED) return c.block == 256 && c.nsite >= 1 && c.nsite <= 1024;  // nsite = groups per item
     return false;
@@ -699,7 +697,6 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     }
     std::vector<LaunchCfg> cands;
     const int blocks_ape[] = {256, 512};
-    const int blocks_shift[] = {64, 128, 256};
     const int ns_ape[] = {1, 2, 4};
     const int ns_shift[] = {1, 2, 4, 8};
     const int tws[] = {1, 2, 4, 8, 16};
@@ -709,11 +706,8 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
             if (op == QDPX_OP_APE) {
                 for (int b : blocks_ape)
                     for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x, tw});
-            } else if (op == QDPX_OP_JACOBI) {
-                for (int n : ns_shift) cands.push_back(LaunchCfg{256, n, x, tw});
             } else {
-                for (int b : blocks_shift)
-                    for (int n : ns_shift) cands.push_back(LaunchCfg{b, n, x, tw});
+                for (int n : ns_shift) cands.push_back(LaunchCfg{256, n, x, tw});
             }
         }
     hipEvent_t e0, e1;

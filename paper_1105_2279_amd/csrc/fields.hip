@@ -147,70 +147,121 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 }
 
 // ------------------------------------------------------- shift expression
-// One site per lane.  A wave handles NS consecutive groups of 64 sites; the
-// FP64 |chi|^2 of each 64-site group is reduced by a wave butterfly and
-// written as one partial, so the reduced value does not depend on the block
-// size, NS or the tile mapping.
+// chi(x) = sum_mu U_mu(x) psi(x+mu) + a phi(x); MODE 1 (one chain step)
+// stores psi(x) - c chi(x) instead of chi.  A block of 256 threads holds one
+// 64-site group per iteration and wave w computes direction mu = w for all 12
+// spinor components, so the four directions' loads are in flight together.
+// The four partial products meet in LDS; after a barrier wave w adds them in
+// direction order for spin w, adds a phi, forms the FP64 |chi|^2 of its three
+// components, and stores spin w.  The four waves' norms are added in wave
+// order and reduced by a wave butterfly into one partial per group, so
+// every sum has a fixed order and nothing depends on the launch geometry.
 template <typename R, int NR, int MODE, int NS>
 __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
                                                 FermWO<R> out, double *__restrict__ partials, int xcd, int tw) {
-    const int nwb = blockDim.x >> 6;
+    __shared__ vec2_t<R> part[4][12][64];  // [direction][component][lane]
+    __shared__ double nrm[4][64];          // [wave][lane]
     const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int mu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int ngroups = num_groups(g);
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
-        const int i = (tile * nwb + wave) * NS + j;
-        if (i >= ngroups) return;  // whole wave leaves together
-        const int grp = xcd == 2 ? slabwalk(g, i, nwb * NS) : traverse(g, i, tw);
-        double n2 = 0.0;
+        const int i = tile * NS + j;  // the same for the four waves
+        if (i >= ngroups) return;
+        const int grp = xcd == 2 ? slabwalk(g, i, NS) : traverse(g, i, tw);
         Site x;
-        if (group_site(g, grp, lane, x)) {
-            const int s = x.s;
-            Cx<R> acc[4][3];
+        const bool live = group_site(g, grp, lane, x);
+        const int s = x.s;
+        const int cmu = coord(x, mu);
+        // spin mu's component bases (this wave stores spin mu), formed outside
+        // the per-lane branches; phi and (MODE 1) psi of spin mu are fetched
+        // now so that their latency overlaps the products and the exchange
+        const vec2_t<R> *fb[3], *pb[3];
+        vec2_t<R> *ob[3];
 #pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
+        for (int cc = 0; cc < 3; ++cc) {
+            fb[cc] = phi.p ? phi.base(mu, cc) : nullptr;
+            pb[cc] = psi.base(mu, cc);
+            ob[cc] = out.base(mu, cc);
+        }
+        Cx<R> f0[3], p0[3];
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
-#pragma unroll 1
-            for (int mu = 0; mu < 4; ++mu) {
-                M3<R> u;
-                U.full_stream(mu, s, u);  // the shift expression reads each link once
-                const int f = hop_fwd(g, s, x.c[mu], mu);
+        for (int cc = 0; cc < 3; ++cc) f0[cc] = p0[cc] = Cx<R>{(R)0, (R)0};
+        if (live && phi.p) {
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp) {
-                    Cx<R> p[3];
+            for (int cc = 0; cc < 3; ++cc) f0[cc] = phi.ld_at(fb[cc], s);
+        }
+        if constexpr (MODE == 1) {
+            if (live) {
 #pragma unroll
-                    for (int cb = 0; cb < 3; ++cb) p[cb] = psi.ld(sp, cb, f);
-#pragma unroll
-                    for (int ca = 0; ca < 3; ++ca)
-#pragma unroll
-                        for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], u.e[ca][cb], p[cb]);
-                }
+                for (int cc = 0; cc < 3; ++cc) p0[cc] = psi.ld_at(pb[cc], s);
             }
+        }
+        Cx<R> acc[4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
+        if (live) {
+            const int f = hop_fwd(g, s, cmu, mu);
+            M3<R> u;
+            U.full_stream(mu, s, u);  // the shift expression reads each link once
+            Cx<R> pf[4][3];
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    Cx<R> v = acc[sp][cc];
-                    if (phi.p) {
-                        const Cx<R> f = phi.ld_stream(sp, cc, s);
-                        v.re = fma(a, f.re, v.re);
-                        v.im = fma(a, f.im, v.im);
-                    }
-                    n2 = fma((double)v.re, (double)v.re, fma((double)v.im, (double)v.im, n2));
-                    if constexpr (MODE == 1) {
-                        const Cx<R> p0 = psi.ld(sp, cc, s);
-                        v.re = fma(-c, v.re, p0.re);
-                        v.im = fma(-c, v.im, p0.im);
-                    }
-                    out.st(sp, cc, s, v);
+                for (int cb = 0; cb < 3; ++cb) pf[sp][cb] = psi.ld(sp, cb, f);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int ca = 0; ca < 3; ++ca)
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) cmac(acc[sp][ca], u.e[ca][cb], pf[sp][cb]);
+        }
+        if (j > 0) __syncthreads();  // the previous group's partials have been read
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                vec2_t<R> v;
+                v.x = acc[sp][cc].re;
+                v.y = acc[sp][cc].im;
+                part[mu][3 * sp + cc][lane] = v;
+            }
+        __syncthreads();
+        double n2 = 0.0;
+        if (live) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Cx<R> v{(R)0, (R)0};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {  // directions in order
+                    const vec2_t<R> q = part[w][3 * mu + cc][lane];
+                    v.re += q.x;
+                    v.im += q.y;
                 }
+                if (phi.p) {
+                    v.re = fma(a, f0[cc].re, v.re);
+                    v.im = fma(a, f0[cc].im, v.im);
+                }
+                n2 = fma((double)v.re, (double)v.re, fma((double)v.im, (double)v.im, n2));
+                if constexpr (MODE == 1) {
+                    v.re = fma(-c, v.re, p0[cc].re);
+                    v.im = fma(-c, v.im, p0[cc].im);
+                }
+                out.st_at(ob[cc], s, v);
+            }
         }
         if (partials) {
-            const double w = wave_sum(n2);
-            if (lane == 0) partials[grp] = w;
+            nrm[mu][lane] = n2;
+            __syncthreads();
+            if (mu == 0) {
+                const double t = ((nrm[0][lane] + nrm[1][lane]) + nrm[2][lane]) + nrm[3][lane];
+                const double w = wave_sum(t);
+                if (lane == 0) partials[grp] = w;
+            }
         }
     }
 }
@@ -225,14 +276,14 @@ static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, cons
     FermRO<R> p{(const V *)psi, g.S}, f{(const V *)phi, g.S};
     FermWO<R> o{(V *)out, g.S};
     const int groups = (g.V + 63) / 64;
-    const int per_block = (cfg.block / 64) * cfg.nsite;  // 64-site groups per block
+    const int per_block = cfg.nsite;  // one 64-site group per iteration, four waves
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
     switch (cfg.nsite) {
-    case 2: k_shift<R, NR, MODE, 2><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    case 4: k_shift<R, NR, MODE, 4><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    case 8: k_shift<R, NR, MODE, 8><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    default: k_shift<R, NR, MODE, 1><<<grid, cfg.block, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 2: k_shift<R, NR, MODE, 2><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 4: k_shift<R, NR, MODE, 4><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 8: k_shift<R, NR, MODE, 8><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    default: k_shift<R, NR, MODE, 1><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
     }
 }
 
