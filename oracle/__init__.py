@@ -63,11 +63,13 @@ def lib():
         h.oracle_ape_w.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, _D]
         h.oracle_reunitarise.argtypes = [ctypes.c_long, _D, _D]
         h.oracle_reunitarise.restype = ctypes.c_long
-        h.oracle_ape_step.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, _D]
+        h.oracle_polar_project.argtypes = [ctypes.c_long, _D, _D]
+        h.oracle_polar_project.restype = ctypes.c_long
+        h.oracle_ape_step.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_int, _D]
         h.oracle_ape_step.restype = ctypes.c_long
-        h.oracle_ape_smear.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_int, _D]
+        h.oracle_ape_smear.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_int, ctypes.c_int, _D]
         h.oracle_ape_smear.restype = ctypes.c_long
-        h.oracle_ape_links.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_long, _L, _I, _D]
+        h.oracle_ape_links.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_int, ctypes.c_long, _L, _I, _D]
         h.oracle_ape_links.restype = ctypes.c_long
         h.oracle_plaquette.argtypes = [_I, _D, _D]
         h.oracle_shift_sites.argtypes = [_I, _D, _D, _D, ctypes.c_double, ctypes.c_long, _L, _D]
@@ -161,33 +163,44 @@ def reunitarise(W):
     return V, int(bad)
 
 
-def ape_step(U, alpha, mask=0xF):
-    """One APE step; links of directions outside mask are copied."""
+def polar_project(W):
+    """Polar (bi-covariant) projection of any (..., 3, 3) array; returns (V, n_degenerate)."""
+    W = _c(W)
+    V = np.empty_like(W)
+    n = W.size // 9
+    bad = lib().oracle_polar_project(n, _dp(W), _dp(V))
+    return V, int(bad)
+
+
+def ape_step(U, alpha, mask=0xF, proj=0):
+    """One APE step; links of directions outside mask are copied.  proj 0:
+    row Gram-Schmidt; 1: polar (bi-covariant) projection."""
     U = _c(U)
     V = np.empty_like(U)
-    bad = lib().oracle_ape_step(_extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), _dp(V))
+    bad = lib().oracle_ape_step(_extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), int(proj), _dp(V))
     if bad:
         raise FloatingPointError(f"{bad} degenerate links in the APE projection")
     return V
 
 
-def ape_smear(U, alpha, n_steps, mask=0xF):
+def ape_smear(U, alpha, n_steps, mask=0xF, proj=0):
     U = _c(U)
     V = np.empty_like(U)
-    bad = lib().oracle_ape_smear(_extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), int(n_steps), _dp(V))
+    bad = lib().oracle_ape_smear(_extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), int(proj), int(n_steps),
+                                 _dp(V))
     if bad:
         raise FloatingPointError(f"{bad} degenerate links in the APE projection")
     return V
 
 
-def ape_links(U, alpha, sites, mus, mask=0xF):
+def ape_links(U, alpha, sites, mus, mask=0xF, proj=0):
     """One APE step evaluated only at the given (flat site, mu) pairs; (n, 3, 3)."""
     U = _c(U)
     sites = np.ascontiguousarray(sites, dtype=np.int64)
     mus = np.ascontiguousarray(mus, dtype=np.int32)
     out = np.empty((sites.size, 3, 3), dtype=np.complex128)
     bad = lib().oracle_ape_links(
-        _extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), sites.size, sites.ctypes.data_as(_L),
+        _extents(U), _dp(U), float(alpha), ctypes.c_uint(mask), int(proj), sites.size, sites.ctypes.data_as(_L),
         mus.ctypes.data_as(_I), _dp(out)
     )
     if bad:

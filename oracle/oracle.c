@@ -374,6 +374,7 @@ void oracle_staple_sums(const int *L, const double *U, double *Sup, double *Slo)
 }
 
 static int reunitarise(const mat3 *W, mat3 *V);
+static int polar_project(const mat3 *W, mat3 *V);
 
 /* W_mu(x) = (1-alpha) U_mu(x) + alpha * (mean of the staples of U_mu(x) in
  * the planes (mu, nu), nu in mask, nu != mu): with all four directions that
@@ -403,14 +404,15 @@ static mat3 ape_w_link(const lat *g, const double *U, long s, int mu, double alp
 
 /* One smeared link: directions outside the mask keep U_mu(x) unchanged,
  * the others are Proj[W_mu(x)].  Returns 1 for a degenerate W. */
-static int ape_link(const lat *g, const double *U, long s, int mu, double alpha, unsigned mask, mat3 *V)
+static int ape_link(const lat *g, const double *U, long s, int mu, double alpha, unsigned mask, int proj,
+                    mat3 *V)
 {
     if (!((mask >> mu) & 1u)) {
         *V = load_link(U, s, mu);
         return 0;
     }
     mat3 w = ape_w_link(g, U, s, mu, alpha, mask);
-    return reunitarise(&w, V);
+    return proj ? polar_project(&w, V) : reunitarise(&w, V);
 }
 
 /* Reunitarise by rows: u = r1/|r1|; v = r2 - (sum_j conj(u_j) r2_j) u, v /= |v|;
@@ -444,6 +446,98 @@ static int reunitarise(const mat3 *W, mat3 *V)
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) V->e[i][j] = c_make(NAN, NAN);
     }
+    return bad;
+}
+
+/* Eigen-decomposition of a real symmetric n x n matrix (n <= 6) by cyclic
+ * Jacobi rotations, A = Q diag(lam) Q^T; A is overwritten.  Each rotation
+ * zeroes one off-diagonal pair; an element below rounding relative to its
+ * two diagonal entries is set to zero instead, and the sweeps stop when a
+ * whole sweep finds nothing left to rotate. */
+static void sym_jacobi(int n, double A[6][6], double lam[6], double Q[6][6])
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Q[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        int rotated = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                if (fabs(A[p][q]) <= 1e-18 * sqrt(fabs(A[p][p] * A[q][q]))) {
+                    A[p][q] = A[q][p] = 0.0;
+                    continue;
+                }
+                rotated = 1;
+                /* rotation angle that zeroes A[p][q]: tan(2 phi) = 2 A_pq / (A_qq - A_pp) */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                /* A <- J^T A J with J = [[c, s], [-s, c]] on rows/columns p, q:
+                 * the rotated pair is zero and the diagonal moves by t A_pq */
+                const double apq = A[p][q];
+                A[p][p] -= t * apq;
+                A[q][q] += t * apq;
+                A[p][q] = A[q][p] = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    if (k == p || k == q) continue;
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = A[p][k] = c * akp - sn * akq;
+                    A[k][q] = A[q][k] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) { /* accumulate Q <- Q J */
+                    double qkp = Q[k][p], qkq = Q[k][q];
+                    Q[k][p] = c * qkp - sn * qkq;
+                    Q[k][q] = sn * qkp + c * qkq;
+                }
+            }
+        if (!rotated) break;
+    }
+    for (int i = 0; i < n; ++i) lam[i] = A[i][i];
+}
+
+/* Bi-covariant projection: V = W (W^dag W)^(-1/2) exp(-i arg(det)/3), the
+ * unitary factor of the polar decomposition of W with the phase of its
+ * determinant removed on the principal branch.  The inverse square root of
+ * the Hermitian H = W^dag W is taken through the real symmetric 6x6 matrix
+ * [[Re H, -Im H], [Im H, Re H]], which represents H faithfully (a function of
+ * it represents the same function of H).  Returns 1 (output NaN) if H is not
+ * positive definite. */
+static int polar_project(const mat3 *W, mat3 *V)
+{
+    mat3 Wd = m_dag(W);
+    mat3 H = m_mul(&Wd, W);
+    double M[6][6], lam[6], Q[6][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            M[i][j] = H.e[i][j].re;
+            M[i][j + 3] = -H.e[i][j].im;
+            M[i + 3][j] = H.e[i][j].im;
+            M[i + 3][j + 3] = H.e[i][j].re;
+        }
+    sym_jacobi(6, M, lam, Q);
+    int bad = 0;
+    double f[6];
+    for (int k = 0; k < 6; ++k) {
+        bad |= !(lam[k] > 0.0);
+        f[k] = 1.0 / sqrt(lam[k]);
+    }
+    mat3 R; /* H^(-1/2): top-left block is its real part, bottom-left its imaginary part */
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < 6; ++k) {
+                re += f[k] * Q[i][k] * Q[j][k];
+                im += f[k] * Q[i + 3][k] * Q[j][k];
+            }
+            R.e[i][j] = c_make(re, im);
+        }
+    mat3 P = m_mul(W, &R);
+    cplx d = c_sub(c_add(c_mul(P.e[0][0], c_sub(c_mul(P.e[1][1], P.e[2][2]), c_mul(P.e[1][2], P.e[2][1]))),
+                         c_mul(P.e[0][2], c_sub(c_mul(P.e[1][0], P.e[2][1]), c_mul(P.e[1][1], P.e[2][0])))),
+                   c_mul(P.e[0][1], c_sub(c_mul(P.e[1][0], P.e[2][2]), c_mul(P.e[1][2], P.e[2][0]))));
+    double ph = -atan2(d.im, d.re) / 3.0;
+    cplx z = c_make(cos(ph), sin(ph));
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V->e[i][j] = bad ? c_make(NAN, NAN) : c_mul(P.e[i][j], z);
     return bad;
 }
 
@@ -482,10 +576,32 @@ long oracle_reunitarise(long n_links, const double *W, double *V)
     return bad;
 }
 
+/* Bi-covariant (polar) projection of n_links matrices (layout [n][3][3][2]).
+ * Returns the number of degenerate inputs. */
+long oracle_polar_project(long n_links, const double *W, double *V)
+{
+    long bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (long i = 0; i < n_links; ++i) {
+        mat3 w, v;
+        const double *p = W + (size_t)i * 18;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) w.e[a][b] = c_make(p[(a * 3 + b) * 2], p[(a * 3 + b) * 2 + 1]);
+        bad += polar_project(&w, &v);
+        double *q = V + (size_t)i * 18;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                q[(a * 3 + b) * 2] = v.e[a][b].re;
+                q[(a * 3 + b) * 2 + 1] = v.e[a][b].im;
+            }
+    }
+    return bad;
+}
+
 /* One APE step: V_mu(x) = Proj[W_mu(x)] for the links of the directions in
  * mask, all from the unsmeared U; the other links are copied.
  * Returns the number of degenerate links. */
-long oracle_ape_step(const int *L, const double *U, double alpha, unsigned mask, double *Vout)
+long oracle_ape_step(const int *L, const double *U, double alpha, unsigned mask, int proj, double *Vout)
 {
     lat g = lat_make(L);
     long bad = 0;
@@ -493,14 +609,15 @@ long oracle_ape_step(const int *L, const double *U, double alpha, unsigned mask,
     for (long s = 0; s < g.V; ++s)
         for (int mu = 0; mu < 4; ++mu) {
             mat3 v;
-            bad += ape_link(&g, U, s, mu, alpha, mask, &v);
+            bad += ape_link(&g, U, s, mu, alpha, mask, proj, &v);
             store_link(Vout, s, mu, &v);
         }
     return bad;
 }
 
 /* n_steps APE steps; Vout receives the last step, U is not modified. */
-long oracle_ape_smear(const int *L, const double *U, double alpha, unsigned mask, int n_steps, double *Vout)
+long oracle_ape_smear(const int *L, const double *U, double alpha, unsigned mask, int proj, int n_steps,
+                      double *Vout)
 {
     lat g = lat_make(L);
     size_t nl = (size_t)g.V * 4 * 18;
@@ -508,7 +625,7 @@ long oracle_ape_smear(const int *L, const double *U, double alpha, unsigned mask
     long bad = 0;
     memcpy(cur, U, sizeof(double) * nl);
     for (int k = 0; k < n_steps; ++k) {
-        bad += oracle_ape_step(L, cur, alpha, mask, Vout);
+        bad += oracle_ape_step(L, cur, alpha, mask, proj, Vout);
         memcpy(cur, Vout, sizeof(double) * nl);
     }
     if (n_steps == 0) memcpy(Vout, U, sizeof(double) * nl);
@@ -517,15 +634,15 @@ long oracle_ape_smear(const int *L, const double *U, double alpha, unsigned mask
 }
 
 /* One APE step evaluated only for the listed links (site[i], mu[i]). */
-long oracle_ape_links(const int *L, const double *U, double alpha, unsigned mask, long n, const long *site,
-                      const int *mu, double *Vout)
+long oracle_ape_links(const int *L, const double *U, double alpha, unsigned mask, int proj, long n,
+                      const long *site, const int *mu, double *Vout)
 {
     lat g = lat_make(L);
     long bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (long i = 0; i < n; ++i) {
         mat3 v;
-        bad += ape_link(&g, U, site[i], mu[i], alpha, mask, &v);
+        bad += ape_link(&g, U, site[i], mu[i], alpha, mask, proj, &v);
         double *q = Vout + (size_t)i * 18;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {

@@ -729,18 +729,21 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
         hipEventElapsedTime(&ms, e0, e1);
         return ms / reps;
     };
-    // Round 1: every candidate once (after one warm-up launch).  Round 2: the
-    // six fastest again, interleaved over five passes, keeping each one's
-    // best pass, so that a single slow or fast sample does not decide.
+    // Warm-up: about 30 launches of the default geometry, so that the first
+    // candidates are not timed at idle clocks.  Round 1: every candidate once
+    // (after one warm-up launch).  Round 2: the eight fastest again,
+    // interleaved over seven passes, keeping each one's best pass, so that a
+    // single slow or fast sample does not decide.
+    for (int r = 0; r < 30; ++r) run(LaunchCfg{});
     std::vector<std::pair<float, int>> r1;
     for (size_t i = 0; i < cands.size(); ++i) {
         if (run(cands[i]) != hipSuccess) continue;
         r1.push_back({time_cfg(cands[i], 5), (int)i});
     }
     std::sort(r1.begin(), r1.end());
-    const size_t keep = std::min<size_t>(6, r1.size());
+    const size_t keep = std::min<size_t>(8, r1.size());
     std::vector<float> best_ms(keep, 1e30f);
-    for (int pass = 0; pass < 5; ++pass)
+    for (int pass = 0; pass < 7; ++pass)
         for (size_t k = 0; k < keep; ++k) best_ms[k] = std::min(best_ms[k], time_cfg(cands[r1[k].second], 10));
     LaunchCfg best_cfg;
     float best = 1e30f;

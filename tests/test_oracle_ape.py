@@ -133,6 +133,77 @@ def test_abelian_closed_form(L, mask):
             assert np.array_equal(V[..., mu, :, :], U[..., mu, :, :])
 
 
+# ------------------------------------------------- polar (bi-covariant) projection
+def _phase_fixed(Vu):
+    d = np.linalg.det(Vu)
+    return Vu * np.exp(-1j * np.angle(d) / 3)[..., None, None]
+
+
+def test_polar_matches_library_polar_decomposition():
+    # The unitary factor of scipy's polar decomposition, with the phase of its
+    # determinant removed on the principal branch.
+    import scipy.linalg
+    W = oracle.ape_w(small_haar((2, 3, 2, 2), 90), ALPHA).reshape(-1, 3, 3)
+    W = np.concatenate([W, latgen._complex_gaussian(np.random.default_rng(91), (50, 3, 3))])
+    V, bad = oracle.polar_project(W)
+    assert bad == 0
+    ref = _phase_fixed(np.array([scipy.linalg.polar(w)[0] for w in W]))
+    assert max_abs(V - ref) < 1e-13
+
+
+def test_polar_projection_is_bicovariant_and_su3():
+    # well-conditioned inputs, as APE combinations are (the inverse square root
+    # of W^dag W loses accuracy as the square of W's condition number)
+    rng = np.random.default_rng(92)
+    W = latgen.haar_su3(rng, 200) + 0.1 * latgen._complex_gaussian(rng, (200, 3, 3))
+    g = latgen.haar_su3(rng, 200)
+    h = latgen.haar_su3(rng, 200)
+    V, _ = oracle.polar_project(W)
+    Vg, _ = oracle.polar_project(g @ W @ dag(h))
+    assert max_abs(Vg - g @ V @ dag(h)) < 1e-13
+    assert unitarity_defect(V) < 1e-14 and det_defect(V) < 1e-14
+    # a scaled SU(3) matrix projects to itself
+    U = latgen.haar_su3(rng, 50)
+    Vs, _ = oracle.polar_project(2.5 * U)
+    assert max_abs(Vs - U) < 1e-14
+
+
+def test_polar_step_gauge_covariant_haar():
+    # With a bi-covariant projection the whole smearing step commutes with a
+    # random (Haar) gauge transformation.
+    U = small_haar()
+    g = latgen.haar_gauge((4, 4, 4, 4), 93)
+    for mask in (0xF, 0x7):
+        V = oracle.ape_step(U, ALPHA, mask, proj=1)
+        Vg = oracle.ape_step(gauge_links(U, g), ALPHA, mask, proj=1)
+        assert max_abs(Vg - gauge_links(V, g)) < 1e-13
+
+
+def test_polar_fixed_points():
+    U = latgen.unit_links((2, 3, 2, 3))
+    assert max_abs(oracle.ape_step(U, ALPHA, proj=1) - U) < 1e-15
+    g = latgen.haar_gauge((2, 3, 4, 5), 94)
+    P = pure_gauge(g)
+    assert max_abs(oracle.ape_step(P, ALPHA, proj=1) - P) < 1e-13
+
+
+def test_polar_abelian_closed_form():
+    # Diagonal W: the polar factor is the diagonal of phases; the determinant
+    # phase (principal branch) is then split evenly over the three entries.
+    L = (3, 2, 4, 2)
+    ang, U = _abelian(L, 95)
+    W = oracle.ape_w(U, ALPHA)
+    V = oracle.ape_step(U, ALPHA, proj=1)
+    wd = np.diagonal(W, axis1=-2, axis2=-1)
+    ph = wd / np.abs(wd)
+    ph = ph * np.exp(-1j * np.angle(np.prod(ph, axis=-1)) / 3)[..., None]
+    assert max_abs(np.diagonal(V, axis1=-2, axis2=-1) - ph) < 1e-14
+    off = V.copy()
+    for k in range(3):
+        off[..., k, k] = 0
+    assert max_abs(off) < 1e-15
+
+
 # ------------------------------------------------- spatial-only smearing
 def test_spatial_smearing_leaves_temporal_links_and_ignores_them():
     # With the three spatial directions smeared, temporal links are copied,

@@ -55,6 +55,10 @@ MUTANTS = {
     "jacobi_extra_iteration": ("for (int n = 0; n < n_iter; ++n) {\n        memcpy(psi",
                                "for (int n = 0; n <= n_iter; ++n) {\n        memcpy(psi"),
     "jacobi_norm_multiplied": ("chi[i] = chi[i] / norm;", "chi[i] = chi[i] * norm;"),
+    "polar_inverse_not_sqrt": ("f[k] = 1.0 / sqrt(lam[k]);", "f[k] = 1.0 / lam[k];"),
+    "polar_no_phase_fix": ("double ph = -atan2(d.im, d.re) / 3.0;", "double ph = 0.0 * atan2(d.im, d.re);"),
+    "polar_wrong_side": ("mat3 H = m_mul(&Wd, W);", "mat3 H = m_mul(W, &Wd);"),
+    "jacobi_rotation_sign": ("A[k][p] = A[p][k] = c * akp - sn * akq;", "A[k][p] = A[p][k] = c * akp + sn * akq;"),
     "norm_drops_imag": ("static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }",
                         "static double c_abs2(cplx a) { return a.re * a.re + a.im * a.im * 0.0 + 0.0 * a.re; }"),
 }
