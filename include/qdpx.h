@@ -77,6 +77,12 @@ typedef enum { QDPX_F64 = 0, QDPX_F32 = 1 } qdpx_prec;
  * is accepted with QDPX_F32 only. */
 typedef enum { QDPX_LINK18 = 0, QDPX_LINK12 = 1 } qdpx_linkfmt;
 
+/* SU(3) projection of the APE combination W (qdpx_ape_smear). */
+typedef enum {
+    QDPX_PROJ_GRAM_SCHMIDT = 0, /* row Gram-Schmidt, rows 0 and 1 of W only */
+    QDPX_PROJ_POLAR = 1         /* W (W^dag W)^(-1/2) with the det phase removed: bi-covariant */
+} qdpx_proj;
+
 typedef struct { int32_t L[4]; } qdpx_geom;
 
 /* Operation ids for qdpx_workspace_bytes() and qdpx_tune(). */
@@ -205,18 +211,27 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
  * argument of the smearing routine of section 7).  The projection is always
  * FP64.  With QDPX_F32 the staple products are evaluated in FP32.  U_in is
  * not modified; U_out must not overlap U_in.
+ * projection: QDPX_PROJ_GRAM_SCHMIDT (the rows above; only rows 0 and 1 of
+ * the staples are formed) or QDPX_PROJ_POLAR: V = W (W^dag W)^(-1/2)
+ * exp(-i arg(det)/3), the unitary polar factor with the phase of its
+ * determinant removed (principal branch), by nine scaled Newton iterations in
+ * FP64 on the full staple sum.  The polar projection commutes with
+ * W -> g W h^dag for any g, h in SU(3), so the whole step commutes with a
+ * gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag; row Gram-Schmidt
+ * does so only for diagonal g.
  * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
  * triple (total, spatial, temporal; normalised as in qdpx_plaquette; all six
  * planes whatever the mask) of the input and of every step's output.  These
  * traces are formed in the link precision and summed in FP64 (qdpx_plaquette
- * forms them in FP64); with smear_mask 0xF they are fused into the smearing
- * kernel, otherwise each is a pass of its own with the same arithmetic.  The
+ * forms them in FP64); with smear_mask 0xF and the Gram-Schmidt projection
+ * they are fused into the smearing kernel, otherwise each is a pass of its
+ * own with the same arithmetic.  The
  * smeared links do not depend on whether plaq is requested.
  * A W whose row 0 or projected row 1 vanishes gives NaN entries.
  * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
 int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                    const void *U_in, void *U_out, double alpha, int n_steps, uint32_t smear_mask,
-                   double *plaq, void *work, size_t work_bytes, void *stream);
+                   qdpx_proj projection, double *plaq, void *work, size_t work_bytes, void *stream);
 
 /* -------------------------------------------------------------- plaquette
  * plaq[0] = (1/(18V)) sum_x sum_{mu<nu} Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]

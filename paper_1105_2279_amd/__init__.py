@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqdpx.so")
 F64, F32 = 0, 1
 LINK18, LINK12 = 0, 1
 OP_SHIFT, OP_CHAIN, OP_APE, OP_PLAQ, OP_BATCHED, OP_JACOBI = 0, 1, 2, 3, 4, 5
+PROJ_GRAM_SCHMIDT, PROJ_POLAR = 0, 1
 
 STATUS = {
     0: "QDPX_OK",
@@ -92,7 +93,7 @@ def lib():
         "qdpx_unpack_fermion": (i32, [_P, _G, _P, i32, _P, _P]),
         "qdpx_eval_shift_mul_axpy": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, _P, _P, _P, sz, _P]),
         "qdpx_shift_chain": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, dbl, i32, _P, _P, sz, _P]),
-        "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, ctypes.c_uint32, _P, _P, sz, _P]),
+        "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, ctypes.c_uint32, i32, _P, _P, sz, _P]),
         "qdpx_plaquette": (i32, [_P, _G, i32, i32, _P, _P, _P, sz, _P]),
         "qdpx_ape_smear_batched": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(_P), ctypes.POINTER(_P), dbl, i32,
                                          _P, _P, sz, _P]),
@@ -244,10 +245,10 @@ def qdpx_shift_chain(ctx, L, prec, fmt, U, psi, phi, a, c, n_iter, norms=None, w
 
 
 def qdpx_ape_smear(ctx, L, prec, fmt, U_in, U_out, alpha, n_steps, plaq=None, work=None, stream=None,
-                   smear_mask=0xF):
+                   smear_mask=0xF, projection=0):
     _check(lib().qdpx_ape_smear(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U_in), _ptr(U_out),
-                                float(alpha), int(n_steps), int(smear_mask), _ptr(plaq), _ptr(work),
-                                _nbytes(work), _stream(stream)), "qdpx_ape_smear")
+                                float(alpha), int(n_steps), int(smear_mask), int(projection), _ptr(plaq),
+                                _ptr(work), _nbytes(work), _stream(stream)), "qdpx_ape_smear")
 
 
 def qdpx_plaquette(ctx, L, prec, fmt, U, plaq, work, stream=None):

@@ -10,7 +10,7 @@ namespace qdpx {
 // consecutive sites per iteration; wave w handles direction mu = w % 4 of
 // group w / 4, so the four links of a site are updated by four waves of the
 // same block, which share the neighbour loads in L1/L2.
-template <typename R, int NR, int NS, int MODE>
+template <typename R, int NR, int NS, int MODE, int PROJ = 0>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
                                                   double c2, unsigned mask, double *__restrict__ partials, int xcd,
                                                   int tw) {
@@ -24,28 +24,31 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
         const int grp = xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
-        ape_group<R, NR, MODE>(g, U, out, c1, c2, mask, partials, grp, mu, lane);
+        ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane);
     }
 }
 
 int ape_num_partials(const Geo &g) { return 4 * ((g.V + 63) / 64); }
 
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st) {
+                           unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st,
+                           int proj) {
     if (mode == kApePlaq && mask != 0xFu) return hipErrorInvalidValue;  // owned planes need every staple
+    if (proj && mode != kApe) return hipErrorInvalidValue;             // polar: plaquettes in their own pass
     const int groups = (g.V + 63) / 64;
     const int gpb = cfg.block / 256;
     const int per_block = gpb * cfg.nsite;
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
-#define QDPX_APE_LAUNCH(R, NR, NS, M)                                                                          \
-    k_ape_step<R, NR, NS, M><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},        \
+#define QDPX_APE_LAUNCH(R, NR, NS, M, P)                                                                       \
+    k_ape_step<R, NR, NS, M, P><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},     \
                                                          LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2, mask,  \
                                                          partials, xcd, cfg.tw)
-#define QDPX_APE_M(R, NR, NS)                                      \
-    if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly);  \
-    else if (mode == kApePlaq) QDPX_APE_LAUNCH(R, NR, NS, kApePlaq); \
-    else QDPX_APE_LAUNCH(R, NR, NS, kApe);
+#define QDPX_APE_M(R, NR, NS)                                         \
+    if (proj) QDPX_APE_LAUNCH(R, NR, NS, kApe, 1);                    \
+    else if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly, 0); \
+    else if (mode == kApePlaq) QDPX_APE_LAUNCH(R, NR, NS, kApePlaq, 0);   \
+    else QDPX_APE_LAUNCH(R, NR, NS, kApe, 0);
 #define QDPX_APE_NS(R, NR)                         \
     switch (cfg.nsite) {                           \
     case 2: QDPX_APE_M(R, NR, 2) break;            \

@@ -185,6 +185,85 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
     }
 }
 
+// Full 3x3 products for the polar projection, which reads all of W.
+// T = A * B
+template <typename R> __device__ __forceinline__ void mul_33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(t, A.e[i][k], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// T = A^dag * B
+template <typename R> __device__ __forceinline__ void mul_dag33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_ca(t, A.e[k][i], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// S += T * C
+template <typename R> __device__ __forceinline__ void acc_33_33(M3<R> &S, const M3<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(S.e[i][j], T.e[i][k], C.e[k][j]);
+}
+// S += T * C^dag
+template <typename R> __device__ __forceinline__ void acc_33_33dag(M3<R> &S, const M3<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
+}
+
+// Full staple sum (all three rows) of link (s, mu) over nu in mask, the same
+// staples in the same order as staple_sum_rows01.
+template <typename R, int NR>
+__device__ __forceinline__ void staple_sum_full(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
+                                                unsigned mask, M3<R> &S) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
+    const int s = x.s;
+    const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        const int nu = k + (k >= mu);
+        if (!((mask >> nu) & 1u)) continue;  // wave-uniform
+        {  // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+            M3<R> A, B, T, C;
+            U.full(nu, s, A);
+            U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
+            mul_33_33(A, B, T);
+            U.full(nu, s_mu, C);
+            acc_33_33dag(S, T, C);
+        }
+        {  // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
+            const int y = hop_bwd(g, s, x.c[nu], nu);
+            M3<R> A, B, T, C;
+            U.full(nu, y, A);
+            U.full(mu, y, B);
+            mul_dag33_33(A, B, T);
+            U.full(nu, hop_fwd(g, y, x.c[mu], mu), C);
+            acc_33_33(S, T, C);
+        }
+    }
+}
+
 // What one (64-site group, direction) wave computes.
 enum ApeMode { kApe = 0, kApePlaq = 1, kPlaqOnly = 2 };
 
@@ -263,10 +342,11 @@ __device__ __forceinline__ double retrace_with(const LinksRO<R, NR> &U, int mu, 
 // partials[grp*4 + mu] (spatial planes, waves 0 and 1) and
 // partials[4*ngroups + grp*4 + mu] (temporal planes, waves 2 and 3).
 // Depends only on (grp, mu), never on the launch geometry.
-template <typename R, int NR, int MODE>
+template <typename R, int NR, int MODE, int PROJ = 0>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
                                           double c2, unsigned mask, double *__restrict__ partials, int grp, int mu,
                                           int lane) {
+    static_assert(PROJ == 0 || MODE == kApe, "the polar projection runs without the fused plaquette");
     const int ngroups = num_groups(g);
     double p = 0.0;
     Site x;
@@ -285,6 +365,23 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             for (int a = 0; a < NR; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, u.e[a][b].re, u.e[a][b].im);
+        } else if constexpr (PROJ == 1) {
+            M3<R> S, u;
+            staple_sum_full(g, U, x, mu, mask, S);
+            U.full(mu, s, u);
+            Cx<double> w[3][3], v[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    w[i][jj].re = fma(c2, (double)S.e[i][jj].re, c1 * (double)u.e[i][jj].re);
+                    w[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u.e[i][jj].im);
+                }
+            polar_project(w, v);
+#pragma unroll
+            for (int a = 0; a < NR; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, (R)v[a][b].re, (R)v[a][b].im);
         } else {
             M23<R> S;
             staple_sum_rows01<R, NR, MODE == kApePlaq>(g, U, x, mu, mask, S, Q);

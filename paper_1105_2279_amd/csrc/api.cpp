@@ -396,7 +396,7 @@ extern "C" int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
 
 extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                               const void *U_in, void *U_out, double alpha, int n_steps, uint32_t smear_mask,
-                              double *plaq, void *work, size_t work_bytes, void *stream) {
+                              qdpx_proj projection, double *plaq, void *work, size_t work_bytes, void *stream) {
     const char *fn = "qdpx_ape_smear";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -405,6 +405,9 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     if (n_steps < 1) return fail(QDPX_EINVAL, "%s: n_steps = %d < 1", fn, n_steps);
     if (smear_mask & ~0xFu)
         return fail(QDPX_EINVAL, "%s: smear_mask 0x%x has bits beyond the 4 directions", fn, smear_mask);
+    if (projection != QDPX_PROJ_GRAM_SCHMIDT && projection != QDPX_PROJ_POLAR)
+        return fail(QDPX_EINVAL, "%s: projection %d unknown", fn, (int)projection);
+    const int polar = (projection == QDPX_PROJ_POLAR);
     const size_t lb = qdpx_links_bytes(geom, prec, fmt);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_APE, geom, prec, fmt, n_steps);
     const bool need_work = (n_steps >= 2) || plaq;
@@ -422,11 +425,12 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     // d = number of smeared directions (alpha/6 for all four).
     const int d = __builtin_popcount(smear_mask);
     const double c1 = 1.0 - alpha, c2 = d > 1 ? alpha / (2.0 * (d - 1)) : 0.0;
-    // With every direction smeared, step k also reduces the plaquette of its
-    // own input (fused into the APE kernel) and only the last output needs the
-    // plaquette-only pass; with a partial mask every plaquette is its own pass
-    // (the same per-plane arithmetic, so the values agree bit for bit).
-    const bool fused = (smear_mask == 0xFu);
+    // With every direction smeared and the Gram-Schmidt projection, step k
+    // also reduces the plaquette of its own input (fused into the APE kernel)
+    // and only the last output needs the plaquette-only pass; otherwise every
+    // plaquette is its own pass (the same per-plane arithmetic, so the values
+    // agree bit for bit).
+    const bool fused = (smear_mask == 0xFu) && !polar;
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
@@ -434,7 +438,7 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
         if (plaq && !fused)
             QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
         QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, smear_mask,
-                                     (plaq && fused) ? part : nullptr, (plaq && fused) ? 1 : 0, cfg, st),
+                                     (plaq && fused) ? part : nullptr, (plaq && fused) ? 1 : 0, cfg, st, polar),
                      fn);
         if (plaq) QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
         src = dst;

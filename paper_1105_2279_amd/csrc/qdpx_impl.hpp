@@ -57,7 +57,8 @@ hipError_t launch_finalize(const double *partials, int n, int mode, double volum
 // temporal), reduced by launch_finalize(partials, ape_num_partials(g), 1, V, out).
 int ape_num_partials(const Geo &g);
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
-                           unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st);
+                           unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st,
+                           int proj = 0);  // proj 1: polar projection (mode 0 only)
 int plaquette_num_partials(const Geo &g);  // per component (2 components)
 hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st);
 

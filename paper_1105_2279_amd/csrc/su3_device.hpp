@@ -340,6 +340,86 @@ __device__ __forceinline__ void reunitarise(const Cx<double> w[2][3], Cx<double>
     v[2][2] = conj_cross(u[0], q[1], u[1], q[0]);
 }
 
+// ------------------------------------------------------- polar projection
+// Bi-covariant projection in FP64: V = W (W^dag W)^(-1/2), the unitary factor
+// of the polar decomposition, by the scaled Newton iteration
+//   X <- (z X + X^(-dag) / z) / 2,   z = (||X^-1||_F / ||X||_F)^(1/2)
+// from X = W, then the phase of det V removed on the principal branch
+// (V exp(-i arg(det V) / 3)).  For a 3x3 matrix with rows x0, x1, x2 the
+// cofactor matrix has rows x1 x x2, x2 x x0, x0 x x1 (plain cross products)
+// and det X = x0 . (x1 x x2), so X^(-dag) = conj(cofactors) / conj(det).
+// kPolarIters iterations reach FP64 rounding for the condition numbers that
+// APE combinations have (below about 1e3).  A singular W gives NaN.
+constexpr int kPolarIters = 9;
+
+__device__ __forceinline__ Cx<double> cmul(const Cx<double> &a, const Cx<double> &b) {
+    return Cx<double>{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+// (a x b)_k without conjugation: cyclic a_i b_j - a_j b_i
+__device__ __forceinline__ void cross3(const Cx<double> a[3], const Cx<double> b[3], Cx<double> c[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = (k + 1) % 3, j = (k + 2) % 3;
+        const Cx<double> t1 = cmul(a[i], b[j]), t2 = cmul(a[j], b[i]);
+        c[k] = Cx<double>{t1.re - t2.re, t1.im - t2.im};
+    }
+}
+
+__device__ __forceinline__ void polar_project(Cx<double> x[3][3], Cx<double> v[3][3]) {
+#pragma unroll 1
+    for (int it = 0; it < kPolarIters; ++it) {
+        Cx<double> c[3][3];
+        cross3(x[1], x[2], c[0]);
+        cross3(x[2], x[0], c[1]);
+        cross3(x[0], x[1], c[2]);
+        Cx<double> d{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const Cx<double> t = cmul(x[0][k], c[0][k]);
+            d.re += t.re;
+            d.im += t.im;
+        }
+        double nx = 0.0, nc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                nx = fma(x[i][j].re, x[i][j].re, fma(x[i][j].im, x[i][j].im, nx));
+                nc = fma(c[i][j].re, c[i][j].re, fma(c[i][j].im, c[i][j].im, nc));
+            }
+        const double dd = fma(d.re, d.re, d.im * d.im);  // |det|^2
+        // z^4 = ||X^-1||_F^2 / ||X||_F^2 = (nc / dd) / nx
+        const double z = sqrt(sqrt(nc / (dd * nx)));
+        const double hz = 0.5 * z, hiz = 0.5 / z;
+        const double rdd = 1.0 / dd;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                // conj(c_ij) / conj(d) = conj(c_ij conj(d)) / |d|^2
+                const Cx<double> cd{fma(c[i][j].re, d.re, c[i][j].im * d.im), fma(c[i][j].im, d.re, -c[i][j].re * d.im)};
+                const Cx<double> y{cd.re * rdd, -cd.im * rdd};
+                x[i][j] = Cx<double>{fma(hz, x[i][j].re, hiz * y.re), fma(hz, x[i][j].im, hiz * y.im)};
+            }
+    }
+    Cx<double> c0[3];
+    cross3(x[1], x[2], c0);
+    Cx<double> d{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const Cx<double> t = cmul(x[0][k], c0[k]);
+        d.re += t.re;
+        d.im += t.im;
+    }
+    double sn, cs;
+    sincos(-atan2(d.im, d.re) / 3.0, &sn, &cs);
+    const Cx<double> ph{cs, sn};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[i][j] = cmul(x[i][j], ph);
+}
+
 // ------------------------------------------------------------- reductions
 // Fixed-shape butterfly over the 64 lanes of a wave: every lane ends with the
 // same sum and the order of additions never changes.

@@ -77,7 +77,7 @@ def test_null_context_rejected_everywhere():
     assert h.qdpx_unpack_fermion(None, g, 1, 0, 2, None) == EINVAL
     assert h.qdpx_eval_shift_mul_axpy(None, g, 0, 0, 1, 2, 3, 0.3, 4, None, None, 0, None) == EINVAL
     assert h.qdpx_shift_chain(None, g, 0, 0, 1, 2, 3, 0.3, 0.1, 8, None, None, 0, None) == EINVAL
-    assert h.qdpx_ape_smear(None, g, 0, 0, 1, 2, 0.5, 1, 0xF, None, None, 0, None) == EINVAL
+    assert h.qdpx_ape_smear(None, g, 0, 0, 1, 2, 0.5, 1, 0xF, 0, None, None, 0, None) == EINVAL
     assert h.qdpx_plaquette(None, g, 0, 0, 1, 2, 3, 0, None) == EINVAL
     assert h.qdpx_free_all(None) == EINVAL
     assert h.qdpx_create(None, 0) == EINVAL
