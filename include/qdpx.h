@@ -276,6 +276,48 @@ int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdp
                            double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,
                            void *stream);
 
+/* ---------------------------------------------- run-time compiled expressions
+ * The paper evaluates each lattice expression with a kernel generated from
+ * its expression tree, compiled at run time and kept for reuse (section 5.1).
+ * Expressions here are S-expressions over Dirac fields (spinor x colour
+ * vectors) and the link field:
+ *   fK                 field argument K (0 <= K < n_fields <= 8)
+ *   (shift E + mu)     E evaluated at x + mu;  (shift E - mu): at x - mu
+ *   (umul mu E)        U_mu(x) E(x);  (uadj mu E): U_mu(x)^dagger E(x)
+ *   (add E F)  (sub E F)  (scale sK E)   sK: scalar argument K (< n_scalars <= 8)
+ *   (sum MASK E)       sum over the directions in MASK (hex, 0x1..0xF) of E
+ *                      with the direction variable m standing for each one
+ * A direction mu is a digit 0..3 (x, y, z, t) or m inside a sum; sums do not
+ * nest.  The listing's hopping term E_1 + E_2 is
+ *   (sum 0xF (add (umul m (shift f0 + m)) (shift (uadj m f0) - m)))
+ * and a smearing iteration E_3 is (add f1 (scale s0 <that>)).
+ *
+ * qdpx_jit_generate: the HIP source of the kernel for an expression (no
+ *   device needed); *needed receives the size including the terminator; with
+ *   buf non-NULL the source is copied (QDPX_ENOMEM if it does not fit).
+ * qdpx_jit_compile: generates the kernel, compiles it with hipRTC for the
+ *   current device (packed FP32 disabled) or loads the code object from the
+ *   on-disk cache (directory $QDPX_JIT_CACHE, else $HOME/.cache/qdpx-jit;
+ *   file name a hash of source, options and architecture), and returns a
+ *   kernel handle valid for the context (released by qdpx_free_all /
+ *   qdpx_destroy).  Not for a capturing stream (it may compile and loads a
+ *   module).  EINVAL with the reason for a malformed expression.
+ * qdpx_jit_info: whether the kernel came from the cache, and its source.
+ * qdpx_jit_eval: out(x) = the expression at every site, fields and links in
+ *   the layout of qdpx_pack_* (prec/fmt of the compile call); fields: host
+ *   array of n_fields device pointers; scalars: host array of n_scalars
+ *   doubles (passed in the field precision).  out must not overlap U or any
+ *   field.  norm2 (nullable, device double) receives |out|^2 in FP64 (fixed
+ *   order; then work >= qdpx_workspace_bytes(QDPX_OP_SHIFT, ...)).  One site
+ *   per thread, 256 threads per block; enqueues only, so it can be captured. */
+int qdpx_jit_generate(const char *expr, qdpx_prec prec, qdpx_linkfmt fmt, int32_t n_fields, int32_t n_scalars,
+                      char *buf, size_t buf_bytes, size_t *needed);
+int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec, qdpx_linkfmt fmt, int32_t n_fields,
+                     int32_t n_scalars, int32_t *kernel);
+int qdpx_jit_info(qdpx_ctx *ctx, int32_t kernel, int32_t *from_cache, char *buf, size_t buf_bytes);
+int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const void *U, const void *const *fields,
+                  const double *scalars, void *out, double *norm2, void *work, size_t work_bytes, void *stream);
+
 /* -------------------------------------------------------------- autotuner
  * Time the candidate launch geometries of operation `op` (QDPX_OP_APE,
  * QDPX_OP_SHIFT, QDPX_OP_CHAIN or QDPX_OP_JACOBI) on `geom` and remember the

@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 LINK18, LINK12 = 0, 1
 OP_SHIFT, OP_CHAIN, OP_APE, OP_PLAQ, OP_BATCHED, OP_JACOBI = 0, 1, 2, 3, 4, 5
 PROJ_GRAM_SCHMIDT, PROJ_POLAR = 0, 1
+OK, EINVAL, EALIAS, ENOMEM, EHIP, EUNSUPPORTED, ECAPTURE = 0, -1, -2, -3, -4, -5, -6
 
 STATUS = {
     0: "QDPX_OK",
@@ -40,6 +41,7 @@ EXPORTS = (
     "qdpx_eval_shift_mul_axpy", "qdpx_shift_chain", "qdpx_ape_smear", "qdpx_plaquette",
     "qdpx_ape_smear_batched", "qdpx_tune", "qdpx_tune_get", "qdpx_tune_set",
     "qdpx_eval_hop", "qdpx_jacobi_smear",
+    "qdpx_jit_generate", "qdpx_jit_compile", "qdpx_jit_info", "qdpx_jit_eval",
 )
 
 
@@ -99,6 +101,10 @@ def lib():
                                          _P, _P, sz, _P]),
         "qdpx_tune": (i32, [_P, i32, _G, i32, i32, _P]),
         "qdpx_eval_hop": (i32, [_P, _G, i32, i32, _P, _P, _P, ctypes.c_uint32, _P]),
+        "qdpx_jit_generate": (i32, [ctypes.c_char_p, i32, i32, i32, i32, _P, sz, ctypes.POINTER(sz)]),
+        "qdpx_jit_compile": (i32, [_P, ctypes.c_char_p, i32, i32, i32, i32, ctypes.POINTER(i32)]),
+        "qdpx_jit_info": (i32, [_P, i32, ctypes.POINTER(i32), _P, sz]),
+        "qdpx_jit_eval": (i32, [_P, i32, _G, _P, _P, _P, _P, _P, _P, sz, _P]),
         "qdpx_jacobi_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, dbl, ctypes.c_uint32, _P, sz, _P]),
         "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -275,6 +281,39 @@ def qdpx_jacobi_smear(ctx, L, prec, fmt, U, chi, kappa, n_iter, norm=1.0, dir_ma
     _check(lib().qdpx_jacobi_smear(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(chi), float(kappa),
                                    int(n_iter), float(norm), int(dir_mask), _ptr(work), _nbytes(work),
                                    _stream(stream)), "qdpx_jacobi_smear")
+
+
+def jit_generate(expr, prec, fmt, n_fields, n_scalars=0) -> str:
+    """HIP source of the run-time compiled kernel for an expression (no device needed)."""
+    need = ctypes.c_size_t(0)
+    _check(lib().qdpx_jit_generate(expr.encode(), prec, fmt, n_fields, n_scalars, None, 0, ctypes.byref(need)),
+           "qdpx_jit_generate")
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().qdpx_jit_generate(expr.encode(), prec, fmt, n_fields, n_scalars, buf, need.value, None),
+           "qdpx_jit_generate")
+    return buf.value.decode()
+
+
+def qdpx_jit_compile(ctx, expr, prec, fmt, n_fields, n_scalars=0) -> int:
+    k = ctypes.c_int32(-1)
+    _check(lib().qdpx_jit_compile(ctx.handle, expr.encode(), prec, fmt, n_fields, n_scalars, ctypes.byref(k)),
+           "qdpx_jit_compile")
+    return k.value
+
+
+def qdpx_jit_info(ctx, kernel):
+    """(came from the on-disk cache, generated source)."""
+    fc = ctypes.c_int32(0)
+    buf = ctypes.create_string_buffer(1 << 20)
+    _check(lib().qdpx_jit_info(ctx.handle, kernel, ctypes.byref(fc), buf, len(buf)), "qdpx_jit_info")
+    return bool(fc.value), buf.value.decode()
+
+
+def qdpx_jit_eval(ctx, kernel, L, U, fields, scalars, out, norm2=None, work=None, stream=None):
+    ptrs = (ctypes.c_void_p * max(1, len(fields)))(*[_ptr(f) for f in fields])
+    sc = (ctypes.c_double * max(1, len(scalars)))(*[float(x) for x in scalars])
+    _check(lib().qdpx_jit_eval(ctx.handle, kernel, ctypes.byref(geom(L)), _ptr(U), ptrs, sc, _ptr(out), _ptr(norm2),
+                               _ptr(work), _nbytes(work), _stream(stream)), "qdpx_jit_eval")
 
 
 def qdpx_tune(ctx, op, L, prec, fmt, stream=None):

@@ -46,6 +46,11 @@ static int hip_fail(hipError_t e, const char *what) {
     } while (0)
 
 extern "C" const char *qdpx_last_error(void) { return g_err.c_str(); }
+
+namespace qdpx {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+void jit_release(const qdpx_ctx *ctx);
+}  // namespace qdpx
 extern "C" const char *qdpx_version(void) { return "qdpx 0.1 (gfx950)"; }
 
 // ------------------------------------------------------------------ context
@@ -92,6 +97,7 @@ static void batch_cache_free(qdpx_ctx *ctx);
 extern "C" int qdpx_free_all(qdpx_ctx *ctx) {
     if (!ctx) return fail(QDPX_EINVAL, "qdpx_free_all: ctx is NULL");
     batch_cache_free(ctx);
+    jit_release(ctx);
     return QDPX_OK;
 }
 
@@ -157,6 +163,11 @@ extern "C" size_t qdpx_fermion_bytes(const qdpx_geom *geom, qdpx_prec prec) {
 static size_t reduce_bytes(int n, int ncomp) {
     return round256(sizeof(double) * (size_t)ncomp * ((size_t)n + (size_t)finalize_stage_a_blocks(n)));
 }
+
+namespace qdpx {
+bool geom_valid(const qdpx_geom *g, const char *fn) { return geom_ok(g, fn); }
+int workspace_reduce_bytes(const qdpx_geom *g) { return (int)reduce_bytes(shift_num_partials(make_geo(g->L)), 1); }
+}  // namespace qdpx
 
 // Batched tables are defined further below.
 static size_t batched_ws_bytes(int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt, int n_steps);

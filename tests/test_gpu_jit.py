@@ -1,0 +1,134 @@
+"""Run-time compiled expression kernels on the GPU against the reference
+expression evaluator (oracle/expr.py) and the C oracle: the listing's
+hopping term and smearing update, the shift expression with its norm, and
+mixed expressions with nested and backward shifts, over the three link
+formats and ragged lattices; the on-disk kernel cache; graph capture."""
+
+import numpy as np
+import pytest
+import torch
+
+import latgen
+import oracle
+import paper_1105_2279_amd as q
+from gpuhelp import FORMAT_IDS, FORMATS, ctx, dev, need_gpu, rel_err, tol
+from oracle import expr
+
+pytestmark = pytest.mark.gpu
+
+HOP = "(sum 0xF (add (umul m (shift f0 + m)) (shift (uadj m f0) - m)))"
+EXPRS = [
+    (HOP, 1, []),
+    (f"(add f1 (scale s0 {HOP}))", 2, [0.21]),
+    ("(add (sum 0xF (umul m (shift f0 + m))) (scale s0 f1))", 2, [0.3]),
+    ("(sub (shift (umul 2 (shift f1 - 0)) + 3) (scale s1 (sum 0x5 (uadj m (shift f0 + m)))))", 2, [0.0, 1.7]),
+    ("(shift (shift (uadj 1 (shift f0 - 1)) + 1) - 3)", 1, []),
+]
+LATTICES = [(4, 4, 4, 4), (3, 5, 4, 7), (8, 6, 2, 4)]
+
+
+@pytest.fixture(autouse=True)
+def _gpu(tmp_path_factory, monkeypatch):
+    need_gpu()
+    monkeypatch.setenv("QDPX_JIT_CACHE", str(tmp_path_factory.getbasetemp() / "jitcache"))
+
+
+def run(L, e, nf, scalars, prec, fmt, seed, with_norm=False, context=None):
+    c = context or ctx()
+    U = latgen.haar_links(L, seed)
+    fields = [latgen.dirac_field(L, seed + 1 + i) for i in range(nf)]
+    k = q.qdpx_jit_compile(c, e, prec, fmt, nf, len(scalars))
+    Ud = q.links_to_device(c, L, U, prec, fmt, dev())
+    fd = [q.fermion_to_device(c, L, f, prec, dev()) for f in fields]
+    out = q.alloc_fermion(L, prec, dev())
+    n2 = torch.zeros(1, dtype=torch.float64, device=dev()) if with_norm else None
+    work = q.alloc_workspace(q.OP_SHIFT, L, prec, fmt, 1, dev()) if with_norm else None
+    q.qdpx_jit_eval(c, k, L, Ud, fd, scalars, out, n2, work)
+    got = q.fermion_to_host(c, L, out, prec)
+    torch.cuda.synchronize()
+    return U, fields, got, (float(n2.item()) if with_norm else None)
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("L", LATTICES, ids=lambda L: "x".join(map(str, L)))
+@pytest.mark.parametrize("i", range(len(EXPRS)))
+def test_jit_matches_reference_evaluator(L, prec, fmt, i):
+    e, nf, sc = EXPRS[i]
+    U, fields, got, _ = run(L, e, nf, sc, prec, fmt, 7000 + 10 * i + sum(L))
+    ref = expr.evaluate(e, U, fields, sc)
+    nrm, mx = rel_err(got, ref)
+    assert nrm < tol(prec) and mx < 10 * tol(prec), (nrm, mx)
+
+
+def test_jit_hop_matches_c_oracle_and_hand_kernel():
+    L = (8, 8, 8, 8)
+    U, (psi,), got, _ = run(L, HOP, 1, [], q.F64, q.LINK18, 7100)
+    assert rel_err(got, oracle.hop(U, psi))[0] < 1e-12
+    c = ctx()
+    Ud = q.links_to_device(c, L, U, q.F64, q.LINK18, dev())
+    pd = q.fermion_to_device(c, L, psi, q.F64, dev())
+    h = q.alloc_fermion(L, q.F64, dev())
+    q.qdpx_eval_hop(c, L, q.F64, q.LINK18, Ud, pd, h, 0xF)
+    assert rel_err(got, q.fermion_to_host(c, L, h, q.F64))[0] < 1e-14
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_jit_norm_matches_c_oracle(prec, fmt):
+    L = (16, 8, 4, 8)
+    e = "(add (sum 0xF (umul m (shift f0 + m))) (scale s0 f1))"
+    U, (psi, phi), got, n2 = run(L, e, 2, [0.3], prec, fmt, 7200, with_norm=True)
+    ref, n2ref = oracle.shift_mul_axpy(U, psi, phi, 0.3)
+    assert rel_err(got, ref)[0] < tol(prec)
+    assert abs(n2 - n2ref) / n2ref < tol(prec)
+
+
+def test_jit_cache_reuses_code_object():
+    e = "(add (shift f0 + 2) (scale s0 (uadj 3 f1)))"
+    c1 = q.Context(0)
+    k1 = q.qdpx_jit_compile(c1, e, q.F32, q.LINK12, 2, 1)
+    c2 = q.Context(0)
+    k2 = q.qdpx_jit_compile(c2, e, q.F32, q.LINK12, 2, 1)
+    hit1, src1 = q.qdpx_jit_info(c1, k1)
+    hit2, src2 = q.qdpx_jit_info(c2, k2)
+    assert hit2 and src1 == src2
+    c1.close()
+    c2.close()
+
+
+def test_jit_graph_replay_matches_eager():
+    L = (8, 8, 4, 8)
+    c = ctx()
+    e = f"(add f1 (scale s0 {HOP}))"
+    k = q.qdpx_jit_compile(c, e, q.F32, q.LINK12, 2, 1)
+    U = q.links_to_device(c, L, latgen.haar_links(L, 7300), q.F32, q.LINK12, dev())
+    f = [q.fermion_to_device(c, L, latgen.dirac_field(L, 7301 + i), q.F32, dev()) for i in range(2)]
+    eager = q.alloc_fermion(L, q.F32, dev())
+    q.qdpx_jit_eval(c, k, L, U, f, [0.21], eager)
+    torch.cuda.synchronize()
+    out = q.alloc_fermion(L, q.F32, dev())
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            q.qdpx_jit_eval(c, k, L, U, f, [0.21], out, stream=s)
+    for _ in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
+
+
+def test_jit_validation():
+    L = (4, 4, 4, 4)
+    c = ctx()
+    with pytest.raises(q.QdpxError) as ei:
+        q.qdpx_jit_compile(c, "(umul m f0)", q.F64, q.LINK18, 1, 0)
+    assert "outside a sum" in str(ei.value)
+    k = q.qdpx_jit_compile(c, HOP, q.F64, q.LINK18, 1, 0)
+    U = q.links_to_device(c, L, latgen.haar_links(L, 7400), q.F64, q.LINK18, dev())
+    f = q.fermion_to_device(c, L, latgen.dirac_field(L, 7401), q.F64, dev())
+    with pytest.raises(q.QdpxError):
+        q.qdpx_jit_eval(c, k, L, U, [f], [], f)  # out aliases the field
+    with pytest.raises(q.QdpxError):
+        q.qdpx_jit_eval(c, 99, L, U, [f], [], q.alloc_fermion(L, q.F64, dev()))
