@@ -295,6 +295,7 @@ def main():
         extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np, table))
         extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen, table))
+        extras.update(jit_extras(torch, q, ctx, dev, stream, latgen))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -443,6 +444,44 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
         out["x".join(map(str, L))] = row
     return {"jacobi_smearing": {"iterations": N_JACOBI, "kappa": KAPPA_JACOBI, "directions": 4,
                                 "flops_per_site_iteration": JACOBI_FLOPS_SITE_ITER, "lattices": out}}
+
+
+def jit_extras(torch, q, ctx, dev, stream, latgen):
+    """The listing's hopping term as a run-time compiled expression kernel
+    (generated, compiled with hipRTC or loaded from the on-disk cache) against
+    the hand-written hop kernel, 32^3x64."""
+    Lj = (32, 32, 32, 64)
+    V = latgen.volume(Lj)
+    hop = "(sum 0xF (add (umul m (shift f0 + m)) (shift (uadj m f0) - m)))"
+    U = latgen.haar_links(Lj, 1305)
+    psi = latgen.dirac_field(Lj, 1306)
+    out = {}
+    for name, prec, fmt, link_b, ferm_b in (("f32_12", q.F32, q.LINK12, 48, 96), ("f64_18", q.F64, q.LINK18, 144, 192)):
+        t0 = time.perf_counter()
+        k = q.qdpx_jit_compile(ctx, hop, prec, fmt, 1, 0)
+        t_compile = time.perf_counter() - t0
+        cached, _ = q.qdpx_jit_info(ctx, k)
+        Ud = q.links_to_device(ctx, Lj, U, prec, fmt, dev)
+        pd = q.fermion_to_device(ctx, Lj, psi, prec, dev)
+        o1, o2 = q.alloc_fermion(Lj, prec, dev), q.alloc_fermion(Lj, prec, dev)
+
+        def jit():
+            q.qdpx_jit_eval(ctx, k, Lj, Ud, [pd], [], o1, stream=stream)
+
+        def hand():
+            q.qdpx_eval_hop(ctx, Lj, prec, fmt, Ud, pd, o2, 0xF, stream)
+
+        jit()
+        hand()
+        tj = time_calls(torch, jit, 20, stream) / 20 / 1e3
+        th = time_calls(torch, hand, 20, stream) / 20 / 1e3
+        gbs = (4 * link_b + 2 * ferm_b) * V / tj / 1e9
+        out[name] = {"compile_or_load_s": round(t_compile, 3), "from_disk_cache": bool(cached),
+                     "jit_us": round(tj * 1e6, 1), "hand_written_us": round(th * 1e6, 1),
+                     "jit_hbm_gbs_algorithmic": round(gbs, 1), "jit_over_hand": round(tj / th, 3)}
+        log(f"jit hop {name}: {tj * 1e6:.1f} us (hand-written {th * 1e6:.1f} us), compile/load {t_compile:.2f} s")
+        del Ud, pd, o1, o2
+    return {"jit_hop_32x32x32x64": out}
 
 
 def batched_extras(torch, q, ctx, dev, stream, latgen):
