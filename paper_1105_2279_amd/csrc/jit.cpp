@@ -245,8 +245,9 @@ struct Gen {
     }
 };
 
+// hipRTC provides the device built-ins itself; the source includes no
+// header, so it does not depend on where the HIP headers are installed.
 const char *kPrelude = R"HIP(
-#include <hip/hip_runtime.h>
 typedef REAL real;
 typedef real real2 __attribute__((ext_vector_type(2)));
 struct cx { real re, im; };
