@@ -546,14 +546,14 @@ def batched_extras(torch, q, ctx, dev, stream, latgen):
 
 def cpu_baseline(U):
     """The FP64 oracle on the host: whole APE steps over the full 32^3x64
-    lattice, repeated until at least 10 s of work (at most 8 steps)."""
+    lattice, repeated until at least 10 s of work (at most 40 steps)."""
     import oracle
 
     V = U.shape[0] * U.shape[1] * U.shape[2] * U.shape[3]
     threads = oracle.num_threads()
     log(f"cpu baseline: oracle APE steps on {L} with {threads} threads")
     n, t, cur = 0, 0.0, U
-    while t < 10.0 and n < 8:
+    while t < 10.0 and n < 40:
         t0 = time.perf_counter()
         cur = oracle.ape_step(cur, ALPHA)
         t += time.perf_counter() - t0
