@@ -23,12 +23,18 @@
  *   links    double[V][4][3][3][2]   (site, mu, row, column, re/im)
  *   fermions double[V][4][3][2]      (site, spin, colour, re/im)
  * Library layout ("SoA", opaque to callers, sized by qdpx_links_bytes /
- *   qdpx_fermion_bytes): one array per matrix entry with the site index
- *   innermost, padded to a stride S = qdpx_site_stride(geom):
- *   LINK18: complex[mu][row 0..2][col][S]; LINK12: complex[mu][row 0..1][col][S]
- *   (row 2 is rebuilt as conj(row0 x row1) on every load, exact for SU(3));
- *   fermion: complex[spin][colour][S].  "complex" is double2 for QDPX_F64 and
- *   float2 for QDPX_F32.
+ *   qdpx_fermion_bytes): the site index innermost, padded to a stride
+ *   S = qdpx_site_stride(geom).  Links store rows 0..2 (LINK18) or rows 0..1
+ *   (LINK12; row 2 is rebuilt as conj(row0 x row1) on every load, exact for
+ *   SU(3)); stored element c = 3*row + col of direction mu:
+ *     QDPX_F64  one array of S double2 per element, [mu][c][S];
+ *     QDPX_F32  elements 2k and 2k+1 share one 16-byte entry (float4) of
+ *               array k, [mu][k][S]; the ninth LINK18 element has an array
+ *               of S float2 of its own after the four pair arrays.
+ *   Either way a direction takes 3*rows*S complex slots.  Fermions:
+ *   complex[spin][colour][S], complex = double2 (F64) or float2 (F32).
+ *   Link fields, and workspaces that hold intermediate links, must be
+ *   16-byte aligned (else QDPX_EINVAL).
  *
  * Memory and streams.  Every pointer argument named *_dev, and every field
  *   argument (U, psi, phi, chi, ...), is a DEVICE pointer owned by the caller.

@@ -60,13 +60,12 @@ template <typename R> __device__ __forceinline__ void acc_23_33dag(M23<R> &S, co
 // Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12.
 template <typename R, int NR>
 __device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s, M3<double> &m) {
+    Cx<R> r[3][3];
+    U.template load_rows<false, NR>(mu, s, r);
 #pragma unroll
     for (int a = 0; a < NR; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Cx<R> z = U.ld(mu, a, b, s);
-            m.e[a][b] = Cx<double>{(double)z.re, (double)z.im};
-        }
+        for (int b = 0; b < 3; ++b) m.e[a][b] = Cx<double>{(double)r[a][b].re, (double)r[a][b].im};
     if constexpr (NR == 2) rebuild_row2(m);
 }
 
@@ -84,8 +83,13 @@ __device__ __forceinline__ bool owns_plane(int mu, int nu) {
 template <typename R, int NR>
 __device__ __forceinline__ void row2_of(const LinksRO<R, NR> &U, int mu, int s, const M23<R> &A, Cx<R> r[3]) {
     if constexpr (NR == 3) {
+        if constexpr (LinksRO<R, NR>::Lay::kPaired) {
+            U.template ld_pair<false>(mu, 3, s, r[0], r[1]);  // elements 6 and 7
+            r[2] = U.ld(mu, 2, 2, s);
+        } else {
 #pragma unroll
-        for (int b = 0; b < 3; ++b) r[b] = U.ld(mu, 2, b, s);
+            for (int b = 0; b < 3; ++b) r[b] = U.ld(mu, 2, b, s);
+        }
     } else {
         r[0] = conj_cross(A.e[0][1], A.e[1][2], A.e[0][2], A.e[1][1]);
         r[1] = conj_cross(A.e[0][2], A.e[1][0], A.e[0][0], A.e[1][2]);
@@ -264,6 +268,17 @@ __device__ __forceinline__ void staple_sum_full(const Geo &g, const LinksRO<R, N
     }
 }
 
+// Store the FP64 link v in link precision (round to nearest).
+template <typename R, int NR>
+__device__ __forceinline__ void store_narrowed(const LinksWO<R, NR> &out, int mu, int s, const Cx<double> (&v)[3][3]) {
+    Cx<R> o[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) o[a][b] = Cx<R>{(R)v[a][b].re, (R)v[a][b].im};
+    out.store(mu, s, o);
+}
+
 // What one (64-site group, direction) wave computes.
 enum ApeMode { kApe = 0, kApePlaq = 1, kPlaqOnly = 2 };
 
@@ -361,10 +376,7 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
         } else if (!((mask >> mu) & 1u)) {  // wave-uniform: not smeared
             M3<R> u;
             U.full(mu, s, u);
-#pragma unroll
-            for (int a = 0; a < NR; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, u.e[a][b].re, u.e[a][b].im);
+            out.store(mu, s, u.e);
         } else if constexpr (PROJ == 1) {
             M3<R> S, u;
             staple_sum_full(g, U, x, mu, mask, S);
@@ -378,10 +390,7 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
                     w[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u.e[i][jj].im);
                 }
             polar_project(w, v);
-#pragma unroll
-            for (int a = 0; a < NR; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, (R)v[a][b].re, (R)v[a][b].im);
+            store_narrowed(out, mu, s, v);
         } else {
             M23<R> S;
             staple_sum_rows01<R, NR, MODE == kApePlaq>(g, U, x, mu, mask, S, Q);
@@ -397,10 +406,7 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
                     wm[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u0.e[i][jj].im);
                 }
             reunitarise(wm, v);
-#pragma unroll
-            for (int a = 0; a < NR; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) out.st(mu, a, b, s, (R)v[a][b].re, (R)v[a][b].im);
+            store_narrowed(out, mu, s, v);
         }
     }
     if constexpr (MODE != kApe) {

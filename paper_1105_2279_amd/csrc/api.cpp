@@ -141,6 +141,9 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Link fields are read and written with 16-byte accesses.
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 extern "C" int64_t qdpx_site_stride(const qdpx_geom *geom) {
     if (!geom_ok(geom, "qdpx_site_stride")) return -1;
     return make_geo(geom->L).S;
@@ -222,6 +225,7 @@ extern "C" int qdpx_pack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const doubl
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(soa)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     const Geo g = make_geo(geom->L);
     if (overlap(aos, (size_t)g.V * 4 * 18 * 8, soa, qdpx_links_bytes(geom, prec, fmt)))
         return fail(QDPX_EALIAS, "%s: soa overlaps aos", fn);
@@ -236,6 +240,7 @@ extern "C" int qdpx_unpack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const voi
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(soa)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     const Geo g = make_geo(geom->L);
     if (overlap(aos, (size_t)g.V * 4 * 18 * 8, soa, qdpx_links_bytes(geom, prec, fmt)))
         return fail(QDPX_EALIAS, "%s: aos overlaps soa", fn);
@@ -280,6 +285,7 @@ extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qd
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_SHIFT, geom, prec, fmt, 0);
     if (norm2 && (!work || work_bytes < need))
         return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
@@ -306,6 +312,7 @@ extern "C" int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec 
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !psi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_CHAIN, geom, prec, fmt, n_iter);
     if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
@@ -337,6 +344,7 @@ extern "C" int qdpx_eval_hop(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pre
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !psi || !out) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
     const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
     if (overlap(out, fb, psi, fb) || overlap(out, fb, U, lb)) return fail(QDPX_EALIAS, "%s: out overlaps an input", fn);
@@ -356,6 +364,7 @@ extern "C" int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
     if (norm == 0.0) return fail(QDPX_EINVAL, "%s: norm is 0", fn);
     if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
@@ -398,6 +407,7 @@ extern "C" int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !plaq) return fail(QDPX_EINVAL, "%s: NULL pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_PLAQ, geom, prec, fmt, 0);
     if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
     if (overlap(work, need, U, qdpx_links_bytes(geom, prec, fmt)))
@@ -413,6 +423,7 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U_in || !U_out) return fail(QDPX_EINVAL, "%s: NULL link pointer", fn);
+    if (!aligned16(U_in) || !aligned16(U_out)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (n_steps < 1) return fail(QDPX_EINVAL, "%s: n_steps = %d < 1", fn, n_steps);
     if (smear_mask & ~0xFu)
         return fail(QDPX_EINVAL, "%s: smear_mask 0x%x has bits beyond the 4 directions", fn, smear_mask);
@@ -424,6 +435,8 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     const bool need_work = (n_steps >= 2) || plaq;
     if (need_work && (!work || work_bytes < need))
         return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    if (n_steps >= 2 && !aligned16(work))  // holds the intermediate links
+        return fail(QDPX_EINVAL, "%s: workspace not 16-byte aligned", fn);
     if (overlap(U_in, lb, U_out, lb)) return fail(QDPX_EALIAS, "%s: U_out overlaps U_in", fn);
     if (need_work && (overlap(work, need, U_in, lb) || overlap(work, need, U_out, lb)))
         return fail(QDPX_EALIAS, "%s: workspace overlaps the links", fn);
@@ -528,9 +541,12 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
         return fail(QDPX_EINVAL, "%s: n_steps = %d outside [1, %d]", fn, n_steps, kBatchMaxSteps);
     const size_t need = batched_ws_bytes(n_lat, geoms, prec, fmt, n_steps);
     if (!work || work_bytes < need) return fail(QDPX_ENOMEM, "%s: workspace of %zu bytes < %zu", fn, work_bytes, need);
+    if (!aligned16(work)) return fail(QDPX_EINVAL, "%s: workspace not 16-byte aligned", fn);  // intermediate links
     std::vector<size_t> lb(n_lat);
     for (int i = 0; i < n_lat; ++i) {
         if (!U_in[i] || !U_out[i]) return fail(QDPX_EINVAL, "%s: NULL links for lattice %d", fn, i);
+        if (!aligned16(U_in[i]) || !aligned16(U_out[i]))
+            return fail(QDPX_EINVAL, "%s: links of lattice %d not 16-byte aligned", fn, i);
         lb[i] = qdpx_links_bytes(&geoms[i], prec, fmt);
     }
     for (int i = 0; i < n_lat; ++i) {

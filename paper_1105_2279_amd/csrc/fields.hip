@@ -40,9 +40,9 @@ int launch_order(const Geo &g, const LaunchCfg &cfg, int groups_per_block) {
 }
 
 // ------------------------------------------------------------ pack / unpack
-// AoS double[V][4][3][3][2] -> SoA complex[mu][row < NR][col][S].
-// One thread per (component, site); the component is blockIdx.y so the SoA
-// writes of a wave are contiguous.
+// AoS double[V][4][3][3][2] -> the SoA link layout (LinkLayout).
+// One thread per (stored element, site); the element is blockIdx.y so the
+// SoA writes of a wave are contiguous (every other slot for paired FP32).
 template <typename R, int NR>
 __global__ void __launch_bounds__(256) k_pack_links(Geo g, const double2 *__restrict__ aos,
                                                     vec2_t<R> *__restrict__ soa) {
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_pack_links(Geo g, const double2 *__rest
     vec2_t<R> o;
     o.x = (R)v.x;  // FP64 -> FP32 conversion rounds to nearest even
     o.y = (R)v.y;
-    soa[(int64_t)comp * g.S + s] = o;
+    soa[LinkLayout<R, NR>::slot(mu, a * 3 + b, g.S, s)] = o;
 }
 
 // SoA -> AoS; one thread per (mu, site), row 2 rebuilt in FP64 for NR == 2.
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_unpack_links(Geo g, const vec2_t<R> *__
     for (int a = 0; a < NR; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            vec2_t<R> v = soa[(int64_t)((mu * NR + a) * 3 + b) * g.S + s];
+            const vec2_t<R> v = soa[LinkLayout<R, NR>::slot(mu, a * 3 + b, g.S, s)];
             m.e[a][b] = Cx<double>{(double)v.x, (double)v.y};
         }
     if constexpr (NR == 2) rebuild_row2(m);

@@ -266,12 +266,29 @@ __device__ __forceinline__ void ldspinor(const real2 *__restrict__ f, long long 
 #pragma unroll
         for (int a = 0; a < 3; ++a) r.c[sp][a] = ldc(f, S, sp * 3 + a, s);
 }
-// links [mu][row][col][S]; with NROWS = 2 the third row is conj(row0 x row1)
+// Link (mu, s): direction mu holds 3*NROWS*S complex slots from slot
+// mu*3*NROWS*S on.  Double: one array of S entries per stored element c = 3a+b.
+// Float (PAIRED): elements 2k, 2k+1 share the 16-byte entry s of array k;
+// the ninth element of a three-row link has an array of its own after the
+// four pair arrays.  With NROWS = 2 the third row is conj(row0 x row1).
+typedef real real4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void ldlink(const real2 *__restrict__ U, long long S, int mu, int s, link &u) {
+    const real2 *d = U + (long long)mu * 3 * NROWS * S;
+#if PAIRED
+    const real4 *P = (const real4 *)d;
+#pragma unroll
+    for (int k = 0; k < (3 * NROWS) / 2; ++k) {
+        const real4 v = P[(long long)k * S + s];
+        u.e[(2 * k) / 3][(2 * k) % 3] = cx{v.x, v.y};
+        u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx{v.z, v.w};
+    }
+    if (NROWS == 3) u.e[2][2] = ldc(d + 8 * S, 0, 0, s);
+#else
 #pragma unroll
     for (int a = 0; a < NROWS; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u.e[a][b] = ldc(U, S, (mu * NROWS + a) * 3 + b, s);
+        for (int b = 0; b < 3; ++b) u.e[a][b] = ldc(d, S, a * 3 + b, s);
+#endif
     if (NROWS == 2) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -345,7 +362,8 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
     std::ostringstream src;
     std::string pre = kPrelude;
     const std::string real = prec == QDPX_F64 ? "double" : "float";
-    src << "#define REAL " << real << "\n#define NROWS " << nrows << "\n" << pre;
+    src << "#define REAL " << real << "\n#define NROWS " << nrows << "\n#define PAIRED " << (prec == QDPX_F32 ? 1 : 0)
+        << "\n" << pre;
     src << "extern \"C\" __global__ void __launch_bounds__(256) qdpx_jit_kernel(int L0, int L1, int L2, int L3, "
            "long long S, const real2 *__restrict__ U";
     for (int i = 0; i < n_fields; ++i) src << ", const real2 *__restrict__ f" << i;
@@ -593,6 +611,7 @@ extern "C" int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geo
         k.n_scalars = src.n_scalars;
     }
     if (!U || !out || !fields) return set_error(QDPX_EINVAL, "qdpx_jit_eval: NULL pointer");
+    if ((uintptr_t)U & 15u) return set_error(QDPX_EINVAL, "qdpx_jit_eval: link field not 16-byte aligned");
     const qdpx_linkfmt fmt = k.nrows == 2 ? QDPX_LINK12 : QDPX_LINK18;
     const size_t fb = qdpx_fermion_bytes(geom, (qdpx_prec)k.prec), lb = qdpx_links_bytes(geom, (qdpx_prec)k.prec, fmt);
     auto overlaps = [](const void *a, size_t na, const void *b, size_t nb) {

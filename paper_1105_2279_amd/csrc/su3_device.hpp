@@ -211,59 +211,113 @@ template <typename R> __device__ __forceinline__ void rebuild_row2(M3<R> &m) {
 }
 
 // ----------------------------------------------------------- SoA link field
-// NR = stored rows (3: LINK18, 2: LINK12).  Element (mu, a, b) of site s is
-// at p[((mu*NR + a)*3 + b)*S + s].
+// NR = stored rows (3: LINK18, 2: LINK12).  Stored element c = 3a + b (row
+// a < NR, column b) of direction mu at site s.  Direction mu occupies the
+// 3*NR*S complex slots from slot mu*3*NR*S on:
+//   FP64  one array of S double2 per element: slot c*S + s;
+//   FP32  elements 2k and 2k+1 share the 16-byte entry s of array k (S
+//         float4 entries, element 2k in the low half): slot 2kS + 2s + (c&1);
+//         with NR = 3 the ninth element (c = 8) has an array of S float2 of
+//         its own after the four pair arrays: slot 8S + s.
+// A FP32 link is then three (LINK12) or five (LINK18) 16-byte loads per lane,
+// which halves the vector-memory instructions the APE staples issue.
+template <typename R, int NR> struct LinkLayout {
+    static constexpr bool kPaired = sizeof(R) == 4;
+    // first slot of the array that holds element c (odd elements start one
+    // slot into their pair array)
+    __host__ __device__ static constexpr int64_t array(int mu, int c, int64_t S) {
+        return (int64_t)mu * 3 * NR * S +
+               (kPaired ? (c < 8 ? (int64_t)(c >> 1) * 2 * S + (c & 1) : 8 * S) : (int64_t)c * S);
+    }
+    // slots between consecutive sites of element c
+    __host__ __device__ static constexpr int stride(int c) { return kPaired && c < 8 ? 2 : 1; }
+    __host__ __device__ static constexpr int64_t slot(int mu, int c, int64_t S, int64_t s) {
+        return array(mu, c, S) + s * stride(c);
+    }
+};
+
+template <typename R> using nv4_t = R __attribute__((ext_vector_type(4)));
+
 template <typename R, int NR> struct LinksRO {
+    using Lay = LinkLayout<R, NR>;
     const vec2_t<R> *__restrict__ p;
     int64_t S;
-    // The component base is uniform across the wave (mu is wave-uniform, a
-    // and b are constants) and the site offset fits 32 bits (V < 2^28), so
-    // every load is one SGPR base + one 32-bit VGPR offset.
-    __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
-        const vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
-        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
+    // The array base is uniform across the wave (mu is wave-uniform, the
+    // element index a constant) and the site offset fits 32 bits (V < 2^28),
+    // so every load is one SGPR base + one 32-bit VGPR offset.
+    template <bool NT = false> __device__ __forceinline__ Cx<R> ld(int mu, int a, int b, int s) const {
+        const int c = a * 3 + b;
+        const char *addr = (const char *)sbase(p + Lay::array(mu, c, S)) +
+                           voff((uint32_t)s * (uint32_t)(Lay::stride(c) * sizeof(vec2_t<R>)));
+        const nv2_t<R> v = NT ? __builtin_nontemporal_load(gptr<nv2_t<R>>(addr)) : *gptr<nv2_t<R>>(addr);
         return Cx<R>{v.x, v.y};
     }
-    __device__ __forceinline__ Cx<R> ld_stream(int mu, int a, int b, int s) const {
-        const vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
-        return load_stream<R>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
+    // FP32: elements 2k and 2k+1 in one 16-byte load
+    template <bool NT> __device__ __forceinline__ void ld_pair(int mu, int k, int s, Cx<R> &e0, Cx<R> &e1) const {
+        const char *addr = (const char *)sbase(p + Lay::array(mu, 2 * k, S)) + voff((uint32_t)s * 16u);
+        const nv4_t<R> v = NT ? __builtin_nontemporal_load(gptr<nv4_t<R>>(addr)) : *gptr<nv4_t<R>>(addr);
+        e0 = Cx<R>{v.x, v.y};
+        e1 = Cx<R>{v.z, v.w};
+    }
+    // stored rows 0 .. ROWS-1 of link (mu, s) into e
+    template <bool NT, int ROWS, int N> __device__ __forceinline__ void load_rows(int mu, int s, Cx<R> (&e)[N][3]) const {
+        static_assert(ROWS <= NR && ROWS <= N, "rows beyond the stored ones");
+        if constexpr (Lay::kPaired) {
+#pragma unroll
+            for (int k = 0; k < (3 * ROWS) / 2; ++k)
+                ld_pair<NT>(mu, k, s, e[(2 * k) / 3][(2 * k) % 3], e[(2 * k + 1) / 3][(2 * k + 1) % 3]);
+            if constexpr (ROWS == 3) e[2][2] = ld<NT>(mu, 2, 2, s);
+        } else {
+#pragma unroll
+            for (int a = 0; a < ROWS; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) e[a][b] = ld<NT>(mu, a, b, s);
+        }
     }
     // full link read once per site (no neighbour reuse): streamed
     __device__ __forceinline__ void full_stream(int mu, int s, M3<R> &m) const {
-#pragma unroll
-        for (int a = 0; a < NR; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m.e[a][b] = ld_stream(mu, a, b, s);
+        load_rows<true, NR>(mu, s, m.e);
         if constexpr (NR == 2) rebuild_row2(m);
     }
-    __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m.e[a][b] = ld(mu, a, b, s);
-    }
+    __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const { load_rows<false, 2>(mu, s, m.e); }
     __device__ __forceinline__ void full(int mu, int s, M3<R> &m) const {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m.e[a][b] = ld(mu, a, b, s);
-        if constexpr (NR == 3) {
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m.e[2][b] = ld(mu, 2, b, s);
-        } else {
-            rebuild_row2(m);
-        }
+        load_rows<false, NR>(mu, s, m.e);
+        if constexpr (NR == 2) rebuild_row2(m);
     }
 };
 
 template <typename R, int NR> struct LinksWO {
+    using Lay = LinkLayout<R, NR>;
     vec2_t<R> *__restrict__ p;
     int64_t S;
-    __device__ __forceinline__ void st(int mu, int a, int b, int s, R re, R im) const {
-        vec2_t<R> *base = sbase(p + (int64_t)((mu * NR + a) * 3 + b) * S);
-        // outputs are never re-read by the kernel that writes them: stream
-        // them past the caches so L2 keeps the neighbour links
-        store_stream<R>((char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), re, im);
+    // Outputs are never re-read by the kernel that writes them: stream them
+    // past the caches so L2 keeps the neighbour links.
+    __device__ __forceinline__ void st(int mu, int c, int s, const Cx<R> &z) const {
+        store_stream<R>((char *)sbase(p + Lay::array(mu, c, S)) +
+                            voff((uint32_t)s * (uint32_t)(Lay::stride(c) * sizeof(vec2_t<R>))),
+                        z.re, z.im);
+    }
+    // the NR stored rows of link (mu, s); FP32 as 16-byte pair stores
+    __device__ __forceinline__ void store(int mu, int s, const Cx<R> (&e)[3][3]) const {
+        if constexpr (Lay::kPaired) {
+#pragma unroll
+            for (int k = 0; k < (3 * NR) / 2; ++k) {
+                const Cx<R> &z0 = e[(2 * k) / 3][(2 * k) % 3], &z1 = e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+                nv4_t<R> v;
+                v.x = z0.re;
+                v.y = z0.im;
+                v.z = z1.re;
+                v.w = z1.im;
+                __builtin_nontemporal_store(
+                    v, gptr_w<nv4_t<R>>((char *)sbase(p + Lay::array(mu, 2 * k, S)) + voff((uint32_t)s * 16u)));
+            }
+            if constexpr (NR == 3) st(mu, 8, s, e[2][2]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < NR; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) st(mu, 3 * a + b, s, e[a][b]);
+        }
     }
 };
 

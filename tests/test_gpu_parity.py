@@ -295,3 +295,29 @@ def test_validation_errors():
     with pytest.raises(q.QdpxError) as e:
         q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1, 1)
     assert e.value.code == -1
+
+
+def test_misaligned_links_rejected():
+    """Link fields are accessed 16 bytes at a time: a pointer that is only
+    8-byte aligned is refused before anything is launched."""
+    c = ctx()
+    L = (4, 4, 4, 4)
+    for prec, fmt in FORMATS:
+        lb = q.qdpx_links_bytes(L, prec, fmt)
+        big = q.empty_bytes(2 * lb + 64)
+        good, mis = big[:lb], big[lb + 40:2 * lb + 40]  # offset 40 = 8 mod 16
+        aos = torch.from_numpy(latgen.haar_links(L, 2).view(np.float64).ravel()).to(dev())
+        q.qdpx_pack_links(c, L, aos, prec, fmt, good)
+        work = q.alloc_workspace(q.OP_APE, L, prec, fmt, 2)
+        wbig = q.empty_bytes(q.qdpx_workspace_bytes(q.OP_APE, L, prec, fmt, 2) + 64)
+        for call in (lambda: q.qdpx_pack_links(c, L, aos, prec, fmt, mis),
+                     lambda: q.qdpx_ape_smear(c, L, prec, fmt, good, mis, 0.5, 1, None, work),
+                     lambda: q.qdpx_ape_smear(c, L, prec, fmt, mis, good, 0.5, 1, None, work),
+                     lambda: q.qdpx_ape_smear(c, L, prec, fmt, good, q.alloc_links(L, prec, fmt), 0.5, 2, None,
+                                              wbig[8:]),
+                     lambda: q.qdpx_plaquette(c, L, prec, fmt, mis, torch.zeros(3, dtype=torch.float64, device=dev()),
+                                              work)):
+            with pytest.raises(q.QdpxError) as e:
+                call()
+            assert e.value.code == -1 and "aligned" in str(e.value)
+    torch.cuda.synchronize()
