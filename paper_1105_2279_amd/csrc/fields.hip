@@ -27,6 +27,13 @@ Geo make_geo(const int32_t L[4]) {
         g.P = g.pbx * (L[1] / 8);
     }
     if (g.bwl || g.st[3] % 64 == 0) g.ncol = g.st[3] / 64;
+    g.dL0 = FastDiv::make(L[0]);
+    g.dL1 = FastDiv::make(L[1]);
+    g.dL2 = FastDiv::make(L[2]);
+    g.dP = FastDiv::make(g.P ? g.P : 1);
+    g.dpbx = FastDiv::make(g.pbx ? g.pbx : 1);
+    g.dplane = FastDiv::make(g.P ? g.P * L[2] : 1);
+    g.dslab = FastDiv::make(g.ncol >= 8 ? g.ncol >> 3 : 1);
     return g;
 }
 

@@ -22,6 +22,30 @@ namespace qdpx {
 // t planes can be walked together (see traverse()).  Otherwise (bwl = 0)
 // group g is the 64 consecutive sites [64 g, 64 g + 64).  The mapping depends
 // only on the extents, so per-group partial sums never depend on the launch.
+// Quotient of a non-negative int n < 2^31 by a fixed divisor d >= 1 as one
+// multiply-high, an add and a shift: with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, n / d = (mulhi(m, n) + n) >> l (the
+// round-up method of Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994; n < 2^31 keeps the sum in 32 bits).
+// The constants are made on the host.  gfx950 has no scalar floating point,
+// so a plain division, even of a wave-uniform value, is a long emulated
+// sequence on the vector ALU; this form stays on the scalar unit for
+// wave-uniform operands and is three instructions per lane otherwise.
+struct FastDiv {
+    uint32_t d, m, l;
+    static FastDiv make(uint32_t d) {
+        FastDiv f;
+        f.d = d;
+        f.l = 0;
+        while ((1ull << f.l) < d) ++f.l;
+        f.m = (uint32_t)(((1ull << 32) * ((1ull << f.l) - d)) / d + 1);
+        return f;
+    }
+    __host__ __device__ __forceinline__ int div(int n) const {
+        return (int)(((uint32_t)(((uint64_t)m * (uint32_t)n) >> 32) + (uint32_t)n) >> l);
+    }
+};
+
 struct Geo {
     int L[4];
     int st[4];  // 1, Lx, Lx*Ly, Lx*Ly*Lz
@@ -31,6 +55,8 @@ struct Geo {
     int pbx;    // bricks along x
     int ncol;   // groups per t plane when every group lies in one t plane, else 0
     int64_t S;  // SoA component stride (elements)
+    // divisors of the site decoding: Lx, Ly, Lz, P, pbx, P*Lz, ncol/8
+    FastDiv dL0, dL1, dL2, dP, dpbx, dplane, dslab;
 };
 
 // Neighbour addressing for one site: coordinates are decoded once, every hop
@@ -40,11 +66,11 @@ struct Site {
     int c[4];
     __device__ __forceinline__ void init(const Geo &g, int site) {
         s = site;
-        int r = site;
-        c[0] = r % g.L[0]; r /= g.L[0];
-        c[1] = r % g.L[1]; r /= g.L[1];
-        c[2] = r % g.L[2];
-        c[3] = r / g.L[2];
+        const int q0 = g.dL0.div(site), q1 = g.dL1.div(q0), q2 = g.dL2.div(q1);
+        c[0] = site - q0 * g.L[0];
+        c[1] = q0 - q1 * g.L[1];
+        c[2] = q1 - q2 * g.L[2];
+        c[3] = q2;
     }
 };
 
@@ -55,9 +81,9 @@ __device__ __forceinline__ int num_groups(const Geo &g) { return (g.V + 63) >> 6
 // linear group.
 __device__ __forceinline__ bool group_site(const Geo &g, int grp, int lane, Site &x) {
     if (g.bwl) {
-        const int p = grp % g.P, r = grp / g.P;
-        const int z = r % g.L[2], t = r / g.L[2];
-        const int xb = p % g.pbx, yb = p / g.pbx;
+        const int r = g.dP.div(grp), p = grp - r * g.P;
+        const int t = g.dL2.div(r), z = r - t * g.L[2];
+        const int yb = g.dpbx.div(p), xb = p - yb * g.pbx;
         const int bw = 1 << g.bwl;
         x.c[0] = xb * bw + (lane & (bw - 1));
         x.c[1] = yb * (64 >> g.bwl) + (lane >> g.bwl);
@@ -77,11 +103,12 @@ __device__ __forceinline__ bool group_site(const Geo &g, int grp, int lane, Site
 // (brick, z) column before moving on, so the blocks in flight on one XCD hold
 // each other's t neighbours in L2.  tw = 1 (or the linear mapping) is the
 // identity.  A bijection on [0, num_groups).
+// tw is a power of two (checked on the host).
 __device__ __forceinline__ int traverse(const Geo &g, int i, int tw) {
     if (!g.bwl || tw <= 1) return i;
-    const int tin = i % tw, rest = i / tw;
+    const int tin = i & (tw - 1), rest = i >> __builtin_ctz(tw);
     const int plane = g.P * g.L[2];
-    const int pz = rest % plane, tc = rest / plane;
+    const int tc = g.dplane.div(rest), pz = rest - tc * plane;
     return pz + plane * (tc * tw + tin);
 }
 
@@ -95,11 +122,12 @@ __device__ __forceinline__ int traverse(const Geo &g, int i, int tw) {
 // in time, so they are served from that XCD's L2.  Requires ncol % 8 == 0 and
 // num_groups % (8 m) == 0 for m groups per block (checked on the host).
 // A bijection.
+// m is a power of two (groups per block times groups per wave).
 __device__ __forceinline__ int slabwalk(const Geo &g, int i, int m) {
-    const int blk = i / m, within = i - blk * m;
+    const int blk = i >> __builtin_ctz(m), within = i & (m - 1);
     const int x = blk & 7, jj = (blk >> 3) * m + within;
     const int cx = g.ncol >> 3;
-    const int t = jj / cx, k = jj - t * cx;
+    const int t = g.dslab.div(jj), k = jj - t * cx;
     return (x * cx + k) + g.ncol * t;
 }
 
