@@ -78,43 +78,44 @@ __device__ __forceinline__ bool owns_plane(int mu, int nu) {
            (mu == 3 && nu < 2);
 }
 
-// Row 2 of a link whose rows 0 and 1 are in A (stored row for LINK18,
-// conj(row0 x row1) for LINK12).
-template <typename R, int NR>
-__device__ __forceinline__ void row2_of(const LinksRO<R, NR> &U, int mu, int s, const M23<R> &A, Cx<R> r[3]) {
-    if constexpr (NR == 3) {
-        if constexpr (LinksRO<R, NR>::Lay::kPaired) {
-            U.template ld_pair<false>(mu, 3, s, r[0], r[1]);  // elements 6 and 7
-            r[2] = U.ld(mu, 2, 2, s);
-        } else {
+// Re Tr[U X^dag] for U, X in SU(3) from their rows 0 and 1 alone.  With
+// p_ab = <X_a, U_b> = sum_j conj(X_aj) U_bj and row 2 of each matrix equal to
+// conj(row0 x row1), the Binet-Cauchy identity <a x b, c x d> =
+// <a, c><b, d> - <a, d><b, c> gives <X_2, U_2> = conj(p00 p11 - p01 p10), so
+// Re Tr[U X^dag] = Re p00 + Re p11 + Re(p00 p11 - p01 p10): four 3-term inner
+// products (link precision) and one 2x2 determinant (FP64) instead of the
+// third row of X.  Exact for SU(3) arguments; stored links and their
+// products are SU(3) to the rounding of the link precision.
+template <typename R> __device__ __forceinline__ double retrace_rows01(const M23<R> &u, const M23<R> &X) {
+    Cx<R> p[2][2];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) r[b] = U.ld(mu, 2, b, s);
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            p[a][b] = Cx<R>{(R)0, (R)0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) cmac_ca(p[a][b], X.e[a][j], u.e[b][j]);
         }
-    } else {
-        r[0] = conj_cross(A.e[0][1], A.e[1][2], A.e[0][2], A.e[1][1]);
-        r[1] = conj_cross(A.e[0][2], A.e[1][0], A.e[0][0], A.e[1][2]);
-        r[2] = conj_cross(A.e[0][0], A.e[1][1], A.e[0][1], A.e[1][0]);
-    }
+    const double p00r = p[0][0].re, p00i = p[0][0].im, p11r = p[1][1].re, p11i = p[1][1].im;
+    const double p01r = p[0][1].re, p01i = p[0][1].im, p10r = p[1][0].re, p10i = p[1][0].im;
+    const double d = fma(p00r, p11r, -(p00i * p11i)) - fma(p01r, p10r, -(p01i * p10i));
+    return (p00r + p11r) + d;
 }
 
 // Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
-// in mask (bits 0..3; all four for the fused plaquette).  With PLQ the full upper staples
-// of the planes this wave owns are also summed into Q (all three rows), so
-// that Re Tr[U_mu(x) Q^dag] is the sum of the traces of the owned plaquettes
-// P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag.
+// in mask (bits 0..3; all four for the fused plaquette).  With PLQ, plq
+// receives the sum over the planes this wave owns of Re Tr[U_mu(x) X^dag],
+// X the plane's upper staple, which is the trace of the plaquette
+// P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag; u0 holds
+// rows 0 and 1 of U_mu(x).
 template <typename R, int NR, bool PLQ>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  unsigned mask, M23<R> &S, M3<R> &Q) {
+                                                  unsigned mask, M23<R> &S, const M23<R> &u0, double &plq) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
-    if constexpr (PLQ) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Q.e[i][j] = Cx<R>{(R)0, (R)0};
-    }
+    plq = 0.0;
     const int s = x.s;
     const int s_mu = hop_fwd(g, s, x.c[mu], mu);
 #pragma unroll 1
@@ -141,27 +142,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
 #pragma unroll
                     for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
                 acc_23_33dag(X, T, C);
-                if constexpr (PLQ) {
-                    Cx<R> a2[3], t2[3];
-                    row2_of(U, nu, s, A, a2);
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        t2[j] = Cx<R>{(R)0, (R)0};
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) cmac(t2[j], a2[kk], B.e[kk][j]);
-                    }
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) cmac_cb(Q.e[2][j], t2[kk], C.e[j][kk]);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) {
-                            Q.e[i][j].re += X.e[i][j].re;
-                            Q.e[i][j].im += X.e[i][j].im;
-                        }
-                }
+                if constexpr (PLQ) plq += retrace_rows01(u0, X);
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -282,15 +263,12 @@ __device__ __forceinline__ void store_narrowed(const LinksWO<R, NR> &out, int mu
 // What one (64-site group, direction) wave computes.
 enum ApeMode { kApe = 0, kApePlaq = 1, kPlaqOnly = 2 };
 
-// Owned-plane upper staples only (all three rows, link precision), summed
-// into Q: the same arithmetic as the owned branch of staple_sum_rows01.
+// The owned planes' plaquette traces only: the same arithmetic as the PLQ
+// branch of staple_sum_rows01, so both give the same value bit for bit.
 template <typename R, int NR>
-__device__ __forceinline__ void owned_upper_staples(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                    M3<R> &Q) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Q.e[i][j] = Cx<R>{(R)0, (R)0};
+__device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
+                                                   const M23<R> &u0) {
+    double plq = 0.0;
     const int s = x.s;
     const int s_mu = hop_fwd(g, s, x.c[mu], mu);
 #pragma unroll 1
@@ -311,43 +289,9 @@ __device__ __forceinline__ void owned_upper_staples(const Geo &g, const LinksRO<
 #pragma unroll
             for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
         acc_23_33dag(X, T, C);
-        Cx<R> a2[3], t2[3];
-        row2_of(U, nu, s, A, a2);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            t2[j] = Cx<R>{(R)0, (R)0};
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) cmac(t2[j], a2[kk], B.e[kk][j]);
-        }
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) cmac_cb(Q.e[2][j], t2[kk], C.e[j][kk]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                Q.e[i][j].re += X.e[i][j].re;
-                Q.e[i][j].im += X.e[i][j].im;
-            }
+        plq += retrace_rows01(u0, X);
     }
-}
-
-// Re Tr[U_mu(x) Q^dag] in FP64 from the link's rows 0, 1 (u0) and row 2.
-template <typename R, int NR>
-__device__ __forceinline__ double retrace_with(const LinksRO<R, NR> &U, int mu, int s, const M23<R> &u0,
-                                               const M3<R> &Q) {
-    Cx<R> u2[3];
-    row2_of(U, mu, s, u0, u2);
-    double p = 0.0;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        p = fma((double)u2[b].re, (double)Q.e[2][b].re, fma((double)u2[b].im, (double)Q.e[2][b].im, p));
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-            p = fma((double)u0.e[a][b].re, (double)Q.e[a][b].re, fma((double)u0.e[a][b].im, (double)Q.e[a][b].im, p));
-    }
-    return p;
+    return plq;
 }
 
 // One wave's share of a step: direction mu of the 64 sites of group grp.
@@ -367,12 +311,10 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
     Site x;
     if (group_site(g, grp, lane, x)) {
         const int s = x.s;
-        M3<R> Q;
         if constexpr (MODE == kPlaqOnly) {
-            owned_upper_staples(g, U, x, mu, Q);
             M23<R> u0;
             U.rows01(mu, s, u0);
-            p = retrace_with(U, mu, s, u0, Q);
+            p = owned_plaquettes(g, U, x, mu, u0);
         } else if (!((mask >> mu) & 1u)) {  // wave-uniform: not smeared
             M3<R> u;
             U.full(mu, s, u);
@@ -392,11 +334,15 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             polar_project(w, v);
             store_narrowed(out, mu, s, v);
         } else {
-            M23<R> S;
-            staple_sum_rows01<R, NR, MODE == kApePlaq>(g, U, x, mu, mask, S, Q);
-            M23<R> u0;
-            U.rows01(mu, s, u0);
-            if constexpr (MODE == kApePlaq) p = retrace_with(U, mu, s, u0, Q);
+            M23<R> S, u0;
+            if constexpr (MODE == kApePlaq) {  // the plaquette needs u0 in the staple loop
+                U.rows01(mu, s, u0);
+                staple_sum_rows01<R, NR, true>(g, U, x, mu, mask, S, u0, p);
+            } else {
+                double unused;
+                staple_sum_rows01<R, NR, false>(g, U, x, mu, mask, S, u0, unused);
+                U.rows01(mu, s, u0);
+            }
             Cx<double> wm[2][3], v[3][3];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
