@@ -33,6 +33,32 @@ def ctx():
     return _ctx
 
 
+_bench_ctx = None
+
+
+def bench_ctx():
+    """A context holding the stored launch table: the geometries bench.py times."""
+    global _bench_ctx
+    if _bench_ctx is None:
+        from paper_1105_2279_amd import tuning
+
+        _bench_ctx = q.Context(0)
+        tuning.load(_bench_ctx)
+    return _bench_ctx
+
+
+FMT_NAMES = {(q.F64, q.LINK18): ("F64", "LINK18"), (q.F32, q.LINK18): ("F32", "LINK18"),
+             (q.F32, q.LINK12): ("F32", "LINK12")}
+
+
+def assert_bench_geometry(op_name, op, L, prec, fmt):
+    """The geometry bench_ctx() launches for this shape is the stored one."""
+    from paper_1105_2279_amd import tuning
+
+    stored = tuning.read()[(op_name, *FMT_NAMES[(prec, fmt)], tuple(L))]
+    assert q.qdpx_tune_get(bench_ctx(), op, L, prec, fmt) == stored
+
+
 def dev():
     return torch.device("cuda:0")
 

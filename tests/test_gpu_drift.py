@@ -11,7 +11,7 @@ import torch
 import latgen
 import oracle
 import paper_1105_2279_amd as q
-from gpuhelp import ctx, dev, need_gpu, su3_defects
+from gpuhelp import assert_bench_geometry, bench_ctx, dev, need_gpu, su3_defects
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,9 @@ def _gpu():
 
 
 def test_ten_steps_step_by_step_against_oracle():
-    c = ctx()
+    c = bench_ctx()  # the launch geometry the benchmark times
+    for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        assert_bench_geometry("APE", q.OP_APE, L, prec, fmt)
     U = latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
     cur = {fmt: q.links_to_device(c, L, U, prec, fmt, dev()) for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12))}
     prec_of = {q.LINK18: q.F64, q.LINK12: q.F32}
@@ -54,7 +56,7 @@ def test_ten_steps_step_by_step_against_oracle():
 
 
 def test_n_steps_call_equals_chained_single_steps():
-    c = ctx()
+    c = bench_ctx()
     Ls = (16, 16, 16, 32)
     U = latgen.haar_links(Ls, 77)
     prec, fmt = q.F32, q.LINK12

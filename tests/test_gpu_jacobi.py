@@ -16,7 +16,7 @@ import torch
 import latgen
 import oracle
 import paper_1105_2279_amd as q
-from gpuhelp import FORMAT_IDS, FORMATS, ctx, dev, need_gpu, rel_err, tol
+from gpuhelp import FORMAT_IDS, FORMATS, assert_bench_geometry, bench_ctx, ctx, dev, need_gpu, rel_err, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +42,8 @@ def gpu_hop(L, U, psi, prec, fmt, mask):
     return q.fermion_to_host(c, L, out, prec)
 
 
-def gpu_jacobi(L, U, chi, prec, fmt, kappa, n, norm, mask):
-    c = ctx()
+def gpu_jacobi(L, U, chi, prec, fmt, kappa, n, norm, mask, context=None):
+    c = context or ctx()
     Ud = q.links_to_device(c, L, U, prec, fmt, dev())
     cd = q.fermion_to_device(c, L, chi, prec, dev())
     work = q.alloc_workspace(q.OP_JACOBI, L, prec, fmt, n, dev())
@@ -84,9 +84,10 @@ def test_jacobi_matches_oracle(L, prec, fmt, n, norm, mask):
 @pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
 def test_jacobi_full_lattice_32x32x32x64(prec, fmt):
     L = (32, 32, 32, 64)
+    assert_bench_geometry("JACOBI", q.OP_JACOBI, L, prec, fmt)  # the geometry the benchmark times
     U, chi = _inputs(L, 2400)
     n = 3
-    got = gpu_jacobi(L, U, chi, prec, fmt, KAPPA, n, 2.0, 0x7)
+    got = gpu_jacobi(L, U, chi, prec, fmt, KAPPA, n, 2.0, 0x7, context=bench_ctx())
     ref = oracle.jacobi_smear(U, chi, KAPPA, n, 2.0, 0x7)
     nrm, mx = rel_err(got, ref)
     print(f"32^3x64 {prec}/{fmt}: rel {nrm:.2e} max {mx:.2e}", flush=True)

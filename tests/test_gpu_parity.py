@@ -13,8 +13,8 @@ import torch
 import latgen
 import oracle
 import paper_1105_2279_amd as q
-from gpuhelp import (FORMAT_IDS, FORMATS, ape, chain, ctx, dev, link_err, need_gpu, plaquette, rel_err, shift,
-                     su3_defects, tol)
+from gpuhelp import (FORMAT_IDS, FORMATS, ape, assert_bench_geometry, bench_ctx, chain, ctx, dev, link_err, need_gpu,
+                     plaquette, rel_err, shift, su3_defects, tol)
 from lathelp import gauge_links, pure_gauge
 
 pytestmark = pytest.mark.gpu
@@ -162,10 +162,12 @@ def big_links():
     return L, latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
 
 
-@pytest.mark.parametrize("prec,fmt", [(q.F64, q.LINK18), (q.F32, q.LINK12)], ids=["f64_18", "f32_12"])
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
 def test_ape_32x32x32x64_sampled(big_links, prec, fmt):
+    """The benchmark's lattice in the launch geometry the benchmark times."""
     L, U = big_links
-    V, plaq = ape(L, U, prec, fmt, 1)
+    assert_bench_geometry("APE", q.OP_APE, L, prec, fmt)
+    V, plaq = ape(L, U, prec, fmt, 1, context=bench_ctx())
     rng = np.random.default_rng(99)
     V4 = V.reshape(-1, 4, 3, 3)
     n = 4096
