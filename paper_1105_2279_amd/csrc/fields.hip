@@ -54,7 +54,7 @@ template <typename R, int NR>
 __global__ void __launch_bounds__(256) k_pack_links(Geo g, const double2 *__restrict__ aos,
                                                     vec2_t<R> *__restrict__ soa) {
     const int s = blockIdx.x * 256 + threadIdx.x;
-    const int comp = blockIdx.y;  // (mu*NR + a)*3 + b
+    const int comp = blockIdx.y;  // enumerates (mu, a, b) as (mu*NR + a)*3 + b
     if (s >= g.V) return;
     const int b = comp % 3, a = (comp / 3) % NR, mu = comp / (3 * NR);
     const double2 v = aos[((int64_t)s * 4 + mu) * 9 + a * 3 + b];

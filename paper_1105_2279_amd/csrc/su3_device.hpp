@@ -9,19 +9,7 @@
 
 namespace qdpx {
 
-// ---------------------------------------------------------------- geometry
-// Extents, per-direction site strides, the padded SoA stride and the
-// mapping of 64-site groups (one group per wave) to sites.
-//
-// Brick mapping (bwl = 4 or 3): when Lx is a multiple of bw = 2^bwl and Ly a
-// multiple of 64/bw, group g is a bw x (64/bw) brick of one (z, t) plane:
-// g = p + P*(z + Lz*t) with p the brick within the xy plane (P bricks per
-// plane, pbx along x); lane l sits at x = xb*bw + l % bw, y = yb*(64/bw) + l / bw.
-// A wave then touches 64/bw rows of bw consecutive sites (whole cache lines),
-// and the groups of one xy plane are numbered consecutively, so a window of
-// t planes can be walked together (see traverse()).  Otherwise (bwl = 0)
-// group g is the 64 consecutive sites [64 g, 64 g + 64).  The mapping depends
-// only on the extents, so per-group partial sums never depend on the launch.
+// ------------------------------------------------------ integer division
 // Quotient of a non-negative int n < 2^31 by a fixed divisor d >= 1 as one
 // multiply-high, an add and a shift: with l = ceil(log2 d) and
 // m = floor(2^32 (2^l - d) / d) + 1, n / d = (mulhi(m, n) + n) >> l (the
@@ -46,6 +34,19 @@ struct FastDiv {
     }
 };
 
+// ---------------------------------------------------------------- geometry
+// Extents, per-direction site strides, the padded SoA stride and the
+// mapping of 64-site groups (one group per wave) to sites.
+//
+// Brick mapping (bwl = 4 or 3): when Lx is a multiple of bw = 2^bwl and Ly a
+// multiple of 64/bw, group g is a bw x (64/bw) brick of one (z, t) plane:
+// g = p + P*(z + Lz*t) with p the brick within the xy plane (P bricks per
+// plane, pbx along x); lane l sits at x = xb*bw + l % bw, y = yb*(64/bw) + l / bw.
+// A wave then touches 64/bw rows of bw consecutive sites (whole cache lines),
+// and the groups of one xy plane are numbered consecutively, so a window of
+// t planes can be walked together (see traverse()).  Otherwise (bwl = 0)
+// group g is the 64 consecutive sites [64 g, 64 g + 64).  The mapping depends
+// only on the extents, so per-group partial sums never depend on the launch.
 struct Geo {
     int L[4];
     int st[4];  // 1, Lx, Lx*Ly, Lx*Ly*Lz
@@ -54,7 +55,7 @@ struct Geo {
     int P;      // bricks per xy plane
     int pbx;    // bricks along x
     int ncol;   // groups per t plane when every group lies in one t plane, else 0
-    int64_t S;  // SoA component stride (elements)
+    int64_t S;  // padded site count: V rounded up to 256
     // divisors of the site decoding: Lx, Ly, Lz, P, pbx, P*Lz, ncol/8
     FastDiv dL0, dL1, dL2, dP, dpbx, dplane, dslab;
 };
