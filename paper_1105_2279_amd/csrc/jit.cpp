@@ -234,7 +234,9 @@ struct Gen {
         case Node::Sum: {
             const std::string v = fresh("v");
             body << "    spinor " << v << "; szero(" << v << ");\n";
-            body << "#pragma unroll 1\n    for (int m = 0; m < 4; ++m) {\n";
+            // Two directions per trip keep two sets of neighbour loads in
+            // flight; a full unroll needs every register (occupancy 1).
+            body << "#pragma unroll 2\n    for (int m = 0; m < 4; ++m) {\n";
             body << "    if (!((" << n.mask << "u >> m) & 1u)) continue;\n";
             const std::string a = emit(*n.kids[0], s, c);
             body << "    sadd(" << v << ", " << a << ", " << v << ");\n    }\n";

@@ -150,6 +150,14 @@ def test_batched_validation():
         q.qdpx_ape_smear_batched(c, Ls, prec, fmt, Uds, [q.alloc_links(L, prec, fmt) for L in Ls], 0.5, 1, None,
                                  work[:100])
     assert e.value.code == -3
+    with pytest.raises(q.QdpxError) as e:  # an empty batch
+        q.qdpx_ape_smear_batched(c, [], prec, fmt, [], [], 0.5, 1, None, work)
+    assert e.value.code == -1 and "n_lat" in str(e.value)
+    with pytest.raises(q.QdpxError) as e:  # workspace only 8-byte aligned (it holds intermediate links)
+        need = q.qdpx_workspace_bytes(q.OP_BATCHED, Ls, prec, fmt)
+        q.qdpx_ape_smear_batched(c, Ls, prec, fmt, Uds, [q.alloc_links(L, prec, fmt) for L in Ls], 0.5, 1, None,
+                                 q.empty_bytes(need + 64)[8:])
+    assert e.value.code == -1 and "aligned" in str(e.value)
     with pytest.raises(q.QdpxError) as e:
         big = (64, 64, 64, 32)  # beyond the per-lattice limit of the batched kernel
         q.qdpx_workspace_bytes(q.OP_BATCHED, [big], prec, fmt)
