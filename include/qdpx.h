@@ -33,8 +33,9 @@
  *               of S float2 of its own after the four pair arrays.
  *   Either way a direction takes 3*rows*S complex slots.  Fermions:
  *   complex[spin][colour][S], complex = double2 (F64) or float2 (F32).
- *   Link fields, and workspaces that hold intermediate links, must be
- *   16-byte aligned (else QDPX_EINVAL).
+ *   Link fields and workspaces must be 16-byte aligned, Dirac fields
+ *   aligned to their complex element (8 bytes F32, 16 bytes F64); other
+ *   pointers are refused with QDPX_EINVAL before anything is launched.
  *
  * Memory and streams.  Every pointer argument named *_dev, and every field
  *   argument (U, psi, phi, chi, ...), is a DEVICE pointer owned by the caller.

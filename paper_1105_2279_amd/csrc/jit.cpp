@@ -621,8 +621,13 @@ extern "C" int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geo
         return x < y + nb && y < x + na;
     };
     if (overlaps(out, fb, U, lb)) return set_error(QDPX_EALIAS, "qdpx_jit_eval: out overlaps U");
+    const uintptr_t elem = k.prec == QDPX_F64 ? 16 : 8;  // fields are accessed one complex element at a time
+    if ((uintptr_t)out % elem) return set_error(QDPX_EINVAL, "qdpx_jit_eval: out not aligned to its element size");
+    if (norm2 && ((uintptr_t)work & 15u)) return set_error(QDPX_EINVAL, "qdpx_jit_eval: workspace not 16-byte aligned");
     for (int i = 0; i < k.n_fields; ++i) {
         if (!fields[i]) return set_error(QDPX_EINVAL, "qdpx_jit_eval: NULL field");
+        if ((uintptr_t)fields[i] % elem)
+            return set_error(QDPX_EINVAL, "qdpx_jit_eval: field not aligned to its element size");
         if (overlaps(out, fb, fields[i], fb)) return set_error(QDPX_EALIAS, "qdpx_jit_eval: out overlaps a field");
     }
     if (k.n_scalars && !scalars) return set_error(QDPX_EINVAL, "qdpx_jit_eval: scalars is NULL");

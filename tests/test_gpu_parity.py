@@ -322,4 +322,20 @@ def test_misaligned_links_rejected():
             with pytest.raises(q.QdpxError) as e:
                 call()
             assert e.value.code == -1 and "aligned" in str(e.value)
+        # Dirac fields: aligned to their complex element (8 bytes F32, 16 F64)
+        fb = q.qdpx_fermion_bytes(L, prec)
+        fbig = q.empty_bytes(3 * fb + 64)
+        psi, chi = fbig[:fb], fbig[fb + 64:2 * fb + 64]
+        off = 4 if prec == q.F32 else 8
+        bad = fbig[2 * fb + 64 + off:3 * fb + 64 + off - 16]
+        shift_ws = q.alloc_workspace(q.OP_SHIFT, L, prec, fmt, 1)
+        for call in (lambda: q.qdpx_eval_hop(c, L, prec, fmt, good, bad, chi, 0xF),
+                     lambda: q.qdpx_eval_hop(c, L, prec, fmt, good, psi, bad, 0xF),
+                     lambda: q.qdpx_eval_shift_mul_axpy(c, L, prec, fmt, good, psi, None, 0.3, bad, None, None),
+                     lambda: q.qdpx_eval_shift_mul_axpy(c, L, prec, fmt, good, psi, None, 0.3, chi,
+                                                        torch.zeros(1, dtype=torch.float64, device=dev()),
+                                                        shift_ws[8:])):
+            with pytest.raises(q.QdpxError) as e:
+                call()
+            assert e.value.code == -1 and "aligned" in str(e.value)
     torch.cuda.synchronize()
