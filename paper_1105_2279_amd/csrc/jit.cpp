@@ -228,7 +228,7 @@ struct Gen {
         }
         case Node::Scale: {
             const std::string a = emit(*n.kids[0], s, c), v = fresh("v");
-            body << "    spinor " << v << "; sscale(s" << n.idx << ", " << a << ", " << v << ");\n";
+            body << "    spinor " << v << "; sscale(scal" << n.idx << ", " << a << ", " << v << ");\n";
             return v;
         }
         case Node::Sum: {
@@ -370,7 +370,9 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
            "long long S, const real2 *__restrict__ U";
     for (int i = 0; i < n_fields; ++i) src << ", const real2 *__restrict__ f" << i;
     src << ", real2 *__restrict__ out";
-    for (int i = 0; i < n_scalars; ++i) src << ", real s" << i;
+    // scalar K is the parameter scalK: generated locals are named by fresh()
+    // as one of v, u, s, c followed by a number, so sK would clash with a site
+    for (int i = 0; i < n_scalars; ++i) src << ", real scal" << i;
     src << ", double *__restrict__ partials) {\n";
     src << "    const int V = L0 * L1 * L2 * L3;\n"
            "    const int st0 = 1, st1 = L0, st2 = L0 * L1, st3 = L0 * L1 * L2;\n"
@@ -540,8 +542,17 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
     const std::string dir = cache_dir(), path = dir + "/" + hex + ".co";
     std::vector<char> code;
     if (read_file(path, code)) {
-        k.from_cache = true;
-    } else {
+        // a cached object that no longer loads (a truncated or foreign file)
+        // is dropped and rebuilt; the failed load's error is cleared so that
+        // the next launch check does not report it
+        if (hipModuleLoadData(&k.module, code.data()) == hipSuccess) {
+            k.from_cache = true;
+        } else {
+            (void)hipGetLastError();
+            std::remove(path.c_str());
+        }
+    }
+    if (!k.from_cache) {
         hiprtcProgram prog;
         if (hiprtcCreateProgram(&prog, k.source.c_str(), "qdpx_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
             return set_error(QDPX_EHIP, "qdpx_jit_compile: hiprtcCreateProgram failed");
@@ -564,10 +575,14 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
         make_dirs(dir);
         write_file_atomic(path, code);
     }
-    hipError_t e = hipModuleLoadData(&k.module, code.data());
-    if (e != hipSuccess) return set_error(QDPX_EHIP, "qdpx_jit_compile: hipModuleLoadData failed");
+    hipError_t e = hipSuccess;
+    if (!k.from_cache && (e = hipModuleLoadData(&k.module, code.data())) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QDPX_EHIP, "qdpx_jit_compile: hipModuleLoadData failed");
+    }
     e = hipModuleGetFunction(&k.fn, k.module, "qdpx_jit_kernel");
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         hipModuleUnload(k.module);
         return set_error(QDPX_EHIP, "qdpx_jit_compile: kernel not found in the code object");
     }

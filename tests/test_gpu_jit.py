@@ -23,6 +23,10 @@ EXPRS = [
     ("(add (sum 0xF (umul m (shift f0 + m))) (scale s0 f1))", 2, [0.3]),
     ("(sub (shift (umul 2 (shift f1 - 0)) + 3) (scale s1 (sum 0x5 (uadj m (shift f0 + m)))))", 2, [0.0, 1.7]),
     ("(shift (shift (uadj 1 (shift f0 - 1)) + 1) - 3)", 1, []),
+    # a shifted field and a scalar at the top level: the generated site index
+    # of the shift and the scalar parameter once shared a name
+    ("(add (shift f0 + 1) (scale s0 f0))", 1, [0.7]),
+    ("(sub (scale s1 (shift f1 - 2)) (scale s0 (shift f0 + 3)))", 2, [-1.3, 0.4]),
 ]
 LATTICES = [(4, 4, 4, 4), (3, 5, 4, 7), (8, 6, 2, 4)]
 
@@ -93,6 +97,27 @@ def test_jit_cache_reuses_code_object():
     assert hit2 and src1 == src2
     c1.close()
     c2.close()
+
+
+def test_jit_cache_rebuilds_an_unloadable_entry(tmp_path, monkeypatch):
+    """A cache entry that is not a code object is dropped and rebuilt."""
+    monkeypatch.setenv("QDPX_JIT_CACHE", str(tmp_path / "cache"))
+    e = "(add (shift f0 + 1) (scale s0 f0))"
+    c1 = q.Context(0)
+    q.qdpx_jit_compile(c1, e, q.F64, q.LINK18, 1, 1)
+    files = list((tmp_path / "cache").glob("*.co"))
+    assert len(files) == 1
+    files[0].write_bytes(b"not a code object")
+    c2 = q.Context(0)
+    k2 = q.qdpx_jit_compile(c2, e, q.F64, q.LINK18, 1, 1)
+    assert not q.qdpx_jit_info(c2, k2)[0]
+    L = (4, 6, 4, 4)
+    U, (psi,), got, _ = run(L, e, 1, [0.7], q.F64, q.LINK18, 7500, context=c2)
+    assert rel_err(got, expr.evaluate(e, U, [psi], [0.7]))[0] < 1e-14
+    c3 = q.Context(0)
+    assert q.qdpx_jit_info(c3, q.qdpx_jit_compile(c3, e, q.F64, q.LINK18, 1, 1))[0]  # rewritten
+    for c in (c1, c2, c3):
+        c.close()
 
 
 def test_jit_graph_replay_matches_eager():

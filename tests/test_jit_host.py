@@ -5,6 +5,7 @@ instructions (no GPU needed)."""
 
 import ctypes
 import os
+import re
 import shutil
 import subprocess
 
@@ -22,6 +23,26 @@ def test_generate_valid_expressions():
         for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK18), (q.F32, q.LINK12)):
             src = q.jit_generate(e, prec, fmt, nf, ns)
             assert "qdpx_jit_kernel" in src and ("double" in src) == (prec == q.F64 or "(double)" in src)
+
+
+@pytest.mark.parametrize("e,nf,ns", [(JACOBI, 2, 1), ("(add (shift f0 + 1) (scale s0 f0))", 1, 1),
+                                     ("(sub (scale s1 (shift f1 - 2)) (scale s0 (shift f0 + 3)))", 2, 2),
+                                     ("(scale s2 (sum 0xF (umul m (shift (scale s1 f0) + m))))", 1, 3)])
+def test_generated_locals_never_shadow_parameters(e, nf, ns):
+    """Every name the kernel declares in its body differs from its parameter
+    names, so a scalar or field argument is never hidden by a local (the
+    site index of a shift once took the name of scalar 0)."""
+    src = q.jit_generate(e, q.F64, q.LINK18, nf, ns)
+    sig = src[src.index("qdpx_jit_kernel("):]
+    params = re.findall(r"(\w+)\s*[,)]", sig[:sig.index("{")])
+    body = sig[sig.index("{"):]
+    assert {"U", "out", "partials"} <= set(params) and len(params) == 8 + nf + ns
+    for p in params:
+        # a declaration "type p = ...", "type p;" or a continued one ", p = ..."
+        decl = rf"(?:\b(?:int|spinor|link|double|cx|real)\s+|,\s*){p}\s*[=;]"
+        assert not re.search(decl, body), p
+    for k in range(ns):
+        assert f"real scal{k}" in sig
 
 
 @pytest.mark.parametrize("bad", ["(umul m f0)", "(sum 0x10 f0)", "(add f0)", "(shift f0 * 1)", "(scale s3 f0)",
