@@ -27,6 +27,11 @@ EXPRS = [
     # of the shift and the scalar parameter once shared a name
     ("(add (shift f0 + 1) (scale s0 f0))", 1, [0.7]),
     ("(sub (scale s1 (shift f1 - 2)) (scale s0 (shift f0 + 3)))", 2, [-1.3, 0.4]),
+    # a shifted sum, a scale inside a sum, and a double shift beside a shifted sum
+    ("(shift (sum 0x3 (umul m (shift f0 + m))) - 2)", 1, []),
+    ("(sum 0xF (scale s0 (uadj m (shift f1 - m))))", 2, [0.5]),
+    ("(add (shift (shift f0 + 3) + 3) (shift (sum 0x9 (sub (umul m f1) (scale s1 (shift f0 - m)))) + 0))", 2,
+     [0.5, -2.0]),
 ]
 LATTICES = [(4, 4, 4, 4), (3, 5, 4, 7), (8, 6, 2, 4)]
 
