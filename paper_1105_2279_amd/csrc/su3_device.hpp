@@ -153,7 +153,6 @@ template <typename R> using vec2_t = typename V2<R>::T;
 
 template <typename R> struct Cx { R re, im; };
 
-template <typename R> __device__ __forceinline__ Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
 
 // Every field lives in global memory.  Pointers that come out of a device
 // table are generic; converting them to the global address space lets the
@@ -183,10 +182,6 @@ __device__ __forceinline__ uint32_t voff(uint32_t o) {
 // Streaming (non-temporal) access to one complex element: the builtins need a
 // native two-wide vector type.
 template <typename R> using nv2_t = R __attribute__((ext_vector_type(2)));
-template <typename R> __device__ __forceinline__ Cx<R> load_stream(const void *addr) {
-    const nv2_t<R> v = __builtin_nontemporal_load(gptr<nv2_t<R>>(addr));
-    return Cx<R>{v.x, v.y};
-}
 template <typename R> __device__ __forceinline__ void store_stream(void *addr, R re, R im) {
     nv2_t<R> v;
     v.x = re;
@@ -365,11 +360,6 @@ template <typename R> struct FermRO {
     __device__ __forceinline__ Cx<R> ld_at(const vec2_t<R> *b, int s) const {
         const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
         return Cx<R>{v.x, v.y};
-    }
-    // a field read once per site (no neighbour reuse): stream it
-    __device__ __forceinline__ Cx<R> ld_stream(int sp, int c, int s) const {
-        const vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
-        return load_stream<R>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
     }
 };
 template <typename R> struct FermWO {
