@@ -1,0 +1,49 @@
+"""Host-side pieces of bench.py: the one-GPU guard, and the rule that HBM
+traffic comes from a committed counter summary only while the kernel sources
+still hash to the value the summary records; the summaries' commands run
+committed files only."""
+
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("md,sources", [(bench.APE_COUNTERS_MD, bench.APE_SOURCES),
+                                        (bench.HOP_COUNTERS_MD, bench.HOP_SOURCES)], ids=["ape", "hop"])
+def test_traffic_only_while_sources_match(md, sources, tmp_path):
+    text = open(md).read()
+    recorded = re.search(r"source hash: `([0-9a-f]+)`", text).group(1)
+    for name in ("f32_12", "f64_18", "f32_18"):
+        stored = float(re.search(r"traffic %s: ([0-9.eE+]+)" % name, text).group(1))
+        got = bench.measured_traffic(md, sources, name)
+        if recorded == bench.kernel_source_hash(sources):
+            assert got == stored
+        else:
+            assert got is None
+    stale = tmp_path / "stale.md"
+    stale.write_text(text.replace(recorded, "0" * len(recorded)))
+    assert bench.measured_traffic(str(stale), sources, "f32_12") is None
+    assert bench.measured_traffic(str(tmp_path / "missing.md"), sources, "f32_12") is None
+
+
+def test_profile_commands_run_committed_files():
+    for f in os.listdir(os.path.join(ROOT, "profiles")):
+        text = open(os.path.join(ROOT, "profiles", f)).read()
+        cmds = [l for l in text.splitlines() if " rocprofv3 " in l and l.startswith("timeout")]
+        assert cmds, f
+        for c in cmds:
+            assert "-- python3 -u bench.py" in c and "_work" not in c, c
