@@ -301,6 +301,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(U)
+        extras["cpu_oracle_host"] = cpu_host_context(latgen)
 
     line = {
         "metric": "APE link-updates/s + HBM GB/s fraction, FP32/batched vs FP64, 32^3x64",
@@ -567,6 +568,36 @@ def cpu_baseline(U):
         "sample": f"{n} FP64 APE steps over the full {L[0]}^3x{L[3]} lattice ({4 * V * n} link updates) "
                   f"in {t:.2f} s",
     }
+
+
+def cpu_host_context(latgen):
+    """The host the oracle ran on (CPU model, logical CPUs, memory) and the
+    oracle's single-thread rate: one FP64 APE step on 16^3x32."""
+    import oracle
+
+    model, mem_gb = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), model)
+        with open("/proc/meminfo") as fh:
+            kb = next((int(l.split()[1]) for l in fh if l.startswith("MemTotal")), None)
+            mem_gb = None if kb is None else round(kb / 2**20, 1)
+    except OSError:
+        pass
+    Ls = (16, 16, 16, 32)
+    U = latgen.haar_links(Ls, latgen.SEEDS["shift_16x16x16x32"]["links"])
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.ape_step(U, ALPHA)
+        t = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    rate = 4.0 * latgen.volume(Ls) / t
+    log(f"cpu baseline: one thread {rate / 1e6:.2f} M link-updates/s on {model}")
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_gb": mem_gb, "threads_used": threads,
+            "single_thread_link_updates_per_s": rate, "single_thread_sample": "1 FP64 APE step on 16^3x32"}
 
 
 if __name__ == "__main__":
