@@ -102,6 +102,19 @@ template <typename R> __device__ __forceinline__ double retrace_rows01(const M23
     return (p00r + p11r) + d;
 }
 
+// Rows 0 and 1 of U_nu(x) from the LDS copy the block stages for its group:
+// own[(nu*3 + k)*64 + lane] holds elements 2k and 2k+1 (FP32 only).
+template <typename R>
+__device__ __forceinline__ void own_rows01(const nv4_t<R> *own, int nu, M23<R> &A) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const nv4_t<R> v = own[(nu * 3 + k) * 64 + lane];
+        A.e[(2 * k) / 3][(2 * k) % 3] = Cx<R>{v.x, v.y};
+        A.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = Cx<R>{v.z, v.w};
+    }
+}
+
 // Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
 // in mask (bits 0..3; all four for the fused plaquette).  With PLQ, plq
 // receives the sum over the planes this wave owns of Re Tr[U_mu(x) X^dag],
@@ -110,7 +123,8 @@ template <typename R> __device__ __forceinline__ double retrace_rows01(const M23
 // rows 0 and 1 of U_mu(x).
 template <typename R, int NR, bool PLQ>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  unsigned mask, M23<R> &S, const M23<R> &u0, double &plq) {
+                                                  unsigned mask, M23<R> &S, const M23<R> &u0, double &plq,
+                                                  const nv4_t<R> *own = nullptr) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -125,7 +139,8 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
         {
             M23<R> A;
-            U.rows01(nu, s, A);
+            if (own) own_rows01(own, nu, A);  // wave nu's own link, staged in LDS
+            else U.rows01(nu, s, A);
             M3<R> B;
             U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
             M23<R> T;
@@ -304,7 +319,7 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
 template <typename R, int NR, int MODE, int PROJ = 0>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
                                           double c2, unsigned mask, double *__restrict__ partials, int grp, int mu,
-                                          int lane) {
+                                          int lane, const nv4_t<R> *own = nullptr) {
     static_assert(PROJ == 0 || MODE == kApe, "the polar projection runs without the fused plaquette");
     const int ngroups = num_groups(g);
     double p = 0.0;
@@ -336,12 +351,14 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
         } else {
             M23<R> S, u0;
             if constexpr (MODE == kApePlaq) {  // the plaquette needs u0 in the staple loop
-                U.rows01(mu, s, u0);
-                staple_sum_rows01<R, NR, true>(g, U, x, mu, mask, S, u0, p);
+                if (own) own_rows01(own, mu, u0);
+                else U.rows01(mu, s, u0);
+                staple_sum_rows01<R, NR, true>(g, U, x, mu, mask, S, u0, p, own);
             } else {
                 double unused;
-                staple_sum_rows01<R, NR, false>(g, U, x, mu, mask, S, u0, unused);
-                U.rows01(mu, s, u0);
+                staple_sum_rows01<R, NR, false>(g, U, x, mu, mask, S, u0, unused, own);
+                if (own) own_rows01(own, mu, u0);
+                else U.rows01(mu, s, u0);
             }
             Cx<double> wm[2][3], v[3][3];
 #pragma unroll
