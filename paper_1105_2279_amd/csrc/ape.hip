@@ -33,22 +33,8 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
             const int i = (tile * NS + j) * gpb + (w >> 2);
             const bool valid = i < ngroups;
             const int grp = !valid ? 0 : xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
-            Site x;
-            const bool live = valid && group_site(g, grp, lane, x);
             if (j > 0) __syncthreads();  // the previous group's copies have been read
-            if (live) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Cx<R> e0, e1;
-                    U.template ld_pair<false>(mu, k, x.s, e0, e1);
-                    nv4_t<R> v;
-                    v.x = e0.re;
-                    v.y = e0.im;
-                    v.z = e1.re;
-                    v.w = e1.im;
-                    mine[(mu * 3 + k) * 64 + lane] = v;
-                }
-            }
+            if (valid) stage_own_link(g, U, grp, mu, lane, mine);
             __syncthreads();
             if (valid) ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, mine);
         }
@@ -121,12 +107,12 @@ __global__ void __launch_bounds__(256) k_plaquette(Geo g, LinksRO<R, NR> U, doub
         for (int mu = 0; mu < 3; ++mu) {
             M3<double> a;
             load_f64(U, mu, s, a);
-            const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+            const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
 #pragma unroll 1
             for (int nu = mu + 1; nu < 4; ++nu) {
                 M3<double> b, c, d;
                 load_f64(U, nu, s_mu, b);                                // U_nu(x+mu)
-                load_f64(U, mu, hop_fwd(g, s, x.c[nu], nu), c);          // U_mu(x+nu)
+                load_f64(U, mu, hop_fwd(g, s, coord(x, nu), nu), c);          // U_mu(x+nu)
                 load_f64(U, nu, s, d);                                   // U_nu(x)
                 // Re Tr[(a b)(d c)^dag]
                 double p = 0.0;

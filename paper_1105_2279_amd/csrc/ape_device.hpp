@@ -115,6 +115,27 @@ __device__ __forceinline__ void own_rows01(const nv4_t<R> *own, int nu, M23<R> &
     }
 }
 
+// Stage rows 0 and 1 of this wave's own link U_mu(x) for the sites of group
+// grp into own[(mu*3 + k)*64 + lane] (FP32 pairs), where own_rows01 of the
+// block's other direction waves reads them after a barrier.
+template <typename R, int NR>
+__device__ __forceinline__ void stage_own_link(const Geo &g, const LinksRO<R, NR> &U, int grp, int mu, int lane,
+                                               nv4_t<R> *own) {
+    Site x;
+    if (!group_site(g, grp, lane, x)) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Cx<R> e0, e1;
+        U.template ld_pair<false>(mu, k, x.s, e0, e1);
+        nv4_t<R> v;
+        v.x = e0.re;
+        v.y = e0.im;
+        v.z = e1.re;
+        v.w = e1.im;
+        own[(mu * 3 + k) * 64 + lane] = v;
+    }
+}
+
 // Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
 // in mask (bits 0..3; all four for the fused plaquette).  With PLQ, plq
 // receives the sum over the planes this wave owns of Re Tr[U_mu(x) X^dag],
@@ -131,7 +152,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
     plq = 0.0;
     const int s = x.s;
-    const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+    const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         const int nu = k + (k >= mu);
@@ -142,7 +163,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             if (own) own_rows01(own, nu, A);  // wave nu's own link, staged in LDS
             else U.rows01(nu, s, A);
             M3<R> B;
-            U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
+            U.full(mu, hop_fwd(g, s, coord(x, nu), nu), B);
             M23<R> T;
             mul_23_33(A, B, T);
             M3<R> C;
@@ -171,7 +192,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         }
         // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
         {
-            const int y = hop_bwd(g, s, x.c[nu], nu);
+            const int y = hop_bwd(g, s, coord(x, nu), nu);
             M3<R> A;
             U.full(nu, y, A);
             M3<R> B;
@@ -179,7 +200,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             M23<R> T;
             mul_dag23_33(A, B, T);
             M3<R> C;
-            U.full(nu, hop_fwd(g, y, x.c[mu], mu), C);  // y has the same mu-coordinate as x
+            U.full(nu, hop_fwd(g, y, coord(x, mu), mu), C);  // y has the same mu-coordinate as x
             acc_23_33(S, T, C);
         }
     }
@@ -285,7 +306,7 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
                                                    const M23<R> &u0) {
     double plq = 0.0;
     const int s = x.s;
-    const int s_mu = hop_fwd(g, s, x.c[mu], mu);
+    const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         const int nu = k + (k >= mu);
@@ -293,7 +314,7 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
         M23<R> A;
         U.rows01(nu, s, A);
         M3<R> B;
-        U.full(mu, hop_fwd(g, s, x.c[nu], nu), B);
+        U.full(mu, hop_fwd(g, s, coord(x, nu), nu), B);
         M23<R> T;
         mul_23_33(A, B, T);
         M3<R> C;

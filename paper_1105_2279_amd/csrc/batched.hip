@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat
     __shared__ int s_ok;
     __shared__ double lds[kReduceBlock / 64];
     __shared__ double stage[2][kBatchMaxStage];
+    __shared__ nv4_t<R> own[sizeof(R) == 4 ? 4 * 3 * 64 : 1];  // the group's own links (FP32)
     // mu is wave-uniform; readfirstlane lets the compiler keep it in an SGPR
     const int mu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int xid = __builtin_amdgcn_readfirstlane(xcd_id());
@@ -118,8 +119,18 @@ __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat
                     const LinksWO<R, NR> O{(vec2_t<R> *)dst, L.g.S};
                     if (ape) {
 #pragma unroll 1
-                        for (int row = row0; row < row1; ++row)
-                            ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, col + L.ncol * row, mu, lane);
+                        for (int row = row0; row < row1; ++row) {
+                            const int grp = col + L.ncol * row;
+                            if constexpr (sizeof(R) == 4) {  // own links staged in LDS, as the single-lattice step
+                                // (take_ticket's barriers separate items; rows of one item need their own)
+                                if (row > row0) __syncthreads();
+                                stage_own_link(L.g, U, grp, mu, lane, own);
+                                __syncthreads();
+                                ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, own);
+                            } else {
+                                ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane);
+                            }
+                        }
                     } else {
 #pragma unroll 1
                         for (int row = row0; row < row1; ++row)
