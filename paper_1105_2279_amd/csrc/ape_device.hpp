@@ -102,6 +102,16 @@ template <typename R> __device__ __forceinline__ double retrace_rows01(const M23
     return (p00r + p11r) + d;
 }
 
+// Coordinate mu of x for a run-time, wave-uniform mu.  The FP32 steps read it
+// through selects: with their LDS staging, indexing the array made the
+// batched kernel keep the coordinates in scratch.  The FP64 steps index the
+// array, which the compiler keeps in registers, and the selects would cost
+// them a wave of occupancy.
+template <typename R> __device__ __forceinline__ int site_coord(const Site &x, int mu) {
+    if constexpr (sizeof(R) == 4) return coord(x, mu);
+    else return x.c[mu];
+}
+
 // Rows 0 and 1 of U_nu(x) from the LDS copy the block stages for its group:
 // own[(nu*3 + k)*64 + lane] holds elements 2k and 2k+1 (FP32 only).
 template <typename R>
@@ -152,7 +162,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
     plq = 0.0;
     const int s = x.s;
-    const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
+    const int s_mu = hop_fwd(g, s, site_coord<R>(x, mu), mu);
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         const int nu = k + (k >= mu);
@@ -163,7 +173,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             if (own) own_rows01(own, nu, A);  // wave nu's own link, staged in LDS
             else U.rows01(nu, s, A);
             M3<R> B;
-            U.full(mu, hop_fwd(g, s, coord(x, nu), nu), B);
+            U.full(mu, hop_fwd(g, s, site_coord<R>(x, nu), nu), B);
             M23<R> T;
             mul_23_33(A, B, T);
             M3<R> C;
@@ -192,7 +202,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         }
         // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
         {
-            const int y = hop_bwd(g, s, coord(x, nu), nu);
+            const int y = hop_bwd(g, s, site_coord<R>(x, nu), nu);
             M3<R> A;
             U.full(nu, y, A);
             M3<R> B;
@@ -200,7 +210,7 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             M23<R> T;
             mul_dag23_33(A, B, T);
             M3<R> C;
-            U.full(nu, hop_fwd(g, y, coord(x, mu), mu), C);  // y has the same mu-coordinate as x
+            U.full(nu, hop_fwd(g, y, site_coord<R>(x, mu), mu), C);  // y has the same mu-coordinate as x
             acc_23_33(S, T, C);
         }
     }
@@ -306,7 +316,7 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
                                                    const M23<R> &u0) {
     double plq = 0.0;
     const int s = x.s;
-    const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
+    const int s_mu = hop_fwd(g, s, site_coord<R>(x, mu), mu);
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         const int nu = k + (k >= mu);
@@ -314,7 +324,7 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
         M23<R> A;
         U.rows01(nu, s, A);
         M3<R> B;
-        U.full(mu, hop_fwd(g, s, coord(x, nu), nu), B);
+        U.full(mu, hop_fwd(g, s, site_coord<R>(x, nu), nu), B);
         M23<R> T;
         mul_23_33(A, B, T);
         M3<R> C;
