@@ -296,6 +296,7 @@ def main():
         extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen, table))
         extras.update(jit_extras(torch, q, ctx, dev, stream, latgen))
+        extras.update(pack_extras(torch, q, ctx, dev, stream, latgen, U))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -331,6 +332,31 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def pack_extras(torch, q, ctx, dev, stream, latgen, U):
+    """Boundary staging at 32^3x64: the canonical FP64 links (already in device
+    memory) into each library layout and back, outside every timed step."""
+    Ls = (32, 32, 32, 64)
+    V = latgen.volume(Ls)
+    aos = torch.from_numpy(U.view("float64").reshape(-1)).to(dev)
+    back = torch.empty_like(aos)
+    aos_bytes = aos.numel() * 8
+    out = {}
+    for name, prec, fmt in (("f64_18", q.F64, q.LINK18), ("f32_18", q.F32, q.LINK18), ("f32_12", q.F32, q.LINK12)):
+        soa = q.alloc_links(Ls, prec, fmt, dev)
+        pack = lambda: q.qdpx_pack_links(ctx, Ls, aos, prec, fmt, soa, stream)
+        unpack = lambda: q.qdpx_unpack_links(ctx, Ls, soa, prec, fmt, back, stream)
+        pack(), unpack()
+        torch.cuda.synchronize()
+        ms_p = time_calls(torch, pack, 5, stream) / 5
+        ms_u = time_calls(torch, unpack, 5, stream) / 5
+        moved = aos_bytes + soa.numel()
+        out[name] = {"pack_ms": ms_p, "unpack_ms": ms_u, "pack_gbs": moved / (ms_p / 1e3) / 1e9,
+                     "unpack_gbs": moved / (ms_u / 1e3) / 1e9}
+        log(f"pack {name}: {ms_p:.2f} ms, unpack {ms_u:.2f} ms for {V} sites")
+        del soa
+    return {"pack_unpack_links_32x32x32x64": out}
 
 
 def shift_extras(torch, q, ctx, dev, stream, latgen, np, table):
