@@ -535,7 +535,7 @@ static size_t batched_ws_bytes(int n_lat, const qdpx_geom *geoms, qdpx_prec prec
 // of arguments and kept by the context (like the paper's device storage for
 // shift tables, section 5.2); later calls, and graph replays, reuse it.
 static void batch_cache_free(qdpx_ctx *ctx) {
-    for (auto &kv : ctx->batch_tables) hipFree(kv.second);
+    for (auto &kv : ctx->batch_tables) (void)hipFree(kv.second);
     ctx->batch_tables.clear();
 }
 
@@ -633,7 +633,7 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
         QDPX_TRY_HIP(hipMalloc(&dtab, sizeof(BatchLat) * n_lat), fn);
         hipError_t e = hipMemcpy(dtab, tab.data(), sizeof(BatchLat) * n_lat, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            hipFree(dtab);
+            (void)hipFree(dtab);
             return hip_fail(e, fn);
         }
         ctx->batch_tables[key] = dtab;
@@ -722,12 +722,14 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
         void *p = nullptr;
         if (hipMalloc(&p, n) != hipSuccess) return nullptr;
         bufs.push_back(p);
-        hipMemsetAsync(p, 0x3c, n, st);  // finite values in both precisions
+        // finite values in both precisions; a buffer that cannot be filled is
+        // reported as not allocated
+        if (hipMemsetAsync(p, 0x3c, n, st) != hipSuccess) return nullptr;
         return p;
     };
     auto release = [&]() {
-        hipStreamSynchronize(st);
-        for (void *p : bufs) hipFree(p);
+        (void)hipStreamSynchronize(st);
+        for (void *p : bufs) (void)hipFree(p);
     };
     void *U = alloc(lb), *A = nullptr, *B = nullptr, *C = nullptr, *part = nullptr;
     if (op == QDPX_OP_APE) {
@@ -757,31 +759,35 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
                 for (int n : ns_shift) cands.push_back(LaunchCfg{256, n, x, tw});
             }
         }
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        release();
+        return fail(QDPX_EHIP, "%s: could not create timing events", fn);
+    }
     const int nrows = nrows_of(fmt);
     auto run = [&](const LaunchCfg &c) -> hipError_t {
         if (op == QDPX_OP_APE) return launch_ape_step(g, prec, nrows, U, A, 0.5, 0.5 / 6.0, 0xFu, nullptr, 0, c, st);
         if (op == QDPX_OP_JACOBI) return launch_hop(g, prec, nrows, U, A, B, 0.1, 1.0, false, 0xFu, C, c, st);
         return launch_shift(g, prec, nrows, U, A, B, 0.3, op == QDPX_OP_CHAIN ? 1 : 0, 0.1, C, (double *)part, c, st);
     };
-    // milliseconds per launch over `reps` back-to-back launches
+    // milliseconds per launch over `reps` back-to-back launches (1e30 if
+    // anything failed, so a failing geometry is never chosen)
     auto time_cfg = [&](const LaunchCfg &c, int reps) -> float {
-        hipEventRecord(e0, st);
-        for (int r = 0; r < reps; ++r) run(c);
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
+        bool ok = hipEventRecord(e0, st) == hipSuccess;
+        for (int r = 0; r < reps; ++r) ok = run(c) == hipSuccess && ok;
+        ok = hipEventRecord(e1, st) == hipSuccess && ok;
+        ok = hipEventSynchronize(e1) == hipSuccess && ok;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        return ms / reps;
+        ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ok;
+        return ok ? ms / reps : 1e30f;
     };
     // Warm-up: about 30 launches of the default geometry, so that the first
     // candidates are not timed at idle clocks.  Round 1: every candidate once
     // (after one warm-up launch).  Round 2: the eight fastest again,
     // interleaved over seven passes, keeping each one's best pass, so that a
     // single slow or fast sample does not decide.
-    for (int r = 0; r < 30; ++r) run(LaunchCfg{});
+    for (int r = 0; r < 30; ++r) (void)run(LaunchCfg{});
     std::vector<std::pair<float, int>> r1;
     for (size_t i = 0; i < cands.size(); ++i) {
         if (run(cands[i]) != hipSuccess) continue;
@@ -799,9 +805,10 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
             best = best_ms[k];
             best_cfg = cands[r1[k].second];
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     release();
+    if (best >= 1e30f) return fail(QDPX_EHIP, "%s: no candidate geometry ran", fn);
     ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = best_cfg;
     return QDPX_OK;
 }

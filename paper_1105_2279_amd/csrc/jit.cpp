@@ -499,7 +499,7 @@ void jit_release(const qdpx_ctx *ctx) {
     auto it = g_kernels.find(ctx);
     if (it == g_kernels.end()) return;
     for (JitKernel &k : it->second)
-        if (k.module) hipModuleUnload(k.module);
+        if (k.module) (void)hipModuleUnload(k.module);
     g_kernels.erase(it);
 }
 }  // namespace qdpx
@@ -583,7 +583,7 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
     e = hipModuleGetFunction(&k.fn, k.module, "qdpx_jit_kernel");
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        hipModuleUnload(k.module);
+        (void)hipModuleUnload(k.module);
         return set_error(QDPX_EHIP, "qdpx_jit_compile: kernel not found in the code object");
     }
     std::lock_guard<std::mutex> lock(g_mutex);
