@@ -231,6 +231,11 @@ def main():
         head()
     ms_eager = time_calls(torch, head, args.steps, stream) / args.steps
     log(f"eager launches: {ms_eager:.3f} ms/step")
+    # spread of single steps: graph replays each bracketed by its own events
+    singles = sorted(time_calls(torch, graph.replay, 1, stream) for _ in range(max(20, args.steps)))
+    spread = {"replays": len(singles), "median_ms": singles[len(singles) // 2], "min_ms": singles[0],
+              "max_ms": singles[-1]}
+    log(f"single steps: median {spread['median_ms']:.3f} ms, min {spread['min_ms']:.3f} ms")
 
     # ---------------------------------------- per-kernel timing of each path
     kernel = {}
@@ -287,6 +292,7 @@ def main():
         "speedup_fp32_12_vs_fp64": results["f32_12"] / results["f64_18"],
         "f32_12_eager_ms_per_step": ms_eager,
         "f32_12_eager_link_updates_per_s": 4.0 * V * N_APE / (ms_eager / 1e3),
+        "f32_12_single_step_ms": spread,
         "ape_kernel_roofline": {k: roof(k) for k in paths},
         "tuned_launch": tuned,
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
