@@ -109,6 +109,9 @@ typedef struct qdpx_ctx qdpx_ctx;
 /* Create a context bound to HIP device `device`.  The context plays the role
  * of the paper's device storage container (section 5.2): it caches
  * tuned launch geometries and the per-lattice tables of batched calls.
+ * Every later call that takes the context and launches, tunes or compiles
+ * must be made while `device` is the current HIP device; otherwise it
+ * returns QDPX_EINVAL and does nothing.
  * Returns QDPX_EINVAL for a null `out` or a device that does not exist. */
 int qdpx_create(qdpx_ctx **out, int device);
 

@@ -50,6 +50,7 @@ extern "C" const char *qdpx_last_error(void) { return g_err.c_str(); }
 namespace qdpx {
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 void jit_release(const qdpx_ctx *ctx);
+int device_ok(const qdpx_ctx *ctx, const char *fn);
 }  // namespace qdpx
 extern "C" const char *qdpx_version(void) { return "qdpx 0.1 (gfx950)"; }
 
@@ -83,6 +84,18 @@ extern "C" int qdpx_create(qdpx_ctx **out, int device) {
     qdpx_ctx *c = new qdpx_ctx;
     c->device = device;
     *out = c;
+    return QDPX_OK;
+}
+
+// Kernels go to the caller's stream on the current device, and the
+// context's launch tables and cached device tables belong to its own device:
+// a call made while another device is current is refused.
+int qdpx::device_ok(const qdpx_ctx *ctx, const char *fn) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, fn);
+    if (cur != ctx->device)
+        return fail(QDPX_EINVAL, "%s: current device %d is not the context's device %d", fn, cur, ctx->device);
     return QDPX_OK;
 }
 
@@ -217,8 +230,11 @@ static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     return c;
 }
 
-#define QDPX_CHECK_CTX(fn) \
-    if (!ctx) return fail(QDPX_EINVAL, "%s: ctx is NULL", fn)
+#define QDPX_CHECK_CTX(fn)                                         \
+    do {                                                           \
+        if (!ctx) return fail(QDPX_EINVAL, "%s: ctx is NULL", fn); \
+        if (int r_ = qdpx::device_ok(ctx, fn)) return r_;          \
+    } while (0)
 
 // ------------------------------------------------------------ pack / unpack
 extern "C" int qdpx_pack_links(qdpx_ctx *ctx, const qdpx_geom *geom, const double *aos, qdpx_prec prec,

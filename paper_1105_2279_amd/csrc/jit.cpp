@@ -39,6 +39,7 @@
 
 namespace qdpx {
 int set_error(int code, const char *msg);  // api.cpp
+int device_ok(const qdpx_ctx *ctx, const char *fn);  // api.cpp
 bool geom_valid(const qdpx_geom *g, const char *fn);
 int workspace_reduce_bytes(const qdpx_geom *g);
 }  // namespace qdpx
@@ -522,6 +523,7 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
                                 int32_t n_scalars, int32_t *kernel) {
     const char *fn = "qdpx_jit_compile";
     if (!ctx || !kernel) return set_error(QDPX_EINVAL, "qdpx_jit_compile: ctx or kernel is NULL");
+    if (int r = device_ok(ctx, fn)) return r;
     JitKernel k;
     if (int r = parse_and_generate(expr, prec, fmt, n_fields, n_scalars, k.source, fn)) return r;
     k.prec = prec;
@@ -613,6 +615,7 @@ extern "C" int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geo
                              size_t work_bytes, void *stream) {
     const char *fn = "qdpx_jit_eval";
     if (!ctx) return set_error(QDPX_EINVAL, "qdpx_jit_eval: ctx is NULL");
+    if (int r = device_ok(ctx, fn)) return r;
     if (!geom_valid(geom, fn)) return QDPX_EINVAL;
     JitKernel k;
     {
