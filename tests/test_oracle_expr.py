@@ -62,3 +62,14 @@ def test_parse_errors():
         expr.evaluate("(umul m f0)", latgen.unit_links(L), [np.zeros(L[::-1] + (4, 3))])
     with pytest.raises(ValueError):
         expr.parse("(add f0 f1) f2")
+
+
+def test_uadj_undoes_umul_and_empty_sum_is_zero(data):
+    """For SU(3) links U^dag U = 1, so uadj inverts umul site by site in either
+    order; a sum over no direction is the zero field."""
+    U, psi, _ = data
+    for mu in range(4):
+        for e in (f"(uadj {mu} (umul {mu} f0))", f"(umul {mu} (uadj {mu} f0))"):
+            assert np.max(np.abs(expr.evaluate(e, U, [psi]) - psi)) < 1e-14, e
+    zero = expr.evaluate("(sum 0x0 (umul m f0))", U, [psi])
+    assert zero.shape == psi.shape and not np.any(zero)
