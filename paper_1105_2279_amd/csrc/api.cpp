@@ -799,8 +799,8 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
         return ok ? ms / reps : 1e30f;
     };
     // Warm-up: about 30 launches of the default geometry, so that the first
-    // candidates are not timed at idle clocks.  Round 1: every candidate once
-    // (after one warm-up launch).  Round 2: the eight fastest again,
+    // candidates are not timed at idle clocks.  First pass: every candidate
+    // once (after one warm-up launch).  Second pass: the eight fastest again,
     // interleaved over seven passes, keeping each one's best pass, so that a
     // single slow or fast sample does not decide.
     for (int r = 0; r < 30; ++r) (void)run(LaunchCfg{});
