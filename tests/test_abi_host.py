@@ -89,3 +89,12 @@ def test_python_binding_raises_on_status():
     with pytest.raises(q.QdpxError) as ei:
         q._check(-1, "qdpx_demo")
     assert "QDPX_EINVAL" in str(ei.value)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libqdpx.so the binding raises instead of falling back to
+    anything else."""
+    monkeypatch.setattr(q, "_lib", None)
+    monkeypatch.setattr(q, "LIB_PATH", str(tmp_path / "libqdpx.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        q.lib()
