@@ -4,7 +4,9 @@
 //    coordinates agree with the site index and with Site::init;
 //  * hop_fwd / hop_bwd give the periodic neighbour x +- mu;
 //  * traverse (t window) and slabwalk (XCD slab walk, where the launch takes
-//    it) are bijections on the group indices, and so is xcd_tile on blocks.
+//    it) are bijections on the group indices, and so is xcd_tile on blocks;
+//  * the link layouts map (mu, element, site) one to one onto the link
+//    buffer, and FP32 pairs share one 16-byte-aligned entry.
 // Over brick, linear and ragged lattices.  Prints "ok" and the number of
 // lattices checked.
 #include <hip/hip_runtime.h>
@@ -84,8 +86,30 @@ static void check_lattice(const int32_t L[4]) {
     }
 }
 
+template <typename R, int NR> static void check_layout(int64_t S) {
+    using Lay = LinkLayout<R, NR>;
+    const int64_t n = 4 * 3 * NR * S;
+    std::vector<char> seen(n, 0);
+    for (int mu = 0; mu < 4; ++mu)
+        for (int c = 0; c < 3 * NR; ++c)
+            for (int64_t s = 0; s < S; ++s) {
+                const int64_t k = Lay::slot(mu, c, S, s);
+                EXPECT(k >= 0 && k < n && !seen[k], "layout slot %lld reused or outside\n", (long long)k);
+                if (k >= 0 && k < n) seen[k] = 1;
+                if (Lay::kPaired && c < 8) {
+                    const int64_t e = Lay::slot(mu, c & ~1, S, s);
+                    EXPECT(e % 2 == 0 && Lay::slot(mu, c | 1, S, s) == e + 1, "FP32 pair not one 16-byte entry\n");
+                }
+            }
+}
+
 int main() {
     int n = 0;
+    for (int64_t S : {256, 512, 4096}) {
+        check_layout<double, 3>(S);
+        check_layout<float, 3>(S);
+        check_layout<float, 2>(S);
+    }
     const int xs[] = {2, 3, 4, 8, 16, 24, 32, 48}, ys[] = {2, 4, 5, 8, 12}, zs[] = {2, 3, 4, 8}, ts[] = {2, 4, 6, 8, 16};
     for (int lx : xs)
         for (int ly : ys)
