@@ -58,6 +58,7 @@ def lib():
         h.oracle_num_threads.restype = ctypes.c_int
         h.oracle_set_num_threads.argtypes = [ctypes.c_int]
         h.oracle_shift_mul_axpy.argtypes = [_I, _D, _D, _D, ctypes.c_double, _D, _D]
+        h.oracle_shift_expr.argtypes = [_I, _D, _D, _D, ctypes.c_double, ctypes.c_uint, ctypes.c_int, _D, _D]
         h.oracle_shift_chain.argtypes = [_I, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_int, _D]
         h.oracle_staple_sums.argtypes = [_I, _D, _D, _D]
         h.oracle_ape_w.argtypes = [_I, _D, ctypes.c_double, ctypes.c_uint, _D]
@@ -122,6 +123,22 @@ def shift_mul_axpy(U, psi, phi=None, a=0.0):
         phi = _c(phi)
         phi_p = _dp(phi)
     lib().oracle_shift_mul_axpy(_extents(U), _dp(U), _dp(psi), phi_p, float(a), _dp(chi), ctypes.byref(n2))
+    return chi, float(n2.value)
+
+
+def shift_expr(U, psi, phi=None, a=0.0, mask=0xF, sign=+1):
+    """chi = sum_{mu in mask} h_mu(x) + a*phi(x) with the forward hop
+    h_mu = U_mu(x) psi(x+mu) (sign > 0) or the backward hop
+    h_mu = U_mu(x-mu)^dag psi(x-mu) (sign < 0); returns (chi, |chi|^2)."""
+    U, psi = _c(U), _c(psi)
+    chi = np.empty_like(psi)
+    n2 = ctypes.c_double(0.0)
+    phi_p = None
+    if phi is not None:
+        phi = _c(phi)
+        phi_p = _dp(phi)
+    lib().oracle_shift_expr(_extents(U), _dp(U), _dp(psi), phi_p, float(a), ctypes.c_uint(mask), int(sign),
+                            _dp(chi), ctypes.byref(n2))
     return chi, float(n2.value)
 
 
@@ -239,7 +256,8 @@ def hop(U, psi, mask=0xF):
 
 
 def jacobi_smear(U, chi, kappa, n_iter, norm=1.0, mask=0xF):
-    """s0 = chi; n_iter times {psi = chi; chi = s0 + kappa H psi}; chi / norm."""
+    """(1/norm) sum_{n=0}^{n_iter} (kappa H)^n chi: the truncated series of
+    K^{-1} = (1 - kappa H)^{-1} applied to the source chi."""
     U = _c(U)
     chi = _c(chi).copy()
     lib().oracle_jacobi_smear(_extents(U), _dp(U), _dp(chi), float(kappa), int(n_iter), float(norm), int(mask))

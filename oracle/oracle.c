@@ -24,8 +24,11 @@
  *     hopping term of the smearing operator K in section 7.
  *   - chi = sum_mu U_mu(x) psi(x+mu) + a phi(x): the forward hop summed over
  *     mu plus the axpy of expression E_3 (section 7); a*phi is added once.
- *   - Jacobi smearing: the hop of K in both directions summed over the
- *     smeared directions, iterated as the paper's listing does (section 7).
+ *   - the backward hop U_mu(x-mu)^dagger X(x-mu), the other term of K, with a
+ *     mask of directions for either hop.
+ *   - Jacobi smearing: the truncated power series of K^{-1} = (1 - kappa H)^{-1}
+ *     applied to a source (section 7), H the hop in both directions summed over
+ *     the smeared directions.
  *   - The APE step (staple sum, combination with weight alpha, row
  *     Gram-Schmidt reunitarisation) and the plaquette are not in the paper;
  *     they follow the workload definition of one APE step on a periodic
@@ -190,37 +193,52 @@ void oracle_set_num_threads(int n)
 /* shift expression                                                    */
 /* ------------------------------------------------------------------ */
 
-/* chi at one site: sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x) (phi may be NULL).
- * U acts on colour and is the identity in spin. */
-static void shift_site(const lat *g, const double *U, const double *psi, const double *phi, double a, long s,
-                       cplx acc[4][3])
+/* chi at one site: sum_{mu in mask} h_mu(x) + a*phi(x) (phi may be NULL), with the
+ * hop h_mu(x) = U_mu(x) psi(x+mu) for sign > 0 (shift(psi, FORWARD, mu) times the
+ * link) and h_mu(x) = U_mu(x-mu)^dagger psi(x-mu) for sign < 0 (the backward term
+ * of the smearing operator K, section 7).  U acts on colour and is the identity
+ * in spin. */
+static void shift_site(const lat *g, const double *U, const double *psi, const double *phi, double a,
+                       unsigned mask, int sign, long s, cplx acc[4][3])
 {
     for (int sp = 0; sp < 4; ++sp)
         for (int c = 0; c < 3; ++c) acc[sp][c] = c_make(0.0, 0.0);
     for (int mu = 0; mu < 4; ++mu) {
-        mat3 u = load_link(U, s, mu);
-        long fwd = hop(g, s, mu, +1);
-        for (int sp = 0; sp < 4; ++sp)
-            for (int ca = 0; ca < 3; ++ca)
-                for (int cb = 0; cb < 3; ++cb)
-                    acc[sp][ca] = c_add(acc[sp][ca], c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
+        if (!((mask >> mu) & 1u)) continue;
+        if (sign > 0) {
+            mat3 u = load_link(U, s, mu);
+            long fwd = hop(g, s, mu, +1);
+            for (int sp = 0; sp < 4; ++sp)
+                for (int ca = 0; ca < 3; ++ca)
+                    for (int cb = 0; cb < 3; ++cb)
+                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(u.e[ca][cb], load_fermion(psi, fwd, sp, cb)));
+        } else {
+            long back = hop(g, s, mu, -1);
+            mat3 lb = load_link(U, back, mu);
+            /* (U^dagger)_{ab} = conj(U_{ba}) */
+            for (int sp = 0; sp < 4; ++sp)
+                for (int ca = 0; ca < 3; ++ca)
+                    for (int cb = 0; cb < 3; ++cb)
+                        acc[sp][ca] = c_add(acc[sp][ca], c_mul(c_conj(lb.e[cb][ca]), load_fermion(psi, back, sp, cb)));
+        }
     }
     if (phi)
         for (int sp = 0; sp < 4; ++sp)
             for (int c = 0; c < 3; ++c) acc[sp][c] = c_add(acc[sp][c], c_scale(a, load_fermion(phi, s, sp, c)));
 }
 
-/* chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x) for every site.  If
- * norm2 is not NULL it receives sum over sites, spins and colours of |chi|^2. */
-void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, const double *phi,
-                           double a, double *chi, double *norm2)
+/* chi(x) = sum_{mu in mask} h_mu(x) + a*phi(x) for every site, h_mu the forward
+ * (sign > 0) or backward (sign < 0) hop of shift_site.  If norm2 is not NULL it
+ * receives sum over sites, spins and colours of |chi|^2. */
+void oracle_shift_expr(const int *L, const double *U, const double *psi, const double *phi, double a,
+                       unsigned mask, int sign, double *chi, double *norm2)
 {
     lat g = lat_make(L);
     double *site_norm = norm2 ? (double *)malloc(sizeof(double) * (size_t)g.V) : NULL;
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < g.V; ++s) {
         cplx acc[4][3];
-        shift_site(&g, U, psi, phi, a, s, acc);
+        shift_site(&g, U, psi, phi, a, mask, sign, s, acc);
         double n2 = 0.0;
         for (int sp = 0; sp < 4; ++sp)
             for (int c = 0; c < 3; ++c) {
@@ -233,6 +251,13 @@ void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, con
         *norm2 = oracle_neumaier_sum(g.V, site_norm);
         free(site_norm);
     }
+}
+
+/* chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a*phi(x): all four forward hops. */
+void oracle_shift_mul_axpy(const int *L, const double *U, const double *psi, const double *phi,
+                           double a, double *chi, double *norm2)
+{
+    oracle_shift_expr(L, U, psi, phi, a, 0xFu, +1, chi, norm2);
 }
 
 /* n_iter repetitions of: chi_k = shift_mul_axpy(U, psi_{k-1}, phi, a);
@@ -261,7 +286,7 @@ void oracle_shift_sites(const int *L, const double *U, const double *psi, const 
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         cplx acc[4][3];
-        shift_site(&g, U, psi, phi, a, sites[i], acc);
+        shift_site(&g, U, psi, phi, a, 0xFu, +1, sites[i], acc);
         for (int sp = 0; sp < 4; ++sp)
             for (int c = 0; c < 3; ++c) store_fermion(chi, i, sp, c, acc[sp][c]);
     }
@@ -300,28 +325,34 @@ void oracle_hop(const int *L, const double *U, const double *psi, unsigned mask,
     }
 }
 
-/* Jacobi smearing as the listing of section 7 performs it:
- *   s0 = chi;  repeat n_iter times { psi = chi; chi = s0 + kappa * H psi };  chi /= norm.
- * chi is updated in place. */
+/* Jacobi smearing (section 7).  The smearing operator is K = 1 - kappa H, H
+ * the hopping term above, and the smeared source is the truncated power
+ * series of K^{-1} applied to the source s0, divided by a normalisation:
+ *   chi_N = (1/norm) sum_{n=0}^{N} (kappa H)^n s0.
+ * The terms are built one from the other, t_0 = s0 and t_{n+1} = kappa H t_n,
+ * and added in the order n = 0..N.  chi holds s0 on entry and chi_N on exit. */
 void oracle_jacobi_smear(const int *L, const double *U, double *chi, double kappa, int n_iter, double norm,
                          unsigned mask)
 {
     lat g = lat_make(L);
     size_t nf = (size_t)g.V * 4 * 3 * 2;
-    double *s0 = (double *)malloc(sizeof(double) * nf);
-    double *psi = (double *)malloc(sizeof(double) * nf);
+    double *term = (double *)malloc(sizeof(double) * nf);
+    double *sum = (double *)malloc(sizeof(double) * nf);
     double *h = (double *)malloc(sizeof(double) * nf);
-    memcpy(s0, chi, sizeof(double) * nf);
-    for (int n = 0; n < n_iter; ++n) {
-        memcpy(psi, chi, sizeof(double) * nf);
-        oracle_hop(L, U, psi, mask, h);
+    memcpy(term, chi, sizeof(double) * nf);
+    memcpy(sum, chi, sizeof(double) * nf);
+    for (int n = 1; n <= n_iter; ++n) {
+        oracle_hop(L, U, term, mask, h);
 #pragma omp parallel for schedule(static)
-        for (long i = 0; i < (long)nf; ++i) chi[i] = s0[i] + kappa * h[i];
+        for (long i = 0; i < (long)nf; ++i) {
+            term[i] = kappa * h[i];
+            sum[i] += term[i];
+        }
     }
 #pragma omp parallel for schedule(static)
-    for (long i = 0; i < (long)nf; ++i) chi[i] = chi[i] / norm;
-    free(s0);
-    free(psi);
+    for (long i = 0; i < (long)nf; ++i) chi[i] = sum[i] / norm;
+    free(term);
+    free(sum);
     free(h);
 }
 

@@ -1,6 +1,7 @@
 """Pins of the FP64 oracle's Jacobi smearing (the paper's application,
-section 7): the hopping term H of the smearing operator K and the iteration
-of the listing (s0 = chi; psi = chi; chi = s0 + kappa H psi; chi /= norm)."""
+section 7): the hopping term H of the smearing operator K = 1 - kappa H and
+the smeared source, the truncated power series of K^{-1} applied to the
+source, (1/norm) sum_{n=0}^{N} (kappa H)^n s0."""
 
 import numpy as np
 import pytest
@@ -57,8 +58,8 @@ def test_hop_gauge_covariant():
 @pytest.mark.parametrize("mask", [0xF, 0x7])
 def test_jacobi_unit_links_fourier_closed_form(mask):
     # unit links: H is diagonal in momentum space with eigenvalue
-    # h(p) = sum_{mu in mask} 2 cos(2 pi p_mu / L_mu); the listing then gives
-    # chi_N = (1/norm) sum_{k=0}^{N} (kappa h)^k s0.
+    # h(p) = sum_{mu in mask} 2 cos(2 pi p_mu / L_mu), so the truncated
+    # series is (1/norm) sum_{k=0}^{N} (kappa h)^k s0 mode by mode.
     L = (4, 3, 5, 6)
     s0 = latgen.dirac_field(L, 40)
     kappa, n, norm = 0.21, 5, 1.7
@@ -85,6 +86,27 @@ def test_jacobi_solves_k_up_to_truncation(n):
     for _ in range(n + 1):
         t = kappa * oracle.hop(U, t)
     assert max_abs(lhs - (s0 - t)) < 1e-13
+
+
+def test_hop_is_forward_plus_backward_shift():
+    # H = F + B, the forward and the backward hop of the shift expression
+    L = (3, 4, 2, 5)
+    U, psi, _ = fields(L, 70)
+    for mask in (0xF, 0x6):
+        f, _ = oracle.shift_expr(U, psi, None, 0.0, mask, +1)
+        b, _ = oracle.shift_expr(U, psi, None, 0.0, mask, -1)
+        assert max_abs(oracle.hop(U, psi, mask) - (f + b)) < 1e-14
+
+
+def test_jacobi_matches_recursion_of_the_listing():
+    # the listing's recursion chi <- s0 + kappa H chi, started from s0 and
+    # run N times, reaches the same series (up to rounding)
+    U, s0, _ = fields((3, 4, 2, 5), 80)
+    kappa, n, norm = 0.2, 6, 2.5
+    chi = s0.copy()
+    for _ in range(n):
+        chi = s0 + kappa * oracle.hop(U, chi)
+    assert max_abs(oracle.jacobi_smear(U, s0, kappa, n, norm) - chi / norm) < 1e-13
 
 
 def test_shift_sites_equals_full_evaluation():

@@ -2,7 +2,8 @@
 
 Each case copies ``oracle/oracle.c``, plants one mistake (a wrong shift, a
 missing dagger, a transposed product, a dropped staple, a wrong weight, a
-missing conjugate, a wrong sign or normalisation), compiles the copy with the
+missing conjugate, a wrong sign or normalisation, a mask ignored, an extra or
+unscaled series term), compiles the copy with the
 oracle's own flags, and runs the pin tests against it in a fresh process.
 The pins must fail for every mutant.  Nothing here touches the GPU.
 """
@@ -52,9 +53,14 @@ MUTANTS = {
     "hop_backward_no_dagger": ("c_mul(c_conj(ub.e[cb][ca]), load_fermion(psi, bwd, sp, cb))",
                                "c_mul(ub.e[ca][cb], load_fermion(psi, bwd, sp, cb))"),
     "hop_backward_wrong_link_site": ("mat3 ub = load_link(U, bwd, mu);", "mat3 ub = load_link(U, s, mu);"),
-    "jacobi_extra_iteration": ("for (int n = 0; n < n_iter; ++n) {\n        memcpy(psi",
-                               "for (int n = 0; n <= n_iter; ++n) {\n        memcpy(psi"),
-    "jacobi_norm_multiplied": ("chi[i] = chi[i] / norm;", "chi[i] = chi[i] * norm;"),
+    "jacobi_extra_term": ("for (int n = 1; n <= n_iter; ++n) {", "for (int n = 0; n <= n_iter; ++n) {"),
+    "jacobi_term_not_scaled": ("term[i] = kappa * h[i];", "term[i] = h[i];"),
+    "jacobi_norm_multiplied": ("chi[i] = sum[i] / norm;", "chi[i] = sum[i] * norm;"),
+    "shift_backward_no_dagger": ("c_mul(c_conj(lb.e[cb][ca]), load_fermion(psi, back, sp, cb))",
+                                 "c_mul(lb.e[ca][cb], load_fermion(psi, back, sp, cb))"),
+    "shift_backward_link_at_x": ("mat3 lb = load_link(U, back, mu);", "mat3 lb = load_link(U, s, mu);"),
+    "shift_mask_ignored": ("if (!((mask >> mu) & 1u)) continue;\n        if (sign > 0) {",
+                           "if (0) continue;\n        if (sign > 0) {"),
     "polar_inverse_not_sqrt": ("f[k] = 1.0 / sqrt(lam[k]);", "f[k] = 1.0 / lam[k];"),
     "polar_no_phase_fix": ("double ph = -atan2(d.im, d.re) / 3.0;", "double ph = 0.0 * atan2(d.im, d.re);"),
     "polar_wrong_side": ("mat3 H = m_mul(&Wd, W);", "mat3 H = m_mul(W, &Wd);"),

@@ -129,3 +129,78 @@ def test_chain_is_iterated_expression():
         assert norms[k] == n2
         p = p - 0.1 * chi
     assert np.array_equal(got, p)
+
+
+# ------------------------------------------------- direction mask and sign
+# chi = sum_{mu in mask} h_mu + a phi with the forward hop U_mu(x) psi(x+mu)
+# (sign +1) or the backward hop U_mu(x-mu)^dag psi(x-mu) (sign -1), the two
+# terms of the smearing operator K of section 7.
+
+@pytest.mark.parametrize("mask", [0xF, 0x7, 0x9, 0x2, 0x0])
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_masked_unit_links_is_array_shift(mask, sign):
+    # unit links: the hops are plain periodic array shifts (textbook roll)
+    L = (4, 3, 5, 2)
+    psi, phi = latgen.dirac_field(L, 21), latgen.dirac_field(L, 22)
+    chi, n2 = oracle.shift_expr(latgen.unit_links(L), psi, phi, A, mask, sign)
+    ref = A * phi
+    for mu in range(4):
+        if (mask >> mu) & 1:
+            ref = ref + np.roll(psi, -sign, axis=3 - mu)
+    assert max_abs(chi - ref) < 1e-15 * 8
+    assert n2 == pytest.approx(float(np.sum(np.abs(ref) ** 2)), rel=1e-14)
+
+
+@pytest.mark.parametrize("mask", [0xF, 0x5, 0x8])
+def test_backward_is_adjoint_of_forward(mask):
+    # <phi, F psi> = <B phi, psi>: the backward hop is the adjoint of the
+    # forward one, direction by direction (pins the dagger and the link site)
+    L = (3, 4, 2, 5)
+    U = latgen.haar_links(L, 23)
+    psi, phi = latgen.dirac_field(L, 24), latgen.dirac_field(L, 25)
+    f_psi, _ = oracle.shift_expr(U, psi, None, 0.0, mask, +1)
+    b_phi, _ = oracle.shift_expr(U, phi, None, 0.0, mask, -1)
+    lhs, rhs = np.vdot(phi, f_psi), np.vdot(b_phi, psi)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_backward_single_site_brute_force():
+    # psi nonzero at one site y: the backward hop is nonzero exactly at the
+    # four sites y + mu, where it equals U_mu(y)^dag psi(y)
+    L = (3, 4, 5, 6)
+    U = latgen.haar_links(L, 26)
+    psi = np.zeros((6, 5, 4, 3, 4, 3), dtype=np.complex128)
+    v = latgen.dirac_field((1, 1, 1, 1), 27)[0, 0, 0, 0]
+    y = (2, 3, 1, 2)  # (t, z, y, x)
+    psi[y] = v
+    chi, _ = oracle.shift_expr(U, psi, None, 0.0, 0xF, -1)
+    expect = np.zeros_like(psi)
+    for mu in range(4):
+        dst = list(y)
+        ax = 3 - mu
+        dst[ax] = (dst[ax] + 1) % psi.shape[ax]
+        expect[tuple(dst)] += np.einsum("ab,sb->sa", dag(U[y][mu]), v)
+    assert max_abs(chi - expect) < 1e-15 * 4
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_masked_gauge_covariance(sign):
+    L = (4, 3, 2, 5)
+    U = latgen.haar_links(L, 28)
+    psi, phi = latgen.dirac_field(L, 29), latgen.dirac_field(L, 30)
+    g = latgen.haar_gauge(L, 31)
+    chi, n2 = oracle.shift_expr(U, psi, phi, A, 0xB, sign)
+    chig, n2g = oracle.shift_expr(gauge_links(U, g), gauge_fermion(psi, g), gauge_fermion(phi, g), A, 0xB, sign)
+    assert max_abs(chig - gauge_fermion(chi, g)) < 1e-13
+    assert n2g == pytest.approx(n2, rel=1e-13)
+
+
+def test_masks_add_up():
+    # the hop over a mask is the sum of the hops over a split of the mask
+    L = (3, 4, 2, 5)
+    U = latgen.haar_links(L, 32)
+    psi = latgen.dirac_field(L, 33)
+    for sign in (+1, -1):
+        full, _ = oracle.shift_expr(U, psi, None, 0.0, 0xF, sign)
+        parts = sum(oracle.shift_expr(U, psi, None, 0.0, 1 << mu, sign)[0] for mu in range(4))
+        assert max_abs(full - parts) < 1e-14
