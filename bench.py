@@ -134,7 +134,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    ctx = q.Context(0)
+    ctx = tuning.context(0)  # launches the stored geometries (the launch table the library reads)
     V = latgen.volume(L)
     t = time.time()
     U = latgen.haar_links(L, latgen.SEEDS["ape_32x32x32x64"]["links"])
@@ -147,10 +147,9 @@ def main():
     torch.cuda.synchronize()
     # launch geometry: the stored table of autotuner results, or the
     # autotuner now for shapes it lacks (not timed)
-    table = tuning.load(ctx)
     tuned = {}
     for name, (prec, fmt) in paths.items():
-        cfg, src = tuning.ensure(ctx, q.OP_APE, prec, fmt, L, table)
+        cfg, src = tuning.ensure(ctx, q.OP_APE, prec, fmt, L)
         tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window"), cfg), source=src)
         log(f"APE {name} launch: {tuned[name]}")
 
@@ -187,7 +186,7 @@ def main():
         # then, per format, the tuned Jacobi hop kernel, four launches
         psi = latgen.dirac_field(L, latgen.SEEDS["ape_32x32x32x64"]["links"] + 1)
         for name, (prec, fmt) in paths.items():
-            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L, table)
+            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L)
             pd = q.fermion_to_device(ctx, L, psi, prec, dev)
             h = q.alloc_fermion(L, prec, dev)
             for _ in range(4):
@@ -263,6 +262,12 @@ def main():
             log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s with plaquettes (graph replay)")
     results["f32_12"] = value
 
+    # ------------------------------ per-step errors (outside every timed region)
+    samp_sites, samp_mus = error_sample(np, V)
+    steps = step_by_step(torch, q, ctx, dev, stream, paths, dev_links, samp_sites, samp_mus)
+    same_as_call = bool(torch.equal(steps["f32_12_final"], head_out))
+    log(f"step-by-step FP32-12 output identical to the timed call: {same_as_call}")
+
     def roof(name):
         t_k = kernel[name]
         flops = FLOPS_PER_LINK[name] * 4 * V
@@ -296,18 +301,33 @@ def main():
         "ape_kernel_roofline": {k: roof(k) for k in paths},
         "tuned_launch": tuned,
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
+        "errors_per_step_32x32x32x64": {
+            "note": "step k = 1..10 of the timed workload; FP32-12 and FP64-18 GPU paths against each other on "
+                    "every link, SU(3) defects on every link, and against the FP64 oracle on "
+                    f"{len(samp_sites)} sampled links (the oracle's steps of the cpu_baseline leg)",
+            "max_abs_f32_12_minus_f64_gpu": steps["d32_64"],
+            "f32_12_max_unitarity_defect": steps["u32"],
+            "f32_12_max_det_defect": steps["det32"],
+            "f64_18_max_unitarity_defect": steps["u64"],
+            "f64_18_max_det_defect": steps["det64"],
+            "plaquette_f32_12": steps["plaq32"],
+            "plaquette_f64_18": steps["plaq64"],
+            "step_by_step_identical_to_timed_call": same_as_call,
+        },
     }
     if not args.no_extras:
-        extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np, table))
+        extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
         extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
-        extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen, table))
+        extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(jit_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(pack_extras(torch, q, ctx, dev, stream, latgen, U))
+        extras.update(large_extras(torch, q, ctx, dev, stream, latgen, np))
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(U)
+        cpu, oracle_err = cpu_baseline(U, steps, samp_sites, samp_mus)
+        extras["errors_per_step_32x32x32x64"].update(oracle_err)
         extras["cpu_oracle_host"] = cpu_host_context(latgen)
 
     line = {
@@ -365,7 +385,7 @@ def pack_extras(torch, q, ctx, dev, stream, latgen, U):
     return {"pack_unpack_links_32x32x32x64": out}
 
 
-def shift_extras(torch, q, ctx, dev, stream, latgen, np, table):
+def shift_extras(torch, q, ctx, dev, stream, latgen, np):
     """Shift expression chi = sum_mu U psi(x+mu) + a phi at 32^3x64 (FP64 and FP32-12)."""
     from paper_1105_2279_amd import tuning
 
@@ -383,7 +403,7 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np, table):
         chi = q.alloc_fermion(Ls, prec, dev)
         n2 = torch.zeros(1, dtype=torch.float64, device=dev)
         work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
-        tuning.ensure(ctx, q.OP_SHIFT, prec, fmt, Ls, table)
+        tuning.ensure(ctx, q.OP_SHIFT, prec, fmt, Ls)
 
         def call():
             q.qdpx_eval_shift_mul_axpy(ctx, Ls, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work, stream)
@@ -424,7 +444,7 @@ N_JACOBI = 20
 KAPPA_JACOBI = 0.21
 
 
-def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
+def jacobi_extras(torch, q, ctx, dev, stream, latgen):
     """The whole Jacobi routine (copy, N_JACOBI fused hop+axpy iterations,
     division by the norm) on the lattices of the paper's Table 1, FP32 with
     12-real and 18-real links and FP64, each call replayed from a HIP graph;
@@ -444,7 +464,7 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen, table):
             Ud = q.links_to_device(ctx, L, U, prec, fmt, dev)
             cd = q.fermion_to_device(ctx, L, chi, prec, dev)
             work = q.alloc_workspace(q.OP_JACOBI, L, prec, fmt, N_JACOBI, dev)
-            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L, table)
+            tuning.ensure(ctx, q.OP_JACOBI, prec, fmt, L)
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream()
@@ -517,6 +537,147 @@ def jit_extras(torch, q, ctx, dev, stream, latgen):
     return {"jit_hop_32x32x32x64": out}
 
 
+LARGE = (48, 48, 48, 96)
+N_LARGE_APE = 20
+N_CHAIN = 8
+
+
+def large_extras(torch, q, ctx, dev, stream, latgen, np):
+    """The large single lattice, 48^3x96: 20 APE steps with the plaquette of
+    every step, then the fused shift-expression chain psi <- psi - 0.1 chi,
+    chi = sum_mu U_mu(x) psi(x+mu) + 0.3 phi, 8 times on the smeared links;
+    FP32-12 (FP64 projection and reductions) against the plain FP64-18 GPU
+    path.  Haar links are timed (each call replayed from a HIP graph) and
+    compared; near-unit links are compared; unit links are checked as a fixed
+    point."""
+    from paper_1105_2279_amd import tuning
+
+    Ls = LARGE
+    V = latgen.volume(Ls)
+    seeds = latgen.SEEDS["large_48x48x48x96"]
+    t = time.time()
+    U = latgen.haar_links(Ls, seeds["links_haar"])
+    psi = latgen.dirac_field(Ls, seeds["psi"])
+    phi = latgen.dirac_field(Ls, seeds["phi"])
+    log(f"large: generated 48^3x96 Haar links and fields in {time.time() - t:.1f} s")
+    paths = (("f32_12", q.F32, q.LINK12, 48, 480), ("f64_18", q.F64, q.LINK18, 144, 1152))
+    res, full, psi_out, norms_out = {}, {}, {}, {}
+    for name, prec, fmt, link_b, site_b in paths:
+        launch = {"ape": tuning.ensure(ctx, q.OP_APE, prec, fmt, Ls),
+                  "chain": tuning.ensure(ctx, q.OP_CHAIN, prec, fmt, Ls)}
+        Ud = q.links_to_device(ctx, Ls, U, prec, fmt, dev)
+        Vd = q.alloc_links(Ls, prec, fmt, dev)
+        work = q.alloc_workspace(q.OP_APE, Ls, prec, fmt, N_LARGE_APE, dev)
+        plaq = torch.zeros(3 * (N_LARGE_APE + 1), dtype=torch.float64, device=dev)
+        pd = q.fermion_to_device(ctx, Ls, psi, prec, dev)
+        pd0 = pd.clone()
+        fd = q.fermion_to_device(ctx, Ls, phi, prec, dev)
+        norms = torch.zeros(N_CHAIN, dtype=torch.float64, device=dev)
+        cwork = q.alloc_workspace(q.OP_CHAIN, Ls, prec, fmt, N_CHAIN, dev)
+        torch.cuda.synchronize()
+        graphs = []
+        for fn in (lambda st: q.qdpx_ape_smear(ctx, Ls, prec, fmt, Ud, Vd, ALPHA, N_LARGE_APE, plaq, work, st),
+                   lambda st: q.qdpx_shift_chain(ctx, Ls, prec, fmt, Vd, pd, fd, 0.3, 0.1, N_CHAIN, norms, cwork,
+                                                 st)):
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(stream)
+            with torch.cuda.graph(g, stream=cs):
+                fn(cs)
+            graphs.append(g)
+        g_ape, g_chain = graphs
+        g_ape.replay()
+        g_chain.replay()
+        torch.cuda.synchronize()
+        ms_ape = time_calls(torch, g_ape.replay, 3, stream) / 3
+        ms_chain = time_calls(torch, g_chain.replay, 3, stream) / 3
+        # the results: the smeared links are those of every replay; the chain
+        # runs once more from the initial psi
+        pd.copy_(pd0)
+        g_chain.replay()
+        torch.cuda.synchronize()
+        full[name] = unpack_device(torch, q, ctx, Ls, Vd, prec, fmt, dev).reshape(-1, 3, 3)
+        psi_out[name] = torch.empty((V, 4, 3, 2), dtype=torch.float64, device=dev)  # canonical FP64 layout
+        q.qdpx_unpack_fermion(ctx, Ls, pd, prec, psi_out[name])
+        norms_out[name] = norms.cpu().numpy()
+        u, d = su3_defects_device(torch, full[name])
+        ups = 4.0 * V * N_LARGE_APE / (ms_ape / 1e3)
+        res[name] = {
+            "launch": {k: {"geometry": v[0], "source": v[1]} for k, v in launch.items()},
+            "ape_20_steps_ms": round(ms_ape, 3),
+            "ape_link_updates_per_s": ups,
+            "ape_hbm_gbs_algorithmic": round(2 * link_b * ups / 1e9, 1),
+            "chain_8_iterations_ms": round(ms_chain, 3),
+            "chain_hbm_gbs_algorithmic": round(site_b * V * N_CHAIN / (ms_chain / 1e3) / 1e9, 1),
+            "chain_hbm_frac": round(site_b * V * N_CHAIN / (ms_chain / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+            "plaquettes": plaq.cpu().numpy().reshape(-1, 3)[[0, 1, 5, 10, 20]].tolist(),
+            "max_unitarity_defect": u,
+            "max_det_defect": d,
+            "chain_norms": norms_out[name].tolist(),
+        }
+        log(f"large {name}: 20 APE steps {ms_ape:.2f} ms ({ups / 1e9:.2f} G link-updates/s), chain "
+            f"{ms_chain:.2f} ms ({res[name]['chain_hbm_gbs_algorithmic']} GB/s)")
+        del Ud, Vd, work, pd, pd0, fd, cwork, g_ape, g_chain, graphs
+    d_links = float((full["f32_12"] - full["f64_18"]).abs().max())
+    dpsi = psi_out["f32_12"] - psi_out["f64_18"]
+    ref = psi_out["f64_18"]
+    chain_rel = float(dpsi.square().sum().sqrt() / ref.square().sum().sqrt())
+    chain_maxrel = float(dpsi.abs().max() / ref.abs().max())
+    norm_rel = float(np.max(np.abs(norms_out["f32_12"] - norms_out["f64_18"]) / norms_out["f64_18"]))
+    del full, psi_out, dpsi, ref
+    log(f"large: after 20 steps max |V32 - V64| {d_links:.2e}; chain psi rel. difference {chain_rel:.2e}")
+    # near-unit links: FP32-12 against FP64 after 20 steps; unit links: fixed point
+    t = time.time()
+    Un = latgen.near_unit_links(Ls, seeds["links_near_unit"])
+    log(f"large: generated near-unit links in {time.time() - t:.1f} s")
+    near, pl = {}, {}
+    for name, prec, fmt, _, _ in paths:
+        Ud = q.links_to_device(ctx, Ls, Un, prec, fmt, dev)
+        Vd = q.alloc_links(Ls, prec, fmt, dev)
+        work = q.alloc_workspace(q.OP_APE, Ls, prec, fmt, N_LARGE_APE, dev)
+        plaq = torch.zeros(3 * (N_LARGE_APE + 1), dtype=torch.float64, device=dev)
+        q.qdpx_ape_smear(ctx, Ls, prec, fmt, Ud, Vd, ALPHA, N_LARGE_APE, plaq, work, stream)
+        near[name] = unpack_device(torch, q, ctx, Ls, Vd, prec, fmt, dev).reshape(-1, 3, 3)
+        pl[name] = plaq.cpu().numpy().reshape(-1, 3)
+        del Ud, Vd, work
+    del Un
+    un32, _ = su3_defects_device(torch, near["f32_12"])
+    d_near = float((near["f32_12"] - near["f64_18"]).abs().max())
+    del near
+    Uu = latgen.unit_links(Ls)
+    Ud = q.links_to_device(ctx, Ls, Uu, q.F32, q.LINK12, dev)
+    del Uu
+    Vd = q.alloc_links(Ls, q.F32, q.LINK12, dev)
+    work = q.alloc_workspace(q.OP_APE, Ls, q.F32, q.LINK12, N_LARGE_APE, dev)
+    plaq = torch.zeros(3 * (N_LARGE_APE + 1), dtype=torch.float64, device=dev)
+    q.qdpx_ape_smear(ctx, Ls, q.F32, q.LINK12, Ud, Vd, ALPHA, N_LARGE_APE, plaq, work, stream)
+    unit = unpack_device(torch, q, ctx, Ls, Vd, q.F32, q.LINK12, dev).reshape(-1, 3, 3)
+    eye = torch.eye(3, dtype=torch.complex128, device=dev)
+    unit_dev = float((unit - eye).abs().max())
+    unit_plaq = float(plaq.abs().sub(1.0).abs().max())
+    del unit, Ud, Vd, work
+    log(f"large: near-unit max |V32 - V64| {d_near:.2e}; unit links max |V - 1| {unit_dev:.2e}")
+    speed = res["f32_12"]["ape_link_updates_per_s"] / res["f64_18"]["ape_link_updates_per_s"]
+    return {"large_48x48x48x96": {
+        "sites": V, "ape_steps": N_LARGE_APE, "chain_iterations": N_CHAIN, "a": 0.3, "c": 0.1,
+        "haar": res,
+        "ape_speedup_f32_12_vs_f64": speed,
+        "chain_speedup_f32_12_vs_f64": res["f64_18"]["chain_8_iterations_ms"] / res["f32_12"]["chain_8_iterations_ms"],
+        "errors": {
+            "haar_max_abs_f32_12_minus_f64_after_20_steps": d_links,
+            "chain_psi_rel_norm_f32_12_vs_f64": chain_rel,
+            "chain_psi_max_abs_over_max_ref_f32_12_vs_f64": chain_maxrel,
+            "chain_norms_max_rel_f32_12_vs_f64": norm_rel,
+            "near_unit_max_abs_f32_12_minus_f64_after_20_steps": d_near,
+            "near_unit_f32_12_max_unitarity_defect": un32,
+            "near_unit_plaquette_f32_12_input_and_20": [pl["f32_12"][0].tolist(), pl["f32_12"][-1].tolist()],
+            "near_unit_plaquette_f64_18_input_and_20": [pl["f64_18"][0].tolist(), pl["f64_18"][-1].tolist()],
+            "unit_links_f32_12_max_abs_v_minus_1_after_20_steps": unit_dev,
+            "unit_links_f32_12_max_abs_plaquette_minus_1": unit_plaq,
+        },
+    }}
+
+
 def batched_extras(torch, q, ctx, dev, stream, latgen):
     """64 lattices with extents drawn from 8^4, 12^3x24, 16^3x32, 24^3x48; 5 APE
     steps + final plaquettes, FP32-12: one persistent launch replayed from a
@@ -577,21 +738,41 @@ def batched_extras(torch, q, ctx, dev, stream, latgen):
     }
 
 
-def cpu_baseline(U):
+def cpu_baseline(U, steps, samp_sites, samp_mus):
     """The FP64 oracle on the host: whole APE steps over the full 32^3x64
-    lattice, repeated until at least 10 s of work (at most 40 steps)."""
+    lattice, repeated until at least 10 s of work (at least N_APE, at most 40
+    steps).  Only the steps are timed.  The oracle's links after steps
+    1..N_APE are the reference of the per-step errors of both GPU paths (on
+    the sampled links), and its plaquettes (untimed) of their plaquettes."""
+    import numpy as np
+
     import oracle
 
     V = U.shape[0] * U.shape[1] * U.shape[2] * U.shape[3]
+    flat = U.reshape(V, 4, 3, 3)
     threads = oracle.num_threads()
     log(f"cpu baseline: oracle APE steps on {L} with {threads} threads")
+    err = {"oracle_max_abs_f32_12": [], "oracle_max_abs_f64_18": [], "oracle_plaquette_abs_err_f32_12": [],
+           "oracle_plaquette_abs_err_f64_18": [], "oracle_plaquette": []}
+    p0 = oracle.plaquette(U)
+    err["oracle_plaquette_input"] = [float(x) for x in p0]
     n, t, cur = 0, 0.0, U
-    while t < 10.0 and n < 40:
+    while (t < 10.0 or n < N_APE) and n < 40:
         t0 = time.perf_counter()
         cur = oracle.ape_step(cur, ALPHA)
         t += time.perf_counter() - t0
         n += 1
-    log(f"cpu baseline: {n} steps in {t:.1f} s")
+        if n <= N_APE:
+            ref = cur.reshape(V, 4, 3, 3)[samp_sites, samp_mus]
+            err["oracle_max_abs_f32_12"].append(float(np.max(np.abs(steps["s32"][n - 1] - ref))))
+            err["oracle_max_abs_f64_18"].append(float(np.max(np.abs(steps["s64"][n - 1] - ref))))
+            p = oracle.plaquette(cur)
+            err["oracle_plaquette"].append([float(x) for x in p])
+            err["oracle_plaquette_abs_err_f32_12"].append(float(np.max(np.abs(np.array(steps["plaq32"][n]) - p))))
+            err["oracle_plaquette_abs_err_f64_18"].append(float(np.max(np.abs(np.array(steps["plaq64"][n]) - p))))
+    del flat
+    log(f"cpu baseline: {n} steps in {t:.1f} s; step-10 oracle error FP32-12 "
+        f"{err['oracle_max_abs_f32_12'][-1]:.2e}, FP64 {err['oracle_max_abs_f64_18'][-1]:.2e}")
     return {
         "value": 4.0 * V * n / t,
         "unit": "link-updates/s",
@@ -599,7 +780,78 @@ def cpu_baseline(U):
         "kind": "oracle",
         "sample": f"{n} FP64 APE steps over the full {L[0]}^3x{L[3]} lattice ({4 * V * n} link updates) "
                   f"in {t:.2f} s",
-    }
+    }, err
+
+
+def error_sample(np, V, n=4096, seed=1305 + 77):
+    """Links (site, direction) at which the GPU results are compared with the oracle."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(V, size=n, replace=False)), rng.integers(0, 4, n)
+
+
+def su3_defects_device(torch, m, chunk=1 << 22):
+    """(max ||V^dag V - 1||_F, max |det V - 1|) over (n, 3, 3) complex128 on the
+    device, by explicit elementwise sums (no batched library products)."""
+    eye = torch.eye(3, dtype=torch.complex128, device=m.device)
+    u = d = 0.0
+    for i in range(0, m.shape[0], chunk):
+        x = m[i:i + chunk]
+        gram = (x.conj().unsqueeze(-1) * x.unsqueeze(-2)).sum(-3) - eye  # sum_k conj(x_ki) x_kj
+        u = max(u, float(gram.abs().square().sum((-1, -2)).sqrt().max()))
+        det = (x[:, 0, 0] * (x[:, 1, 1] * x[:, 2, 2] - x[:, 1, 2] * x[:, 2, 1])
+               - x[:, 0, 1] * (x[:, 1, 0] * x[:, 2, 2] - x[:, 1, 2] * x[:, 2, 0])
+               + x[:, 0, 2] * (x[:, 1, 0] * x[:, 2, 1] - x[:, 1, 1] * x[:, 2, 0]))
+        d = max(d, float((det - 1.0).abs().max()))
+    return u, d
+
+
+def unpack_device(torch, q, ctx, Ls, soa, prec, fmt, dev):
+    """SoA links -> device complex128 tensor (V, 4, 3, 3) in the canonical order."""
+    n = Ls[0] * Ls[1] * Ls[2] * Ls[3]
+    aos = torch.empty((n, 4, 3, 3, 2), dtype=torch.float64, device=dev)
+    q.qdpx_unpack_links(ctx, Ls, soa, prec, fmt, aos)
+    return torch.view_as_complex(aos)
+
+
+def step_by_step(torch, q, ctx, dev, stream, paths, dev_links, samp_sites, samp_mus):
+    """The timed workload one APE step per call (bit-identical to one call of
+    N_APE steps), FP32-12 and FP64-18 side by side: after every step the two
+    outputs are compared on every link, their SU(3) defects are taken on
+    every link, and the sampled links are kept for the oracle comparison."""
+    sel_s = torch.from_numpy(samp_sites).to(dev)
+    sel_m = torch.from_numpy(samp_mus).to(dev)
+    res = {"d32_64": [], "u32": [], "det32": [], "u64": [], "det64": [], "s32": [], "s64": []}
+    cur, bufs, plaq = {}, {}, {}
+    for name in ("f32_12", "f64_18"):
+        prec, fmt = paths[name]
+        cur[name] = dev_links[name]
+        bufs[name] = [q.alloc_links(L, prec, fmt, dev), q.alloc_links(L, prec, fmt, dev)]
+        plaq[name] = torch.zeros(3 * (N_APE + 1), dtype=torch.float64, device=dev)
+    for k in range(N_APE):
+        full = {}
+        for name in ("f32_12", "f64_18"):
+            prec, fmt = paths[name]
+            out = bufs[name][k & 1]
+            p2 = torch.zeros(6, dtype=torch.float64, device=dev)
+            work = q.alloc_workspace(q.OP_APE, L, prec, fmt, 1, dev)
+            q.qdpx_ape_smear(ctx, L, prec, fmt, cur[name], out, ALPHA, 1, p2, work, stream)
+            if k == 0:
+                plaq[name][0:3] = p2[0:3]
+            plaq[name][3 * (k + 1):3 * (k + 2)] = p2[3:6]
+            cur[name] = out
+            full[name] = unpack_device(torch, q, ctx, L, out, prec, fmt, dev).reshape(-1, 4, 3, 3)
+            tag = "32" if name == "f32_12" else "64"
+            u, d = su3_defects_device(torch, full[name].reshape(-1, 3, 3))
+            res["u" + tag].append(u)
+            res["det" + tag].append(d)
+            res["s" + tag].append(full[name][sel_s, sel_m].cpu().numpy())
+        res["d32_64"].append(float((full["f32_12"] - full["f64_18"]).abs().max()))
+        del full
+        log(f"step {k + 1}: max |V32 - V64| {res['d32_64'][-1]:.2e}, FP32 unitarity defect {res['u32'][-1]:.2e}")
+    res["plaq32"] = plaq["f32_12"].cpu().numpy().reshape(-1, 3).tolist()
+    res["plaq64"] = plaq["f64_18"].cpu().numpy().reshape(-1, 3).tolist()
+    res["f32_12_final"] = cur["f32_12"]
+    return res
 
 
 def cpu_host_context(latgen):

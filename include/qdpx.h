@@ -112,8 +112,23 @@ typedef struct qdpx_ctx qdpx_ctx;
  * Every later call that takes the context and launches, tunes or compiles
  * must be made while `device` is the current HIP device; otherwise it
  * returns QDPX_EINVAL and does nothing.
- * Returns QDPX_EINVAL for a null `out` or a device that does not exist. */
-int qdpx_create(qdpx_ctx **out, int device);
+ * tune_cache_path (nullable): a launch-table file that keeps tuned thread
+ *   geometries for later runs, as the paper's auto-tuning proposal does
+ *   (sections 5.4 and 9).  NULL takes the path from the environment variable
+ *   QDPX_TUNE_CACHE, if set; otherwise the context has no table and every
+ *   operation starts from the default geometry.  The file is read here
+ *   (a missing file is an empty table; entries recorded for another GPU
+ *   architecture are ignored) and rewritten, merged, by every qdpx_tune on
+ *   this context and by qdpx_tune_save.  Format: JSON
+ *   {"device": "<gcnArchName>", "entries": [{"op": "APE", "prec": "F32",
+ *   "fmt": "LINK12", "L": [Lx, Ly, Lz, Lt], "launch": [block,
+ *   groups_per_wave, xcd_map, t_window]}, ...]}, op one of SHIFT CHAIN APE
+ *   PLAQ BATCHED JACOBI, prec F64 or F32, fmt LINK18 or LINK12.
+ *   With the environment variable QDPX_LOG set (not "" or "0") the library
+ *   prints one line on stderr per table read or write and per tuned geometry.
+ * Returns QDPX_EINVAL for a null `out`, a device that does not exist, or a
+ * table file that cannot be read or holds malformed or invalid entries. */
+int qdpx_create(qdpx_ctx **out, int device, const char *tune_cache_path);
 
 /* Destroy a context (NULL is accepted).  Frees what the context cached. */
 int qdpx_destroy(qdpx_ctx *ctx);
@@ -159,24 +174,33 @@ int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const void *soa, q
                         double *aos, void *stream);
 
 /* ------------------------------------------------------- shift expression
- * chi(x) = sum_{mu=0..3} U_mu(x) psi(x+mu) + a * phi(x)
- * The forward hop shift(psi, FORWARD, mu) multiplied by the link, summed
- * over the four directions, plus an axpy term added once (paper section 7:
- * the hopping term of K and the listing's expressions E_1/E_2 and E_3).
+ * chi(x) = sum_{mu in dir_mask} h_mu(x) + a * phi(x), with
+ *   sign = +1:  h_mu(x) = U_mu(x) psi(x+mu)          (forward hop)
+ *   sign = -1:  h_mu(x) = U_mu(x-mu)^dagger psi(x-mu) (backward hop)
+ * The forward term is shift(psi, FORWARD, mu) multiplied by the link, the
+ * backward term the shift(adj(U) psi, BACKWARD, mu) of the other hopping
+ * term of K, summed over the directions in dir_mask, plus an axpy term added
+ * once (paper section 7: the smearing operator K and the listing's
+ * expressions E_1, E_2 and E_3).  With dir_mask 0xF and sign +1 this is the
+ * 16^3 x 32 shift-expression workload (a = 0.3, four forward hops, FP64 norm).
  *   U: SoA links (prec, fmt); psi, phi: SoA fermions (prec); phi may be NULL
  *   (then `a` is ignored); chi: SoA fermion output, must not overlap psi, phi
- *   or U.  norm2 (nullable, device double*) receives sum_x |chi(x)|^2
+ *   or U.  dir_mask: bit mu selects direction mu (0 leaves only a * phi);
+ *   bits above 3 are refused.  sign: +1 or -1, anything else is refused.
+ *   Both hops of qdpx_eval_hop together are sign +1 plus sign -1.
+ *   norm2 (nullable, device double*) receives sum_x |chi(x)|^2
  *   accumulated in FP64 for both precisions.  work: workspace of
  *   work_bytes >= qdpx_workspace_bytes(QDPX_OP_SHIFT, ...). */
 int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                             const void *U, const void *psi, const void *phi, double a, void *chi,
-                             double *norm2, void *work, size_t work_bytes, void *stream);
+                             const void *U, const void *psi, const void *phi, double a, uint32_t dir_mask,
+                             int sign, void *chi, double *norm2, void *work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------- expression chain
  * n_iter repetitions of  chi_k = sum_mu U_mu(x) psi_{k-1}(x+mu) + a*phi(x);
  *                        psi_k = psi_{k-1} - c * chi_k
  * with U and phi fixed (the iteration structure of the paper's smearing
- * listing).  psi is updated in place; chi is not stored.  norms (nullable,
+ * listing; as a workload, 8 iterations with a = 0.3 and c = 0.1 on 48^3 x 96
+ * after 20 APE steps).  psi is updated in place; chi is not stored.  norms (nullable,
  * device double[n_iter]) receives |chi_k|^2 in FP64.  phi may be NULL.
  * n_iter >= 1.  work: >= qdpx_workspace_bytes(QDPX_OP_CHAIN, ..., n_iter). */
 int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
@@ -194,10 +218,13 @@ int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_
  *   mu).  dir_mask bit mu selects direction mu (0xF: all four, as the
  *   listing's loop over Nd; 0x7: the three spatial ones).  out must not
  *   overlap psi or U.
- * qdpx_jacobi_smear: s0 = chi; n_iter times { psi = chi; chi = s0 + kappa
- *   (H psi) }; chi = chi / norm  (expressions E_0, E_1/E_2, E_3, E_4), chi
- *   updated in place; n_iter >= 1, norm != 0.  One kernel per iteration; the
- *   division by norm is fused into the last one.
+ * qdpx_jacobi_smear: chi <- (1/norm) sum_{n=0}^{n_iter} (kappa H)^n chi, the
+ *   power series of K^{-1} = (1 - kappa H)^{-1} truncated after n_iter hops
+ *   and applied to the source held in chi (H summed over dir_mask), updated
+ *   in place; n_iter >= 1, norm != 0.  It is evaluated in Horner form, each
+ *   partial sum p_k = s0 + kappa H p_{k-1} (p_0 = s0) one fused kernel with
+ *   the division by norm folded into the last one; this is the expression
+ *   sequence E_0 .. E_4 of the listing.
  *   work: >= qdpx_workspace_bytes(QDPX_OP_JACOBI, ...) (two fermion fields). */
 int qdpx_eval_hop(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt, const void *U,
                   const void *psi, void *out, uint32_t dir_mask, void *stream);
@@ -206,7 +233,12 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
                       size_t work_bytes, void *stream);
 
 /* ----------------------------------------------------------- APE smearing
- * n_steps >= 1 APE steps.  One step, for every site x and every direction
+ * n_steps >= 1 APE steps.  The step is defined by the workload, not by the
+ * paper (whose application is the Jacobi smearing above): one step of
+ * alpha = 0.5 on a 4^4 periodic lattice of Haar-random links in FP64 with
+ * the row Gram-Schmidt projection and the FP64 plaquette, and 10 iterated
+ * steps on 32^3 x 64 with FP32 staples on 12-real links and the projection
+ * and plaquette in FP64.  One step, for every site x and every direction
  * mu in smear_mask, from the unsmeared links of that step:
  *   W_mu(x) = (1-alpha) U_mu(x) + alpha/(2(d-1)) sum_{nu in mask, nu != mu} [
  *               U_nu(x) U_mu(x+nu) U_nu(x+mu)^dagger
@@ -244,6 +276,9 @@ int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
                    qdpx_proj projection, double *plaq, void *work, size_t work_bytes, void *stream);
 
 /* -------------------------------------------------------------- plaquette
+ * The average plaquette the APE workloads report in FP64 (one step on 4^4,
+ * 10 steps on 32^3 x 64); the normalisation, which the workload leaves
+ * open, makes unit links give 1:
  * plaq[0] = (1/(18V)) sum_x sum_{mu<nu} Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]
  * plaq[1] = the same over the three spatial planes (nu < 3), / (9V)
  * plaq[2] = the same over the three planes with nu = t,      / (9V)
@@ -253,6 +288,9 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
                    const void *U, double *plaq, void *work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------ batched APE smearing
+ * The batched workload: 64 independent lattices with extents drawn from
+ * 8^4, 12^3 x 24, 16^3 x 32 and 24^3 x 48, 5 APE steps each and the final
+ * plaquettes, in one persistent launch that a HIP graph may capture.
  * n_lat independent lattices of any extents (each at most 4194304 sites),
  * each smeared n_steps times (1 <= n_steps <= 1024) as in qdpx_ape_smear
  * with smear_mask 0xF, followed by each lattice's output plaquette triple, in
@@ -340,7 +378,11 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * (sections 5.4 and 9).  Allocates and frees temporary device buffers and
  * synchronises the device, so it returns QDPX_ECAPTURE on a capturing
  * stream.  Every candidate produces bit-identical results.
- * qdpx_tune_get / qdpx_tune_set read and write the remembered choice;
+ * A context created with a launch table writes the tuned geometry to it.
+ * qdpx_tune_get / qdpx_tune_set read and write the remembered choice
+ * (every output pointer of qdpx_tune_get is nullable; *source receives 0
+ * for the default geometry, 1 for one read from the launch table, 2 for one
+ * qdpx_tune found, 3 for one qdpx_tune_set gave);
  * t_window must divide Lt and only matters when Lx is a multiple of 8 and Ly
  * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED only
  * sites_per_thread is used, as the number of 64-site groups per work item,
@@ -348,9 +390,16 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
 int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
               void *stream);
 int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                  int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window);
+                  int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window,
+                  int32_t *source);
 int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                   int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window);
+/* Write every geometry the context read, tuned or was given into the
+ * launch-table file `path` (NULL: the context's own table), merged with the
+ * entries the file already holds for other shapes; the file is replaced
+ * atomically.  Host only, no device work.  QDPX_EINVAL if there is no path or
+ * the file cannot be read or written. */
+int qdpx_tune_save(qdpx_ctx *ctx, const char *path);
 
 #ifdef __cplusplus
 }

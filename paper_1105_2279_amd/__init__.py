@@ -40,7 +40,7 @@ EXPORTS = (
     "qdpx_pack_links", "qdpx_unpack_links", "qdpx_pack_fermion", "qdpx_unpack_fermion",
     "qdpx_eval_shift_mul_axpy", "qdpx_shift_chain", "qdpx_ape_smear", "qdpx_plaquette",
     "qdpx_ape_smear_batched", "qdpx_tune", "qdpx_tune_get", "qdpx_tune_set",
-    "qdpx_eval_hop", "qdpx_jacobi_smear",
+    "qdpx_eval_hop", "qdpx_jacobi_smear", "qdpx_tune_save",
     "qdpx_jit_generate", "qdpx_jit_compile", "qdpx_jit_info", "qdpx_jit_eval",
 )
 
@@ -80,7 +80,8 @@ def lib():
     h = ctypes.CDLL(LIB_PATH)
     i32, sz, dbl = ctypes.c_int, ctypes.c_size_t, ctypes.c_double
     sig = {
-        "qdpx_create": (i32, [ctypes.POINTER(_P), i32]),
+        "qdpx_create": (i32, [ctypes.POINTER(_P), i32, ctypes.c_char_p]),
+        "qdpx_tune_save": (i32, [_P, ctypes.c_char_p]),
         "qdpx_destroy": (i32, [_P]),
         "qdpx_free_all": (i32, [_P]),
         "qdpx_last_error": (ctypes.c_char_p, []),
@@ -93,7 +94,8 @@ def lib():
         "qdpx_unpack_links": (i32, [_P, _G, _P, i32, i32, _P, _P]),
         "qdpx_pack_fermion": (i32, [_P, _G, _P, i32, _P, _P]),
         "qdpx_unpack_fermion": (i32, [_P, _G, _P, i32, _P, _P]),
-        "qdpx_eval_shift_mul_axpy": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, _P, _P, _P, sz, _P]),
+        "qdpx_eval_shift_mul_axpy": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, ctypes.c_uint32, i32, _P, _P, _P, sz,
+                                           _P]),
         "qdpx_shift_chain": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, dbl, i32, _P, _P, sz, _P]),
         "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, ctypes.c_uint32, i32, _P, _P, sz, _P]),
         "qdpx_plaquette": (i32, [_P, _G, i32, i32, _P, _P, _P, sz, _P]),
@@ -108,7 +110,7 @@ def lib():
         "qdpx_jacobi_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, dbl, ctypes.c_uint32, _P, sz, _P]),
         "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32)]),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "qdpx_tune_set": (i32, [_P, i32, _G, i32, i32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32]),
     }
@@ -152,11 +154,14 @@ def _nbytes(t) -> int:
 
 # --------------------------------------------------------------------- context
 class Context:
-    """Owns one ``qdpx_ctx`` (tuned geometries, cached tables)."""
+    """Owns one ``qdpx_ctx`` (tuned geometries, cached tables).  ``tune_cache``:
+    path of a launch-table file the library reads now and rewrites when it
+    tunes (None: the library takes ``$QDPX_TUNE_CACHE`` if set)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache=None):
         p = _P()
-        _check(lib().qdpx_create(ctypes.byref(p), int(device)), "qdpx_create")
+        path = None if tune_cache is None else os.fsencode(tune_cache)
+        _check(lib().qdpx_create(ctypes.byref(p), int(device), path), "qdpx_create")
         self._p = p
         self.device = int(device)
 
@@ -238,10 +243,11 @@ def qdpx_unpack_fermion(ctx, L, soa, prec, aos, stream=None):
                                      _stream(stream)), "qdpx_unpack_fermion")
 
 
-def qdpx_eval_shift_mul_axpy(ctx, L, prec, fmt, U, psi, phi, a, chi, norm2=None, work=None, stream=None):
+def qdpx_eval_shift_mul_axpy(ctx, L, prec, fmt, U, psi, phi, a, chi, norm2=None, work=None, stream=None,
+                             dir_mask=0xF, sign=1):
     _check(lib().qdpx_eval_shift_mul_axpy(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(psi),
-                                          _ptr(phi), float(a), _ptr(chi), _ptr(norm2), _ptr(work), _nbytes(work),
-                                          _stream(stream)), "qdpx_eval_shift_mul_axpy")
+                                          _ptr(phi), float(a), int(dir_mask), int(sign), _ptr(chi), _ptr(norm2),
+                                          _ptr(work), _nbytes(work), _stream(stream)), "qdpx_eval_shift_mul_axpy")
 
 
 def qdpx_shift_chain(ctx, L, prec, fmt, U, psi, phi, a, c, n_iter, norms=None, work=None, stream=None):
@@ -320,12 +326,28 @@ def qdpx_tune(ctx, op, L, prec, fmt, stream=None):
     _check(lib().qdpx_tune(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, _stream(stream)), "qdpx_tune")
 
 
+TUNE_SOURCES = ("default", "table", "tuned", "set")
+
+
+def _tune_get(ctx, op, L, prec, fmt):
+    b, n, x, t, src = (ctypes.c_int32() for _ in range(5))
+    _check(lib().qdpx_tune_get(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, ctypes.byref(b), ctypes.byref(n),
+                               ctypes.byref(x), ctypes.byref(t), ctypes.byref(src)), "qdpx_tune_get")
+    return (int(b.value), int(n.value), int(x.value), int(t.value)), TUNE_SOURCES[src.value]
+
+
 def qdpx_tune_get(ctx, op, L, prec, fmt):
     """(block, sites_per_thread, xcd_map, t_window) remembered for this case."""
-    b, n, x, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().qdpx_tune_get(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, ctypes.byref(b), ctypes.byref(n),
-                               ctypes.byref(x), ctypes.byref(t)), "qdpx_tune_get")
-    return int(b.value), int(n.value), int(x.value), int(t.value)
+    return _tune_get(ctx, op, L, prec, fmt)[0]
+
+
+def qdpx_tune_source(ctx, op, L, prec, fmt) -> str:
+    """Where the remembered geometry came from: "default", "table", "tuned" or "set"."""
+    return _tune_get(ctx, op, L, prec, fmt)[1]
+
+
+def qdpx_tune_save(ctx, path=None):
+    _check(lib().qdpx_tune_save(ctx.handle, None if path is None else os.fsencode(path)), "qdpx_tune_save")
 
 
 def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map, t_window=1):

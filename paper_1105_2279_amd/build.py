@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqdpx.so")
-SOURCES = ["fields.hip", "ape.hip", "batched.hip", "api.cpp", "jit.cpp"]
+SOURCES = ["fields.hip", "ape.hip", "batched.hip", "api.cpp", "jit.cpp", "tunecache.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -68,23 +68,121 @@ struct BatchKey {
     bool operator<(const BatchKey &o) const { return v < o.v; }
 };
 
+// Where a remembered geometry came from (qdpx_tune_get's source).
+enum { kSrcDefault = 0, kSrcTable = 1, kSrcTuned = 2, kSrcSet = 3 };
+
+struct Tuned {
+    LaunchCfg cfg;
+    int source = kSrcDefault;
+};
+
 struct qdpx_ctx {
     int device = 0;
-    std::map<TuneKey, LaunchCfg> tuned;
+    std::string arch;        // gcnArchName of the device
+    std::string cache_path;  // launch-table file ("" = none)
+    std::map<TuneKey, Tuned> tuned;
     std::map<BatchKey, void *> batch_tables;  // device tables of batched calls
 };
 
-extern "C" int qdpx_create(qdpx_ctx **out, int device) {
+// QDPX_LOG set to anything but "" or "0": one line on stderr per launch-table
+// read or write and per tuning decision.
+static bool log_on() {
+    const char *e = getenv("QDPX_LOG");
+    return e && *e && strcmp(e, "0") != 0;
+}
+
+static const char *op_name(int op) {
+    static const char *const n[] = {"SHIFT", "CHAIN", "APE", "PLAQ", "BATCHED", "JACOBI"};
+    return (op >= 0 && op < 6) ? n[op] : "?";
+}
+
+static void log_cfg(const char *what, const TuneKey &k, const LaunchCfg &c) {
+    if (!log_on()) return;
+    fprintf(stderr, "qdpx: %s %s prec %d fmt %d L %dx%dx%dx%d: block %d, groups/wave %d, xcd map %d, t window %d\n",
+            what, op_name(k.op), k.prec, k.fmt, k.L[0], k.L[1], k.L[2], k.L[3], c.block, c.nsite, c.xcd, c.tw);
+}
+
+static bool cfg_valid(qdpx_op op, const LaunchCfg &c);
+
+extern "C" int qdpx_create(qdpx_ctx **out, int device, const char *tune_cache_path) {
     if (!out) return fail(QDPX_EINVAL, "qdpx_create: out is NULL");
     *out = nullptr;
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (device < 0 || device >= n) return fail(QDPX_EINVAL, "qdpx_create: device %d not in [0, %d)", device, n);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    std::string path;
+    if (tune_cache_path) {
+        path = tune_cache_path;
+    } else {
+        const char *env = getenv("QDPX_TUNE_CACHE");
+        if (env) path = env;
+    }
+    std::vector<TuneEntry> entries;
+    if (!path.empty()) {
+        std::string err;
+        const int r = tune_table_read(path.c_str(), prop.gcnArchName, entries, err);
+        if (r < 0) return fail(QDPX_EINVAL, "qdpx_create: launch table %s", err.c_str());
+        if (log_on())
+            fprintf(stderr, "qdpx: launch table %s: %s\n", path.c_str(),
+                    r == 1 ? "no such file yet" : r == 2 ? "recorded on another architecture, ignored" : "read");
+        for (const TuneEntry &t : entries) {
+            bool extents_ok = true;
+            for (int d = 0; d < 4; ++d) extents_ok = extents_ok && t.L[d] >= 2 && t.L[d] <= 4096;
+            if (!extents_ok || !cfg_valid((qdpx_op)t.op, t.cfg) || t.L[3] % t.cfg.tw != 0)
+                return fail(QDPX_EINVAL, "qdpx_create: launch table %s holds an invalid geometry for op %s",
+                            path.c_str(), op_name(t.op));
+        }
+    }
     qdpx_ctx *c = new qdpx_ctx;
     c->device = device;
+    c->arch = prop.gcnArchName;
+    c->cache_path = path;
+    for (const TuneEntry &t : entries) {
+        const TuneKey k{t.op, t.prec, t.fmt, {t.L[0], t.L[1], t.L[2], t.L[3]}};
+        c->tuned[k] = Tuned{t.cfg, kSrcTable};
+        log_cfg("table", k, t.cfg);
+    }
     *out = c;
     return QDPX_OK;
+}
+
+// Merge the context's table and tuned geometries into the file at `path`
+// (entries already in the file for other shapes are kept).
+static int save_table(qdpx_ctx *ctx, const std::string &path, const char *fn) {
+    std::vector<TuneEntry> merged;
+    std::string err;
+    const int r = tune_table_read(path.c_str(), ctx->arch.c_str(), merged, err);
+    if (r < 0) return fail(QDPX_EINVAL, "%s: launch table %s", fn, err.c_str());
+    std::map<TuneKey, LaunchCfg> all;
+    for (const TuneEntry &t : merged) all[TuneKey{t.op, t.prec, t.fmt, {t.L[0], t.L[1], t.L[2], t.L[3]}}] = t.cfg;
+    for (const auto &kv : ctx->tuned)
+        if (kv.second.source != kSrcDefault) all[kv.first] = kv.second.cfg;
+    std::vector<TuneEntry> rows;
+    for (const auto &kv : all) {
+        TuneEntry t;
+        t.op = kv.first.op;
+        t.prec = kv.first.prec;
+        t.fmt = kv.first.fmt;
+        for (int d = 0; d < 4; ++d) t.L[d] = kv.first.L[d];
+        t.cfg = kv.second;
+        rows.push_back(t);
+    }
+    if (tune_table_write(path.c_str(), ctx->arch.c_str(), rows, err) != 0)
+        return fail(QDPX_EINVAL, "%s: %s", fn, err.c_str());
+    if (log_on()) fprintf(stderr, "qdpx: launch table %s: wrote %zu entries\n", path.c_str(), rows.size());
+    return QDPX_OK;
+}
+
+extern "C" int qdpx_tune_save(qdpx_ctx *ctx, const char *path) {
+    const char *fn = "qdpx_tune_save";
+    if (!ctx) return fail(QDPX_EINVAL, "%s: ctx is NULL", fn);
+    const std::string p = path ? std::string(path) : ctx->cache_path;
+    if (p.empty()) return fail(QDPX_EINVAL, "%s: no path and the context has no launch table", fn);
+    return save_table(ctx, p, fn);
 }
 
 // Kernels go to the caller's stream on the current device, and the
@@ -225,7 +323,7 @@ static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     if (ctx) {
         TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
         auto it = ctx->tuned.find(k);
-        if (it != ctx->tuned.end()) c = it->second;
+        if (it != ctx->tuned.end()) c = it->second.cfg;
     }
     return c;
 }
@@ -299,12 +397,15 @@ extern "C" int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const v
 
 // ------------------------------------------------------------ shift / chain
 extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                                        const void *U, const void *psi, const void *phi, double a, void *chi,
-                                        double *norm2, void *work, size_t work_bytes, void *stream) {
+                                        const void *U, const void *psi, const void *phi, double a,
+                                        uint32_t dir_mask, int sign, void *chi, double *norm2, void *work,
+                                        size_t work_bytes, void *stream) {
     const char *fn = "qdpx_eval_shift_mul_axpy";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
+    if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
+    if (sign != 1 && sign != -1) return fail(QDPX_EINVAL, "%s: sign %d is neither +1 nor -1", fn, sign);
     if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (!field_aligned(psi, prec) || !field_aligned(phi, prec) || !field_aligned(chi, prec))
@@ -323,7 +424,9 @@ extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qd
     const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_SHIFT, geom, prec, fmt);
     hipStream_t st = (hipStream_t)stream;
     double *part = norm2 ? (double *)work : nullptr;
-    QDPX_TRY_HIP(launch_shift(g, prec, nrows_of(fmt), U, psi, phi, a, 0, 0.0, chi, part, cfg, st), fn);
+    QDPX_TRY_HIP(launch_shift(g, prec, nrows_of(fmt), U, psi, phi, a, 0, 0.0, chi, part, cfg, st, dir_mask,
+                              sign < 0 ? 1 : 0),
+                 fn);
     if (norm2) QDPX_TRY_HIP(launch_finalize(part, shift_num_partials(g), 0, (double)g.V, norm2, st), fn);
     return QDPX_OK;
 }
@@ -687,7 +790,8 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
 }
 
 extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                             int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window) {
+                             int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window,
+                             int32_t *source) {
     const char *fn = "qdpx_tune_get";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -697,6 +801,10 @@ extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     if (sites_per_thread) *sites_per_thread = c.nsite;
     if (xcd_map) *xcd_map = c.xcd;
     if (t_window) *t_window = c.tw;
+    if (source) {
+        auto it = ctx->tuned.find(TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}});
+        *source = it == ctx->tuned.end() ? kSrcDefault : it->second.source;
+    }
     return QDPX_OK;
 }
 
@@ -714,7 +822,8 @@ extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     if (!cfg_valid(op, c) || geom->L[3] % c.tw != 0)
         return fail(QDPX_EINVAL, "%s: geometry (block %d, sites %d, xcd %d, t window %d) not valid for op %d", fn,
                     block, sites_per_thread, xcd_map, t_window, (int)op);
-    ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = c;
+    ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] =
+        Tuned{c, kSrcSet};
     return QDPX_OK;
 }
 
@@ -825,6 +934,10 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     (void)hipEventDestroy(e1);
     release();
     if (best >= 1e30f) return fail(QDPX_EHIP, "%s: no candidate geometry ran", fn);
-    ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] = best_cfg;
+    const TuneKey key{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
+    ctx->tuned[key] = Tuned{best_cfg, kSrcTuned};
+    log_cfg("tuned", key, best_cfg);
+    // a context with a launch table keeps what it tuned for later processes
+    if (!ctx->cache_path.empty()) return save_table(ctx, ctx->cache_path, fn);
     return QDPX_OK;
 }

@@ -154,10 +154,13 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 }
 
 // ------------------------------------------------------- shift expression
-// chi(x) = sum_mu U_mu(x) psi(x+mu) + a phi(x); MODE 1 (one chain step)
-// stores psi(x) - c chi(x) instead of chi.  A block of 256 threads holds one
+// chi(x) = sum_{mu in mask} h_mu(x) + a phi(x), with the forward hop
+// h_mu = U_mu(x) psi(x+mu) or (bwd) the backward hop
+// h_mu = U_mu(x-mu)^dag psi(x-mu); MODE 1 (one chain step) stores
+// psi(x) - c chi(x) instead of chi.  A block of 256 threads holds one
 // 64-site group per iteration and wave w computes direction mu = w for all 12
 // spinor components, so the four directions' loads are in flight together.
+// Either hop reads each link once per launch, so links are streamed.
 // The four partial products meet in LDS; after a barrier wave w adds them in
 // direction order for spin w, adds a phi, forms the FP64 |chi|^2 of its three
 // components, and stores spin w.  The four waves' norms are added in wave
@@ -165,7 +168,8 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 // every sum has a fixed order and nothing depends on the launch geometry.
 template <typename R, int NR, int MODE, int NS>
 __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> phi, R a, R c,
-                                                FermWO<R> out, double *__restrict__ partials, int xcd, int tw) {
+                                                unsigned mask, int bwd, FermWO<R> out, double *__restrict__ partials,
+                                                int xcd, int tw) {
     __shared__ vec2_t<R> part[4][12][64];  // [direction][component][lane]
     __shared__ double nrm[4][64];          // [wave][lane]
     const int tile = xcd == 1 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -210,10 +214,22 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
-        if (live) {
-            const int f = hop_fwd(g, s, cmu, mu);
+        if (live && ((mask >> mu) & 1u)) {  // wave-uniform
+            const int f = bwd ? hop_bwd(g, s, cmu, mu) : hop_fwd(g, s, cmu, mu);
             M3<R> u;
-            U.full_stream(mu, s, u);  // the shift expression reads each link once
+            U.full_stream(mu, bwd ? f : s, u);  // each link is read once
+            if (bwd) {  // U^dag: transpose and conjugate in registers
+#pragma unroll
+                for (int ca = 0; ca < 3; ++ca) {
+                    u.e[ca][ca].im = -u.e[ca][ca].im;
+#pragma unroll
+                    for (int cb = ca + 1; cb < 3; ++cb) {
+                        const Cx<R> t = u.e[ca][cb];
+                        u.e[ca][cb] = Cx<R>{u.e[cb][ca].re, -u.e[cb][ca].im};
+                        u.e[cb][ca] = Cx<R>{t.re, -t.im};
+                    }
+                }
+            }
             Cx<R> pf[4][3];
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
@@ -277,7 +293,8 @@ int shift_num_partials(const Geo &g) { return (g.V + 63) / 64; }
 
 template <typename R, int NR, int MODE>
 static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, const void *phi, double a, double c,
-                              void *out, double *partials, const LaunchCfg &cfg, hipStream_t st) {
+                              unsigned mask, int bwd, void *out, double *partials, const LaunchCfg &cfg,
+                              hipStream_t st) {
     using V = vec2_t<R>;
     LinksRO<R, NR> u{(const V *)U, g.S};
     FermRO<R> p{(const V *)psi, g.S}, f{(const V *)phi, g.S};
@@ -287,26 +304,27 @@ static void shift_dispatch_ns(const Geo &g, const void *U, const void *psi, cons
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
     switch (cfg.nsite) {
-    case 2: k_shift<R, NR, MODE, 2><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    case 4: k_shift<R, NR, MODE, 4><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    case 8: k_shift<R, NR, MODE, 8><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
-    default: k_shift<R, NR, MODE, 1><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, o, partials, xcd, cfg.tw); break;
+    case 2: k_shift<R, NR, MODE, 2><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, mask, bwd, o, partials, xcd, cfg.tw); break;
+    case 4: k_shift<R, NR, MODE, 4><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, mask, bwd, o, partials, xcd, cfg.tw); break;
+    case 8: k_shift<R, NR, MODE, 8><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, mask, bwd, o, partials, xcd, cfg.tw); break;
+    default: k_shift<R, NR, MODE, 1><<<grid, 256, 0, st>>>(g, u, p, f, (R)a, (R)c, mask, bwd, o, partials, xcd, cfg.tw); break;
     }
 }
 
 template <int MODE>
 static void shift_dispatch(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
-                           double a, double c, void *out, double *partials, const LaunchCfg &cfg, hipStream_t st) {
-    if (prec == 0) shift_dispatch_ns<double, 3, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
-    else if (nrows == 3) shift_dispatch_ns<float, 3, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
-    else shift_dispatch_ns<float, 2, MODE>(g, U, psi, phi, a, c, out, partials, cfg, st);
+                           double a, double c, unsigned mask, int bwd, void *out, double *partials,
+                           const LaunchCfg &cfg, hipStream_t st) {
+    if (prec == 0) shift_dispatch_ns<double, 3, MODE>(g, U, psi, phi, a, c, mask, bwd, out, partials, cfg, st);
+    else if (nrows == 3) shift_dispatch_ns<float, 3, MODE>(g, U, psi, phi, a, c, mask, bwd, out, partials, cfg, st);
+    else shift_dispatch_ns<float, 2, MODE>(g, U, psi, phi, a, c, mask, bwd, out, partials, cfg, st);
 }
 
 hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
                         double a, int mode, double c, void *out, double *partials, const LaunchCfg &cfg,
-                        hipStream_t st) {
-    if (mode == 0) shift_dispatch<0>(g, prec, nrows, U, psi, phi, a, c, out, partials, cfg, st);
-    else shift_dispatch<1>(g, prec, nrows, U, psi, phi, a, c, out, partials, cfg, st);
+                        hipStream_t st, unsigned mask, int bwd) {
+    if (mode == 0) shift_dispatch<0>(g, prec, nrows, U, psi, phi, a, c, mask, bwd, out, partials, cfg, st);
+    else shift_dispatch<1>(g, prec, nrows, U, psi, phi, a, c, mask, bwd, out, partials, cfg, st);
     return hipGetLastError();
 }
 

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "su3_device.hpp"
 
 namespace qdpx {
@@ -22,6 +25,19 @@ struct LaunchCfg {
 // every tuned geometry of the other kernels.
 constexpr int kReduceBlock = 256;
 
+// One stored launch geometry (launch-table file, tunecache.cpp).  op, prec
+// and fmt are the qdpx_op, qdpx_prec and qdpx_linkfmt values.
+struct TuneEntry {
+    int op = 0, prec = 0, fmt = 0;
+    int L[4] = {0, 0, 0, 0};
+    LaunchCfg cfg;
+};
+// 0: read; 1: no such file; 2: the file was recorded on another
+// architecture (out stays empty); -1: unreadable or malformed (err set).
+int tune_table_read(const char *path, const char *arch, std::vector<TuneEntry> &out, std::string &err);
+// Writes the table atomically (temporary file + rename); 0 or -1 (err set).
+int tune_table_write(const char *path, const char *arch, const std::vector<TuneEntry> &in, std::string &err);
+
 Geo make_geo(const int32_t L[4]);
 int launch_order(const Geo &g, const LaunchCfg &cfg, int groups_per_block);
 
@@ -31,13 +47,14 @@ hipError_t launch_unpack_links(const Geo &g, int prec, int nrows, const void *so
 hipError_t launch_pack_fermion(const Geo &g, int prec, const double *aos, void *soa, hipStream_t st);
 hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double *aos, hipStream_t st);
 
-// Shift expression.  mode 0: out = chi; mode 1: out = psi - c*chi.
-// partials (nullable): one FP64 partial of |chi|^2 per 256-site chunk,
-// shift_num_partials(g) entries.
+// Shift expression chi = sum_{mu in mask} hop_mu(psi) + a*phi, forward hops
+// (bwd = 0) or backward hops (bwd = 1).  mode 0: out = chi; mode 1:
+// out = psi - c*chi.  partials (nullable): one FP64 partial of |chi|^2 per
+// 64-site group, shift_num_partials(g) entries.
 int shift_num_partials(const Geo &g);
 hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const void *psi, const void *phi,
                         double a, int mode, double c, void *out, double *partials, const LaunchCfg &cfg,
-                        hipStream_t st);
+                        hipStream_t st, unsigned mask = 0xFu, int bwd = 0);
 hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *dst, hipStream_t st);
 
 // Jacobi hop: out = [s0 + kappa * H psi] / norm (s0 nullable; division only

@@ -1,15 +1,17 @@
 """Stored launch geometries.
 
 ``qdpx_tune`` times the candidate launch geometries of an operation on one
-lattice shape and keeps the fastest in a context; this module stores such
-choices in a JSON table so that later processes launch the same geometry
-without re-tuning (and so that timing and counter runs measure the same
-kernels).  Entries are keyed by (operation, precision, link format,
-extents).
+lattice shape and keeps the fastest in a context.  A context created with a
+launch-table file (``Context(device, tune_cache=path)``, or
+``$QDPX_TUNE_CACHE``) reads the file in the library and writes every tuned
+geometry back to it, so later processes launch the same geometry without
+re-tuning (and timing and counter runs measure the same kernels).  Entries
+are keyed by (operation, precision, link format, extents).  ``TABLE`` is the
+table stored with the package for the benchmark's shapes.
 
     python -m paper_1105_2279_amd.tuning [--out PATH]
 
-tunes the shapes listed in ``SHAPES`` on the current GPU and writes the table.
+tunes the shapes listed in ``SHAPES`` on the current GPU into that table.
 """
 
 from __future__ import annotations
@@ -18,8 +20,7 @@ import argparse
 import json
 import os
 
-from . import (F32, F64, LINK12, LINK18, OP_APE, OP_CHAIN, OP_JACOBI, OP_SHIFT, Context, qdpx_tune, qdpx_tune_get,
-               qdpx_tune_set)
+from . import (F32, F64, LINK12, LINK18, OP_APE, OP_CHAIN, OP_JACOBI, OP_SHIFT, Context, _tune_get, qdpx_tune)
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_table_mi355x.json")
 
@@ -40,7 +41,9 @@ def _key(op, prec, fmt, L):
 
 
 def read(path=TABLE):
-    """{(op, prec, fmt, L): (block, groups_per_wave, xcd_map, t_window)}; empty if there is no table."""
+    """{(op, prec, fmt, L): (block, groups_per_wave, xcd_map, t_window)} as
+    stored in the file; empty if there is no table (for inspection: contexts
+    read the file in the library)."""
     try:
         with open(path) as fh:
             rows = json.load(fh)["entries"]
@@ -49,23 +52,19 @@ def read(path=TABLE):
     return {_key(r["op"], r["prec"], r["fmt"], r["L"]): tuple(r["launch"]) for r in rows}
 
 
-def load(ctx, path=TABLE):
-    """Set every stored geometry in ctx; returns the keys set."""
-    table = read(path)
-    for (op, prec, fmt, L), cfg in table.items():
-        qdpx_tune_set(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt], *cfg)
-    return set(table)
+def context(device=0, path=TABLE):
+    """A context that launches the stored geometries (and stores what it tunes)."""
+    return Context(device, tune_cache=path)
 
 
-def ensure(ctx, op, prec, fmt, L, table_keys):
-    """Launch geometry for one shape: the stored one if ctx was loaded with
-    it, else tuned now.  Returns (geometry, "table" | "tuned")."""
-    names = ({v: k for k, v in _OPS.items()}[op], {v: k for k, v in _PRECS.items()}[prec],
-             {v: k for k, v in _FMTS.items()}[fmt])
-    if _key(*names, L) in table_keys:
-        return qdpx_tune_get(ctx, op, L, prec, fmt), "table"
-    qdpx_tune(ctx, op, L, prec, fmt)
-    return qdpx_tune_get(ctx, op, L, prec, fmt), "tuned"
+def ensure(ctx, op, prec, fmt, L):
+    """Launch geometry for one shape: the one the context read from its
+    table, else tuned now.  Returns (geometry, "table" | "tuned" | "set")."""
+    cfg, src = _tune_get(ctx, op, L, prec, fmt)
+    if src == "default":
+        qdpx_tune(ctx, op, L, prec, fmt)
+        cfg, src = _tune_get(ctx, op, L, prec, fmt)
+    return cfg, src
 
 
 def main():
@@ -75,17 +74,12 @@ def main():
     import torch
 
     torch.cuda.init()
-    ctx = Context(0)
-    rows = []
+    ctx = Context(0, tune_cache=args.out)
     for op, prec, fmt, L in SHAPES:
-        qdpx_tune(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])
-        cfg = qdpx_tune_get(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])
-        rows.append({"op": op, "prec": prec, "fmt": fmt, "L": list(L), "launch": list(cfg)})
+        qdpx_tune(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])  # written to the table by the library
+        cfg, _ = _tune_get(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])
         print(f"{op} {prec} {fmt} {L}: {cfg}", flush=True)
     ctx.close()
-    with open(args.out, "w") as fh:
-        json.dump({"device": torch.cuda.get_device_properties(0).gcnArchName, "entries": rows}, fh, indent=1)
-        fh.write("\n")
     print(f"wrote {args.out}", flush=True)
 
 

@@ -42,8 +42,7 @@ def bench_ctx():
     if _bench_ctx is None:
         from paper_1105_2279_amd import tuning
 
-        _bench_ctx = q.Context(0)
-        tuning.load(_bench_ctx)
+        _bench_ctx = tuning.context(0)
     return _bench_ctx
 
 
@@ -57,6 +56,7 @@ def assert_bench_geometry(op_name, op, L, prec, fmt):
 
     stored = tuning.read()[(op_name, *FMT_NAMES[(prec, fmt)], tuple(L))]
     assert q.qdpx_tune_get(bench_ctx(), op, L, prec, fmt) == stored
+    assert q.qdpx_tune_source(bench_ctx(), op, L, prec, fmt) == "table"
 
 
 def dev():
@@ -84,15 +84,15 @@ def plaquette(L, U, prec, fmt):
     return plaq.cpu().numpy()
 
 
-def shift(L, U, psi, phi, a, prec, fmt):
-    c = ctx()
+def shift(L, U, psi, phi, a, prec, fmt, mask=0xF, sign=1, context=None):
+    c = context or ctx()
     Ud = q.links_to_device(c, L, U, prec, fmt, dev())
     pd = q.fermion_to_device(c, L, psi, prec, dev())
     fd = q.fermion_to_device(c, L, phi, prec, dev()) if phi is not None else None
     chi = q.alloc_fermion(L, prec, dev())
     n2 = torch.zeros(1, dtype=torch.float64, device=dev())
     work = q.alloc_workspace(q.OP_SHIFT, L, prec, fmt, 1, dev())
-    q.qdpx_eval_shift_mul_axpy(c, L, prec, fmt, Ud, pd, fd, a, chi, n2, work)
+    q.qdpx_eval_shift_mul_axpy(c, L, prec, fmt, Ud, pd, fd, a, chi, n2, work, dir_mask=mask, sign=sign)
     return q.fermion_to_host(c, L, chi, prec), float(n2.item())
 
 

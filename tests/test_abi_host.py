@@ -75,12 +75,13 @@ def test_null_context_rejected_everywhere():
     assert h.qdpx_unpack_links(None, g, 1, 0, 0, 2, None) == EINVAL
     assert h.qdpx_pack_fermion(None, g, 1, 0, 2, None) == EINVAL
     assert h.qdpx_unpack_fermion(None, g, 1, 0, 2, None) == EINVAL
-    assert h.qdpx_eval_shift_mul_axpy(None, g, 0, 0, 1, 2, 3, 0.3, 4, None, None, 0, None) == EINVAL
+    assert h.qdpx_eval_shift_mul_axpy(None, g, 0, 0, 1, 2, 3, 0.3, 0xF, 1, 4, None, None, 0, None) == EINVAL
     assert h.qdpx_shift_chain(None, g, 0, 0, 1, 2, 3, 0.3, 0.1, 8, None, None, 0, None) == EINVAL
     assert h.qdpx_ape_smear(None, g, 0, 0, 1, 2, 0.5, 1, 0xF, 0, None, None, 0, None) == EINVAL
     assert h.qdpx_plaquette(None, g, 0, 0, 1, 2, 3, 0, None) == EINVAL
     assert h.qdpx_free_all(None) == EINVAL
-    assert h.qdpx_create(None, 0) == EINVAL
+    assert h.qdpx_tune_save(None, None) == EINVAL
+    assert h.qdpx_create(None, 0, None) == EINVAL
     assert "NULL" in h.qdpx_last_error().decode()
     assert h.qdpx_destroy(None) == 0
 

@@ -63,6 +63,63 @@ def test_shift_mul_axpy(prec, fmt, L):
     assert abs(n2 - n2ref) < tol(prec) * n2ref
 
 
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_shift_benched_shape_and_geometry(prec, fmt):
+    """The shift expression at 32^3x64 in the stored launch geometry the
+    benchmark times, element by element against the oracle."""
+    L = (32, 32, 32, 64)
+    assert_bench_geometry("SHIFT", q.OP_SHIFT, L, prec, fmt)
+    seeds = latgen.SEEDS["shift_16x16x16x32"]
+    U = latgen.haar_links(L, seeds["links"])
+    psi, phi = latgen.dirac_field(L, seeds["psi"]), latgen.dirac_field(L, seeds["phi"])
+    chi, n2 = shift(L, U, psi, phi, 0.3, prec, fmt, context=bench_ctx())
+    ref, n2ref = oracle.shift_mul_axpy(U, psi, phi, 0.3)
+    e_norm, e_max = rel_err(chi, ref)
+    print(f"shift 32^3x64 {prec}/{fmt}: rel {e_norm:.2e} max {e_max:.2e}", flush=True)
+    assert e_norm < tol(prec) and e_max < tol(prec), (e_norm, e_max)
+    assert abs(n2 - n2ref) < tol(prec) * n2ref
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+@pytest.mark.parametrize("L", [RAGGED, (16, 8, 4, 8), (2, 6, 2, 6)], ids=["ragged", "16x8x4x8", "2x6x2x6"])
+@pytest.mark.parametrize("mask,sign", [(0xF, -1), (0x5, 1), (0x8, -1), (0x6, 1), (0x0, 1)])
+def test_shift_direction_mask_and_backward_hop(prec, fmt, L, mask, sign):
+    U = latgen.haar_links(L, 31 + mask)
+    psi, phi = latgen.dirac_field(L, 32), latgen.dirac_field(L, 33)
+    chi, n2 = shift(L, U, psi, phi, 0.3, prec, fmt, mask=mask, sign=sign)
+    ref, n2ref = oracle.shift_expr(U, psi, phi, 0.3, mask, sign)
+    e_norm, e_max = rel_err(chi, ref)
+    assert e_norm < tol(prec) and e_max < tol(prec), (e_norm, e_max)
+    assert abs(n2 - n2ref) < tol(prec) * n2ref
+
+
+def test_forward_plus_backward_shift_is_the_hop():
+    """sign +1 plus sign -1 over one mask is the hopping term of qdpx_eval_hop."""
+    L = (8, 8, 4, 6)
+    U = latgen.haar_links(L, 41)
+    psi = latgen.dirac_field(L, 42)
+    c = ctx()
+    Ud = q.links_to_device(c, L, U, q.F64, q.LINK18, dev())
+    pd = q.fermion_to_device(c, L, psi, q.F64, dev())
+    f, b, h = (q.alloc_fermion(L, q.F64, dev()) for _ in range(3))
+    q.qdpx_eval_shift_mul_axpy(c, L, q.F64, q.LINK18, Ud, pd, None, 0.0, f, dir_mask=0xB, sign=1)
+    q.qdpx_eval_shift_mul_axpy(c, L, q.F64, q.LINK18, Ud, pd, None, 0.0, b, dir_mask=0xB, sign=-1)
+    q.qdpx_eval_hop(c, L, q.F64, q.LINK18, Ud, pd, h, 0xB)
+    fh, bh, hh = (q.fermion_to_host(c, L, t, q.F64) for t in (f, b, h))
+    assert max(rel_err(fh + bh, hh)) < 1e-14
+
+
+def test_shift_rejects_bad_mask_and_sign():
+    L = (4, 4, 4, 4)
+    c = ctx()
+    U = q.alloc_links(L, q.F64, q.LINK18, dev())
+    psi, chi = q.alloc_fermion(L, q.F64, dev()), q.alloc_fermion(L, q.F64, dev())
+    with pytest.raises(q.QdpxError, match="dir_mask"):
+        q.qdpx_eval_shift_mul_axpy(c, L, q.F64, q.LINK18, U, psi, None, 0.3, chi, dir_mask=0x10)
+    with pytest.raises(q.QdpxError, match="sign"):
+        q.qdpx_eval_shift_mul_axpy(c, L, q.F64, q.LINK18, U, psi, None, 0.3, chi, sign=0)
+
+
 def test_shift_without_phi():
     L = RAGGED
     U = latgen.haar_links(L, 5)
@@ -96,6 +153,26 @@ def test_plaquette(prec, fmt, L):
     got = plaquette(L, U, prec, fmt)
     ref = oracle.plaquette(U)
     assert np.max(np.abs(got - ref)) < tol(prec), (got, ref)
+
+
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_degenerate_w_gives_nan(prec, fmt):
+    """Links that vanish on four t slices make W vanish on the links whose
+    staples all touch them; the projection then writes NaN at exactly the
+    links where the oracle's projection reports a degenerate W, and the
+    oracle's value everywhere else."""
+    L = (8, 8, 4, 10)
+    U = latgen.haar_links(L, 51)
+    U[2:6] = 0.0
+    W = oracle.ape_w(U, 0.5)
+    Vref, nbad = oracle.reunitarise(W)
+    assert nbad > 0
+    bad = np.isnan(Vref).any(axis=(-1, -2))
+    assert np.isnan(Vref[bad]).all()
+    V, _ = ape(L, U, prec, fmt, 1, with_plaq=False)
+    assert np.array_equal(np.isnan(V).any(axis=(-1, -2)), bad)
+    assert np.isnan(V[bad]).all()
+    assert link_err(V[~bad], Vref[~bad]) < tol(prec)
 
 
 def test_plaquette_unit_links_exact():
