@@ -1,10 +1,11 @@
 """Benchmark: APE link smearing on a 32^3 x 64 lattice on one MI355X.
 
-One timed step = one call of qdpx_ape_smear: 10 APE smearing steps (alpha =
-0.5) of Haar-random SU(3) links, staple products in FP32 with links stored
-as 12 reals, FP64 reunitarisation, and the FP64 plaquette of the input and
-of every step's output.  ``value`` is link updates per second,
-4 * V * 10 * K / elapsed, with the links already resident in HBM.
+One timed step = 10 APE smearing steps (alpha = 0.5, one qdpx_ape_smear
+call) of Haar-random SU(3) links, staple products in FP32 with links stored
+as 12 reals, FP64 reunitarisation, then the FP64 plaquette of the smeared
+links (qdpx_plaquette).  ``value`` is link updates per second,
+4 * V * 10 * K / elapsed, with the links already resident in HBM.  The same
+steps with the plaquette of every step's output are reported beside it.
 
 The same JSON line carries the plain all-FP64 path for comparison, the
 roofline of the dominant kernel (the APE step kernel, timed with HIP events
@@ -100,8 +101,9 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--profile", action="store_true",
                    help="short run for hardware-counter profiling: one 1 GiB device copy (the calibration "
-                        "kernel of known size), then two plaquette-free and two timed-step calls of each APE link "
-                        "format, then four Jacobi hop launches per format; no JSON line")
+                        "kernel of known size), then two plaquette-free calls and two timed steps (10 APE steps and "
+                        "the plaquette) of each APE link format, then four Jacobi hop launches per format; no JSON "
+                        "line")
     return p.parse_args()
 
 
@@ -168,6 +170,43 @@ def main():
 
         return call, out, plaq
 
+    results = {}
+
+    def timed_step(name, per_step=False):
+        """The timed workload on one link format: 10 APE steps (one
+        qdpx_ape_smear call) and the FP64 plaquette of the smeared links
+        (qdpx_plaquette), or with per_step the plaquette of the input and of
+        every step's output from the smearing call itself.  Returns
+        (enqueue(stream), output links, plaquettes)."""
+        prec, fmt = paths[name]
+        out = q.alloc_links(L, prec, fmt, dev)
+        work = q.alloc_workspace(q.OP_APE, L, prec, fmt, N_APE, dev)
+        work_p = q.alloc_workspace(q.OP_PLAQ, L, prec, fmt, 1, dev)
+        plaq = torch.zeros(3 * (N_APE + 1) if per_step else 3, dtype=torch.float64, device=dev)
+        src = dev_links[name]
+
+        def enqueue(st):
+            if per_step:
+                q.qdpx_ape_smear(ctx, L, prec, fmt, src, out, ALPHA, N_APE, plaq, work, st)
+            else:
+                q.qdpx_ape_smear(ctx, L, prec, fmt, src, out, ALPHA, N_APE, None, work, st)
+                q.qdpx_plaquette(ctx, L, prec, fmt, out, plaq, work_p, st)
+
+        return enqueue, out, plaq
+
+    def graph_of(enqueue):
+        """The calls recorded once into a HIP graph (replayed on `stream`)."""
+        enqueue(stream)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.graph(g, stream=cs):
+            enqueue(cs)
+        g.replay()
+        torch.cuda.synchronize()
+        return g
+
     if args.profile:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -175,14 +214,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         # after tuning: two plaquette-free calls (the roofline kernel, mode 0)
-        # then two timed-step calls, per link format
+        # then two timed steps (10 APE steps + the plaquette), per link format
         for name in paths:
             call, _, _ = make_call(name, with_plaq=False)
             call()
             call()
-            call, _, _ = make_call(name)
-            call()
-            call()
+            step, _, _ = timed_step(name)
+            step(stream)
+            step(stream)
         # then, per format, the tuned Jacobi hop kernel, four launches
         psi = latgen.dirac_field(L, latgen.SEEDS["ape_32x32x32x64"]["links"] + 1)
         for name, (prec, fmt) in paths.items():
@@ -198,25 +237,15 @@ def main():
         ctx.close()
         return
 
-    results = {}
     # ---------------------------------------------------------------- headline
-    # One step = one qdpx_ape_smear call (10 APE steps + 11 plaquettes), its
-    # ~32 kernel launches recorded once into a HIP graph and replayed.
-    head, head_out, head_plaq = make_call("f32_12")
-    head_work = works["f32_12"]
-    head()
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    cap = torch.cuda.Stream()
-    cap.wait_stream(stream)
-    with torch.cuda.graph(graph, stream=cap):
-        prec_h, fmt_h = paths["f32_12"]
-        q.qdpx_ape_smear(ctx, L, prec_h, fmt_h, dev_links["f32_12"], head_out, ALPHA, N_APE, head_plaq,
-                         head_work, cap)
+    # One step = 10 APE steps + the FP64 plaquette of the result: the two
+    # calls' kernel launches recorded once into a HIP graph and replayed.
+    head, head_out, head_plaq = timed_step("f32_12")
+    graph = graph_of(head)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps of {N_APE} FP32-12 APE steps + plaquettes (graph replay)")
+    log(f"timing {args.steps} steps of {N_APE} FP32-12 APE steps + FP64 plaquette (graph replay)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         graph.replay()
@@ -227,8 +256,8 @@ def main():
     log(f"headline: {value / 1e9:.2f} G link-updates/s, {1e3 * elapsed / args.steps:.3f} ms/step")
     # the same calls launched eagerly, for comparison
     for _ in range(2):
-        head()
-    ms_eager = time_calls(torch, head, args.steps, stream) / args.steps
+        head(stream)
+    ms_eager = time_calls(torch, lambda: head(stream), args.steps, stream) / args.steps
     log(f"eager launches: {ms_eager:.3f} ms/step")
     # spread of single steps: graph replays each bracketed by its own events
     singles = sorted(time_calls(torch, graph.replay, 1, stream) for _ in range(max(20, args.steps)))
@@ -238,28 +267,29 @@ def main():
 
     # ---------------------------------------- per-kernel timing of each path
     kernel = {}
+    per_step_plaq = {}
+    reps = max(3, args.steps // 3)
     for name in paths:
         call, _, _ = make_call(name, with_plaq=False)
         call()
-        reps = max(3, args.steps // 3)
         ms = time_calls(torch, call, reps, stream)
         per_kernel_s = ms / 1e3 / (reps * N_APE)
         kernel[name] = per_kernel_s
         log(f"{name}: APE kernel {per_kernel_s * 1e6:.1f} us")
         if name != "f32_12":
-            # same timed step as the headline (graph replay), other link format
-            prec, fmt = paths[name]
-            _, out_p, plaq_p = make_call(name, with_plaq=True)
-            work_p = works[name]
-            gr = torch.cuda.CUDAGraph()
-            cs = torch.cuda.Stream()
-            cs.wait_stream(stream)
-            with torch.cuda.graph(gr, stream=cs):
-                q.qdpx_ape_smear(ctx, L, prec, fmt, dev_links[name], out_p, ALPHA, N_APE, plaq_p, work_p, cs)
-            gr.replay()
+            # the same timed step as the headline (graph replay), other link format
+            gr = graph_of(timed_step(name)[0])
             ms = time_calls(torch, gr.replay, reps, stream)
             results[name] = 4.0 * V * N_APE * reps / (ms / 1e3)
-            log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s with plaquettes (graph replay)")
+            log(f"{name}: {results[name] / 1e9:.2f} G link-updates/s (graph replay)")
+            del gr
+        if name != "f32_18":
+            # the same 10 steps with the plaquette of every step's output
+            gr = graph_of(timed_step(name, per_step=True)[0])
+            ms = time_calls(torch, gr.replay, reps, stream) / reps
+            per_step_plaq[name] = {"ms_per_step": ms, "link_updates_per_s": 4.0 * V * N_APE / (ms / 1e3)}
+            log(f"{name}: {ms:.3f} ms with the plaquette of every step (graph replay)")
+            del gr
     results["f32_12"] = value
 
     # ------------------------------ per-step errors (outside every timed region)
@@ -301,6 +331,7 @@ def main():
         "ape_kernel_roofline": {k: roof(k) for k in paths},
         "tuned_launch": tuned,
         "plaquette_after_10_steps_f32_12": [float(x) for x in head_plaq.cpu().numpy()[-3:]],
+        "with_plaquette_of_every_step": per_step_plaq,
         "errors_per_step_32x32x32x64": {
             "note": "step k = 1..10 of the timed workload; FP32-12 and FP64-18 GPU paths against each other on "
                     "every link, SU(3) defects on every link, and against the FP64 oracle on "
@@ -344,8 +375,8 @@ def main():
         "dtype": "f32 staples / f64 projection and plaquette",
         "data": "synthetic: Haar-random SU(3) links, seed 1305",
         "config": {
-            "workload": "APE smearing, 10 steps alpha=0.5 + FP64 plaquette per step, 32^3x64 periodic, "
-                        "links FP32 12-real",
+            "workload": "APE smearing, 10 steps alpha=0.5 then the FP64 plaquette of the smeared links, "
+                        "32^3x64 periodic, links FP32 12-real, FP64 projection",
             "lattice": list(L),
             "sites": V,
             "ape_steps_per_step": N_APE,

@@ -263,12 +263,15 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
  * does so only for diagonal g.
  * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
  * triple (total, spatial, temporal; normalised as in qdpx_plaquette; all six
- * planes whatever the mask) of the input and of every step's output.  These
- * traces are formed in the link precision and summed in FP64 (qdpx_plaquette
- * forms them in FP64); with smear_mask 0xF and the Gram-Schmidt projection
- * they are fused into the smearing kernel, otherwise each is a pass of its
- * own with the same arithmetic.  The
- * smeared links do not depend on whether plaq is requested.
+ * planes whatever the mask) of the input and of every step's output, every
+ * product and sum in FP64.  QDPX_F32: each triple is qdpx_plaquette's pass
+ * on those links (the FP32 entries widened to FP64), bit for bit.  QDPX_F64:
+ * with smear_mask 0xF and the Gram-Schmidt projection the traces of a step's
+ * input are fused into that step's kernel (each plaquette from rows 0 and 1
+ * of its two halves, exact for SU(3) links) and the last output's take a
+ * pass of their own with the same arithmetic; they agree with qdpx_plaquette
+ * to FP64 rounding.  The smeared links do not depend on whether plaq is
+ * requested.
  * A W whose row 0 or projected row 1 vanishes gives NaN entries.
  * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
 int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
@@ -290,16 +293,17 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
 /* ------------------------------------------------------ batched APE smearing
  * The batched workload: 64 independent lattices with extents drawn from
  * 8^4, 12^3 x 24, 16^3 x 32 and 24^3 x 48, 5 APE steps each and the final
- * plaquettes, in one persistent launch that a HIP graph may capture.
+ * plaquettes, enqueued as one group of kernels that a HIP graph may capture.
  * n_lat independent lattices of any extents (each at most 4194304 sites),
  * each smeared n_steps times (1 <= n_steps <= 1024) as in qdpx_ape_smear
- * with smear_mask 0xF, followed by each lattice's output plaquette triple, in
- * ONE persistent kernel launch (plus a small kernel that clears its
- * counters).  The launch runs in phases (step 1 .. n_steps, then the
- * plaquettes); within a phase the work items of every lattice are shared by
- * all blocks through per-XCD ticket queues, and a phase starts once every
- * block has finished the previous one, so a batch of small and large
- * lattices fills the GPU as one job.
+ * with smear_mask 0xF, followed by each lattice's output plaquette triple.
+ * All n_steps steps of all lattices run in ONE persistent kernel launch: it
+ * runs in phases (step 1 .. n_steps); within a phase the work items of every
+ * lattice are shared by all blocks through per-XCD ticket queues, and a phase
+ * starts once every block has finished the previous one, so a batch of small
+ * and large lattices fills the GPU as one job.  Around it: a small kernel
+ * that clears the counters before, and (plaq non-NULL) two kernels after it
+ * that form and reduce the plaquettes of every lattice.
  *   geoms: host array [n_lat]; U_in, U_out: host arrays [n_lat] of device
  *   pointers (SoA, prec, fmt; U_out[i] must not overlap any U_in[j] or
  *   another U_out[j]); plaq (nullable): device double[n_lat][3].
@@ -309,16 +313,18 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
  *   1 if a wait for a previous step exceeded its spin limit (outputs are then
  *   incomplete; the limit may be lowered with the environment variable
  *   QDPX_SPIN_LIMIT, read at every call, to exercise this path).
- * The first call with a given (lattices, pointers, workspace) set copies a
- * small per-lattice table to the device and keeps it in the context (freed by
- * qdpx_free_all / qdpx_destroy); that first call synchronises and returns
- * QDPX_ECAPTURE on a capturing stream.  Later calls, and replays of a graph
- * that captured one, reuse the table and only enqueue the two kernels.
- * Links and plaquettes are identical, bit for bit, to qdpx_ape_smear on each
- * lattice with plaquettes requested.  Work items are runs of t-rows of one
- * column (one brick of one z plane) of one lattice, queued per XCD by column;
- * the run length is set with qdpx_tune_set(ctx, QDPX_OP_BATCHED, &geoms[0],
- * prec, fmt, 256, rows, 0, 1) (default 1). */
+ * The first call with a given (lattices, pointers, workspace, groups per
+ * ticket) set copies a small per-lattice table to the device and keeps it in
+ * the context (freed by qdpx_free_all / qdpx_destroy); that first call
+ * synchronises and returns QDPX_ECAPTURE on a capturing stream.  Later calls,
+ * and replays of a graph that captured one, reuse the table and only enqueue
+ * the kernels.  Links and plaquettes are identical, bit for bit, to
+ * qdpx_ape_smear on each lattice with plaquettes requested.  Work items are
+ * runs of 64-site groups of one lattice: each lattice's columns (one brick of
+ * one z plane each) are split into 8 contiguous ranges, one per XCD queue,
+ * walked t-row by t-row.  Threads per block (256 or 512) and groups per
+ * ticket come from qdpx_tune_batched, or qdpx_tune_set(ctx, QDPX_OP_BATCHED,
+ * &geoms[0], prec, fmt, block, groups, 1, 1) (default 256 and 1). */
 int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
                            qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out,
                            double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,
@@ -384,9 +390,10 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * for the default geometry, 1 for one read from the launch table, 2 for one
  * qdpx_tune found, 3 for one qdpx_tune_set gave);
  * t_window must divide Lt and only matters when Lx is a multiple of 8 and Ly
- * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED only
- * sites_per_thread is used, as the number of 64-site groups per work item,
- * keyed by the first lattice's extents. */
+ * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED (tuned by
+ * qdpx_tune_batched, which qdpx_tune refuses with QDPX_EUNSUPPORTED) block is
+ * 256 or 512 and sites_per_thread is the number of 64-site groups per work
+ * ticket, keyed by the first lattice's extents. */
 int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
               void *stream);
 int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
@@ -394,6 +401,15 @@ int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec pr
                   int32_t *source);
 int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                   int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window);
+/* The autotuner of the batched call: times it on this batch of extents
+ * (n_lat lattices, n_steps steps, temporary links) with 256- and 512-thread
+ * blocks (one or two 64-site groups at a time) and 1, 2, 4 or 8 groups per
+ * work ticket, and remembers the fastest for QDPX_OP_BATCHED under the first
+ * lattice's extents (written to the context's launch table, if any).
+ * Allocates, synchronises, and returns QDPX_ECAPTURE on a capturing stream. */
+int qdpx_tune_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt,
+                      int n_steps, void *stream);
+
 /* Write every geometry the context read, tuned or was given into the
  * launch-table file `path` (NULL: the context's own table), merged with the
  * entries the file already holds for other shapes; the file is replaced

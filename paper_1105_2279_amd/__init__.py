@@ -40,7 +40,7 @@ EXPORTS = (
     "qdpx_pack_links", "qdpx_unpack_links", "qdpx_pack_fermion", "qdpx_unpack_fermion",
     "qdpx_eval_shift_mul_axpy", "qdpx_shift_chain", "qdpx_ape_smear", "qdpx_plaquette",
     "qdpx_ape_smear_batched", "qdpx_tune", "qdpx_tune_get", "qdpx_tune_set",
-    "qdpx_eval_hop", "qdpx_jacobi_smear", "qdpx_tune_save",
+    "qdpx_eval_hop", "qdpx_jacobi_smear", "qdpx_tune_save", "qdpx_tune_batched",
     "qdpx_jit_generate", "qdpx_jit_compile", "qdpx_jit_info", "qdpx_jit_eval",
 )
 
@@ -102,6 +102,7 @@ def lib():
         "qdpx_ape_smear_batched": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(_P), ctypes.POINTER(_P), dbl, i32,
                                          _P, _P, sz, _P]),
         "qdpx_tune": (i32, [_P, i32, _G, i32, i32, _P]),
+        "qdpx_tune_batched": (i32, [_P, i32, _G, i32, i32, i32, _P]),
         "qdpx_eval_hop": (i32, [_P, _G, i32, i32, _P, _P, _P, ctypes.c_uint32, _P]),
         "qdpx_jit_generate": (i32, [ctypes.c_char_p, i32, i32, i32, i32, _P, sz, ctypes.POINTER(sz)]),
         "qdpx_jit_compile": (i32, [_P, ctypes.c_char_p, i32, i32, i32, i32, ctypes.POINTER(i32)]),
@@ -324,6 +325,13 @@ def qdpx_jit_eval(ctx, kernel, L, U, fields, scalars, out, norm2=None, work=None
 
 def qdpx_tune(ctx, op, L, prec, fmt, stream=None):
     _check(lib().qdpx_tune(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, _stream(stream)), "qdpx_tune")
+
+
+def qdpx_tune_batched(ctx, Ls, prec, fmt, n_steps, stream=None):
+    n = len(Ls)
+    garr = (Geom * n)(*[geom(x) for x in Ls])
+    _check(lib().qdpx_tune_batched(ctx.handle, n, garr, prec, fmt, int(n_steps), _stream(stream)),
+           "qdpx_tune_batched")
 
 
 TUNE_SOURCES = ("default", "table", "tuned", "set")

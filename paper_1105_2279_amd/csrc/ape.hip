@@ -1,5 +1,7 @@
-// Single-lattice kernels: one APE step (optionally with the plaquette of its
-// input), the plaquette-only pass, and the standalone FP64 plaquette.
+// Single-lattice kernels: one APE step (for FP64 links optionally with the
+// plaquette of its input), the FP64 plaquette-only pass of the step's
+// arithmetic, and the standalone plaquette (FP64 products for every link
+// precision).
 #include "qdpx_impl.hpp"
 #include "ape_device.hpp"
 
@@ -23,7 +25,8 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     // upper staple of direction nu starts from U_nu(x), the own link of wave
     // nu, so each site loads it once instead of four times (a sixth fewer
     // vector-memory instructions; 24 KB of LDS per 512-thread block).
-    constexpr bool kShare = sizeof(R) == 4 && PROJ == 0 && MODE != kPlaqOnly;
+    static_assert(MODE == kApe || sizeof(R) == 8, "FP32 steps take their plaquettes from k_plaquette");
+    constexpr bool kShare = sizeof(R) == 4 && PROJ == 0;
     if constexpr (kShare) {
         // the four own links of each group, rows 0 and 1 as three pairs
         __shared__ nv4_t<R> own[2][4 * 3 * 64];
@@ -56,6 +59,7 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
                            int proj) {
     if (mode == kApePlaq && mask != 0xFu) return hipErrorInvalidValue;  // owned planes need every staple
     if (proj && mode != kApe) return hipErrorInvalidValue;             // polar: plaquettes in their own pass
+    if (prec != 0 && mode != kApe) return hipErrorInvalidValue;        // FP32: plaquettes from k_plaquette
     const int groups = (g.V + 63) / 64;
     const int gpb = cfg.block / 256;
     const int per_block = gpb * cfg.nsite;
@@ -65,74 +69,51 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     k_ape_step<R, NR, NS, M, P><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},     \
                                                          LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2, mask,  \
                                                          partials, xcd, cfg.tw)
-#define QDPX_APE_M(R, NR, NS)                                         \
-    if (proj) QDPX_APE_LAUNCH(R, NR, NS, kApe, 1);                    \
-    else if (mode == kPlaqOnly) QDPX_APE_LAUNCH(R, NR, NS, kPlaqOnly, 0); \
-    else if (mode == kApePlaq) QDPX_APE_LAUNCH(R, NR, NS, kApePlaq, 0);   \
-    else QDPX_APE_LAUNCH(R, NR, NS, kApe, 0);
-#define QDPX_APE_NS(R, NR)                         \
+#define QDPX_APE_M64(NS)                                                       \
+    if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1);                         \
+    else if (mode == kPlaqOnly) QDPX_APE_LAUNCH(double, 3, NS, kPlaqOnly, 0);  \
+    else if (mode == kApePlaq) QDPX_APE_LAUNCH(double, 3, NS, kApePlaq, 0);    \
+    else QDPX_APE_LAUNCH(double, 3, NS, kApe, 0);
+#define QDPX_APE_M32(NR, NS)                          \
+    if (proj) QDPX_APE_LAUNCH(float, NR, NS, kApe, 1); \
+    else QDPX_APE_LAUNCH(float, NR, NS, kApe, 0);
+#define QDPX_APE_NS(M)                             \
     switch (cfg.nsite) {                           \
-    case 2: QDPX_APE_M(R, NR, 2) break;            \
-    case 4: QDPX_APE_M(R, NR, 4) break;            \
-    default: QDPX_APE_M(R, NR, 1) break;           \
+    case 2: M(2) break;                            \
+    case 4: M(4) break;                            \
+    default: M(1) break;                           \
     }
+#define QDPX_APE_F32_3(NS) QDPX_APE_M32(3, NS)
+#define QDPX_APE_F32_2(NS) QDPX_APE_M32(2, NS)
     if (prec == 0) {
-        QDPX_APE_NS(double, 3)
+        QDPX_APE_NS(QDPX_APE_M64)
     } else if (nrows == 3) {
-        QDPX_APE_NS(float, 3)
+        QDPX_APE_NS(QDPX_APE_F32_3)
     } else {
-        QDPX_APE_NS(float, 2)
+        QDPX_APE_NS(QDPX_APE_F32_2)
     }
+#undef QDPX_APE_F32_2
+#undef QDPX_APE_F32_3
+#undef QDPX_APE_M32
+#undef QDPX_APE_M64
 #undef QDPX_APE_NS
-#undef QDPX_APE_M
 #undef QDPX_APE_LAUNCH
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- plaquette
-// One site per lane, block of 256 threads; the spatial and temporal sums of
-// each 64-site group go to partials[grp] and partials[n + grp].
+// One site per lane, four 64-site groups (the brick groups of the step
+// kernels) per 256-thread block; the spatial and temporal sums of group grp
+// go to partials[grp] and partials[n + grp].
 template <typename R, int NR>
 __global__ void __launch_bounds__(256) k_plaquette(Geo g, LinksRO<R, NR> U, double *__restrict__ partials) {
     const int lane = threadIdx.x & 63;
     const int grp = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int n = (g.V + 63) >> 6;
     if (grp >= n) return;
-    const int s = grp * 64 + lane;
     double sp = 0.0, tp = 0.0;
-    if (s < g.V) {
-        Site x;
-        x.init(g, s);
-#pragma unroll 1
-        for (int mu = 0; mu < 3; ++mu) {
-            M3<double> a;
-            load_f64(U, mu, s, a);
-            const int s_mu = hop_fwd(g, s, coord(x, mu), mu);
-#pragma unroll 1
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                M3<double> b, c, d;
-                load_f64(U, nu, s_mu, b);                                // U_nu(x+mu)
-                load_f64(U, mu, hop_fwd(g, s, coord(x, nu), nu), c);          // U_mu(x+nu)
-                load_f64(U, nu, s, d);                                   // U_nu(x)
-                // Re Tr[(a b)(d c)^dag]
-                double p = 0.0;
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        Cx<double> xab{0.0, 0.0}, xdc{0.0, 0.0};
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            cmac(xab, a.e[i][k], b.e[k][j]);
-                            cmac(xdc, d.e[i][k], c.e[k][j]);
-                        }
-                        p = fma(xab.re, xdc.re, fma(xab.im, xdc.im, p));
-                    }
-                if (nu == 3) tp += p;
-                else sp += p;
-            }
-        }
-    }
+    Site x;
+    if (group_site(g, grp, lane, x)) plaquette_site(g, U, x, sp, tp);
     sp = wave_sum(sp);
     tp = wave_sum(tp);
     if (lane == 0) {

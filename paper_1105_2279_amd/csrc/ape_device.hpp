@@ -57,6 +57,51 @@ template <typename R> __device__ __forceinline__ void acc_23_33dag(M23<R> &S, co
             for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
 }
 
+// Full 3x3 products (the polar projection, which reads all of W, and the
+// FP64 plaquette).
+// T = A * B
+template <typename R> __device__ __forceinline__ void mul_33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(t, A.e[i][k], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// T = A^dag * B
+template <typename R> __device__ __forceinline__ void mul_dag33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_ca(t, A.e[k][i], B.e[k][j]);
+            T.e[i][j] = t;
+        }
+}
+// S += T * C
+template <typename R> __device__ __forceinline__ void acc_33_33(M3<R> &S, const M3<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(S.e[i][j], T.e[i][k], C.e[k][j]);
+}
+// S += T * C^dag
+template <typename R> __device__ __forceinline__ void acc_33_33dag(M3<R> &S, const M3<R> &T, const M3<R> &C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
+}
+
 // Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12.
 template <typename R, int NR>
 __device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s, M3<double> &m) {
@@ -67,6 +112,93 @@ __device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s,
 #pragma unroll
         for (int b = 0; b < 3; ++b) m.e[a][b] = Cx<double>{(double)r[a][b].re, (double)r[a][b].im};
     if constexpr (NR == 2) rebuild_row2(m);
+}
+
+// Row i of link (mu, s) in FP64: a stored row widened, or (LINK12, i = 2)
+// rebuilt in FP64 from the widened rows 0 and 1, as load_f64 forms it.
+template <typename R, int NR, int I>
+__device__ __forceinline__ void row_f64(const LinksRO<R, NR> &U, int mu, int s, Cx<double> (&r)[3]) {
+    if constexpr (I < 2 || NR == 3) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const Cx<R> z = U.ld(mu, I, b, s);
+            r[b] = Cx<double>{(double)z.re, (double)z.im};
+        }
+    } else {
+        M3<double> m;
+        Cx<R> e[2][3];
+        U.template load_rows<false, 2>(mu, s, e);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m.e[a][b] = Cx<double>{(double)e[a][b].re, (double)e[a][b].im};
+        rebuild_row2(m);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) r[b] = m.e[2][b];
+    }
+}
+
+// Re Tr P_{mu nu}(x) = Re Tr[(U_mu(x) U_nu(x+mu)) (U_nu(x) U_mu(x+nu))^dag] of
+// the stored links widened to FP64 (row 2 rebuilt in FP64 for LINK12), every
+// product and sum in FP64: the plaquette of the standalone pass, of the FP32
+// steps' per-step plaquettes and of the batched FP32 plaquettes, one
+// function so that they agree bit for bit.  s_mu = x+mu, s_nu = x+nu.  Rows of
+// U_mu(x) and U_nu(x) are loaded as they are needed, so that only the two
+// neighbour links and one product are held in FP64 at a time.
+template <typename R, int NR>
+__device__ __forceinline__ double plaquette_plane(const LinksRO<R, NR> &U, int mu, int nu, int s, int s_mu,
+                                                  int s_nu) {
+    M3<double> m;  // U_mu(x) U_nu(x+mu)
+    {
+        M3<double> b;
+        load_f64(U, nu, s_mu, b);
+        Cx<double> a[3];
+#define QDPX_PLAQ_ROW_M(I)                                                           \
+        row_f64<R, NR, I>(U, mu, s, a);                                              \
+        for (int j = 0; j < 3; ++j) {                                                \
+            Cx<double> t{0.0, 0.0};                                                  \
+            for (int k = 0; k < 3; ++k) cmac(t, a[k], b.e[k][j]);                     \
+            m.e[I][j] = t;                                                           \
+        }
+        QDPX_PLAQ_ROW_M(0)
+        QDPX_PLAQ_ROW_M(1)
+        QDPX_PLAQ_ROW_M(2)
+#undef QDPX_PLAQ_ROW_M
+    }
+    M3<double> c;  // U_mu(x+nu)
+    load_f64(U, mu, s_nu, c);
+    double p = 0.0;
+    Cx<double> d[3];
+#define QDPX_PLAQ_ROW_N(I)                                                               \
+    row_f64<R, NR, I>(U, nu, s, d);                                                      \
+    for (int j = 0; j < 3; ++j) {                                                        \
+        Cx<double> n{0.0, 0.0};                                                          \
+        for (int k = 0; k < 3; ++k) cmac(n, d[k], c.e[k][j]);                            \
+        p = fma(m.e[I][j].re, n.re, fma(m.e[I][j].im, n.im, p));                          \
+    }
+    QDPX_PLAQ_ROW_N(0)
+    QDPX_PLAQ_ROW_N(1)
+    QDPX_PLAQ_ROW_N(2)
+#undef QDPX_PLAQ_ROW_N
+    return p;
+}
+
+// Spatial (nu < 3) and temporal (nu = 3) plaquette sums of site x over the
+// six planes, planes (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) added in that order.
+template <typename R, int NR>
+__device__ __forceinline__ void plaquette_site(const Geo &g, const LinksRO<R, NR> &U, const Site &x, double &sp,
+                                               double &tp) {
+    sp = tp = 0.0;
+#pragma unroll 1
+    for (int mu = 0; mu < 3; ++mu) {
+        const int s_mu = hop_fwd(g, x.s, coord(x, mu), mu);
+#pragma unroll 1
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            const double p = plaquette_plane(U, mu, nu, x.s, s_mu, hop_fwd(g, x.s, coord(x, nu), nu));
+            if (nu == 3) tp += p;
+            else sp += p;
+        }
+    }
 }
 
 // Plaquette planes are shared out over the four direction waves so that each
@@ -214,50 +346,6 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             acc_23_33(S, T, C);
         }
     }
-}
-
-// Full 3x3 products for the polar projection, which reads all of W.
-// T = A * B
-template <typename R> __device__ __forceinline__ void mul_33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            Cx<R> t{(R)0, (R)0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(t, A.e[i][k], B.e[k][j]);
-            T.e[i][j] = t;
-        }
-}
-// T = A^dag * B
-template <typename R> __device__ __forceinline__ void mul_dag33_33(const M3<R> &A, const M3<R> &B, M3<R> &T) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            Cx<R> t{(R)0, (R)0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_ca(t, A.e[k][i], B.e[k][j]);
-            T.e[i][j] = t;
-        }
-}
-// S += T * C
-template <typename R> __device__ __forceinline__ void acc_33_33(M3<R> &S, const M3<R> &T, const M3<R> &C) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(S.e[i][j], T.e[i][k], C.e[k][j]);
-}
-// S += T * C^dag
-template <typename R> __device__ __forceinline__ void acc_33_33dag(M3<R> &S, const M3<R> &T, const M3<R> &C) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
 }
 
 // Full staple sum (all three rows) of link (s, mu) over nu in mask, the same

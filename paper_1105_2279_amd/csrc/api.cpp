@@ -319,7 +319,7 @@ static bool stream_capturing(hipStream_t st) {
 
 static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
     LaunchCfg c;
-    if (op == QDPX_OP_BATCHED) c.nsite = 1;  // t-rows of one column per work item
+    if (op == QDPX_OP_BATCHED) c.nsite = 1;  // groups per ticket
     if (ctx) {
         TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
         auto it = ctx->tuned.find(k);
@@ -584,28 +584,37 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     // d = number of smeared directions (alpha/6 for all four).
     const int d = __builtin_popcount(smear_mask);
     const double c1 = 1.0 - alpha, c2 = d > 1 ? alpha / (2.0 * (d - 1)) : 0.0;
-    // With every direction smeared and the Gram-Schmidt projection, step k
-    // also reduces the plaquette of its own input (fused into the APE kernel)
-    // and only the last output needs the plaquette-only pass; otherwise every
-    // plaquette is its own pass (the same per-plane arithmetic, so the values
+    // Plaquettes.  FP32 links: the standalone plaquette pass (FP64 products
+    // of the widened links) on the input and on every step's output, so each
+    // value is the one qdpx_plaquette gives on those links.  FP64 links: with
+    // every direction smeared and the Gram-Schmidt projection, step k also
+    // reduces the plaquette of its own input (fused into the APE kernel) and
+    // only the last output needs the plaquette-only pass; otherwise every
+    // plaquette is that pass (the same per-plane arithmetic, so the values
     // agree bit for bit).
-    const bool fused = (smear_mask == 0xFu) && !polar;
+    const bool f32 = (prec == QDPX_F32);
+    const bool fused = !f32 && (smear_mask == 0xFu) && !polar;
+    auto plaquette_of = [&](const void *links, double *out) -> int {
+        if (f32) return plaquette_into(g, prec, fmt, links, out, part, st, fn);
+        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), links, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
+        QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, out, st), fn);
+        return QDPX_OK;
+    };
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
         void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
         if (plaq && !fused)
-            QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
+            if (int r = plaquette_of(src, plaq + 3 * k)) return r;
         QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, smear_mask,
                                      (plaq && fused) ? part : nullptr, (plaq && fused) ? 1 : 0, cfg, st, polar),
                      fn);
-        if (plaq) QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
+        if (plaq && fused)
+            QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * k, st), fn);
         src = dst;
     }
-    if (plaq) {
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), U_out, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
-        QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, plaq + 3 * n_steps, st), fn);
-    }
+    if (plaq)
+        if (int r = plaquette_of(U_out, plaq + 3 * n_steps)) return r;
     return QDPX_OK;
 }
 
@@ -697,13 +706,19 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
     if (plaq && overlap(plaq, sizeof(double) * 3 * n_lat, work, need))
         return fail(QDPX_EALIAS, "%s: plaq overlaps the workspace", fn);
 
-    // groups per work item: tuned per (first lattice extents, precision, format)
-    const int group_chunk = std::max(1, cfg_for(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt).nsite);
-    // host table: each lattice's groups as a (column, t-row) grid, columns
-    // dealt to the XCD queues by c % 8, items = runs of group_chunk rows
+    // launch geometry: threads per block (256 or 512: one or two groups at a
+    // time) and groups per ticket, tuned per (first lattice's extents,
+    // precision, format)
+    const LaunchCfg bcfg = cfg_for(ctx, QDPX_OP_BATCHED, &geoms[0], prec, fmt);
+    const int block = bcfg.block == 512 ? 512 : 256;
+    const int group_chunk = std::max(1, bcfg.nsite);
+    // host table: each lattice's groups as a (column, t-row) grid, its
+    // columns split into 8 contiguous ranges (one per XCD queue) walked
+    // t-row by t-row, in tickets of group_chunk groups
     std::vector<BatchLat> tab(n_lat);
     char *base = (char *)work + batched_counter_bytes(n_lat);
     int64_t xtotal[kXcds] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t pblocks = 0;
     for (int i = 0; i < n_lat; ++i) {
         BatchLat &L = tab[i];
         memset(&L, 0, sizeof L);
@@ -722,17 +737,21 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
             L.ncol = L.ngroups;
             L.nrow = 1;
         }
-        L.nchunk = (L.nrow + group_chunk - 1) / group_chunk;
         for (int x = 0; x < kXcds; ++x) {
+            L.xcol0[x] = (int)((int64_t)x * L.ncol / kXcds);
+            L.xcol1[x] = (int)((int64_t)(x + 1) * L.ncol / kXcds);
+            const int cols = L.xcol1[x] - L.xcol0[x];
+            L.dcols[x] = FastDiv::make((uint32_t)std::max(cols, 1));
             L.xbase[x] = (int)xtotal[x];
-            const int cols = L.ncol > x ? (L.ncol - x + kXcds - 1) / kXcds : 0;
-            xtotal[x] += (int64_t)cols * L.nchunk;
+            xtotal[x] += ((int64_t)cols * L.nrow + group_chunk - 1) / group_chunk;
         }
+        L.pbase = (int)pblocks;
+        pblocks += batched_plaq_blocks((int)prec, L.ngroups);
     }
     int64_t items = 0;
     for (int x = 0; x < kXcds; ++x) items += xtotal[x];
-    const int n_phases = n_steps + (plaq ? 1 : 0);
-    if (items >= (int64_t)1 << 31) return fail(QDPX_EUNSUPPORTED, "%s: too many work items", fn);
+    if (items >= (int64_t)1 << 31 || pblocks >= (int64_t)1 << 31)
+        return fail(QDPX_EUNSUPPORTED, "%s: too many work items", fn);
 
     BatchKey key;
     key.v = {(uint64_t)n_lat, (uint64_t)prec, (uint64_t)fmt, (uint64_t)(uintptr_t)work, (uint64_t)group_chunk};
@@ -758,6 +777,7 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
         ctx->batch_tables[key] = dtab;
     }
     BatchArgs a;
+    memset(&a, 0, sizeof a);
     a.lats = (const BatchLat *)dtab;
     a.counters = (unsigned *)work;
     a.plaq = plaq;
@@ -765,15 +785,15 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
     a.c2 = alpha / 6.0;
     a.n_lat = n_lat;
     a.n_steps = n_steps;
-    a.n_phases = n_phases;
     a.items_per_phase = (int)items;
     for (int x = 0; x < kXcds; ++x) a.xtotal[x] = (int)xtotal[x];
     a.group_chunk = group_chunk;
+    a.plaq_blocks = (int)pblocks;
     a.spin_limit = spin_limit_from_env();
-    const int resident = batched_resident_blocks(prec, nrows_of(fmt));
+    const int resident = batched_resident_blocks(prec, nrows_of(fmt), block);
     if (resident <= 0) return fail(QDPX_EHIP, "%s: occupancy query failed", fn);
-    const int grid = (int)std::min<int64_t>(resident, std::max<int64_t>(items, n_lat));
-    QDPX_TRY_HIP(launch_ape_batched(a, prec, nrows_of(fmt), grid, st), fn);
+    const int grid = (int)std::min<int64_t>(resident, std::max<int64_t>(items, 1));
+    QDPX_TRY_HIP(launch_ape_batched(a, prec, nrows_of(fmt), block, grid, st), fn);
     return QDPX_OK;
 }
 
@@ -785,7 +805,8 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN || op == QDPX_OP_JACOBI)  // four waves per group, one per direction
         return c.block == 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
-    if (op == QDPX_OP_BATCHED) return c.block == 256 && c.nsite >= 1 && c.nsite <= 1024;  // nsite = groups per item
+    if (op == QDPX_OP_BATCHED)  // nsite = groups per ticket; xcd_map and t_window unused
+        return (c.block == 256 || c.block == 512) && c.nsite >= 1 && c.nsite <= 1024;
     return false;
 }
 
@@ -837,7 +858,8 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, fmt, fn)) return r;
     if (op != QDPX_OP_APE && op != QDPX_OP_SHIFT && op != QDPX_OP_CHAIN && op != QDPX_OP_JACOBI)
-        return fail(QDPX_EUNSUPPORTED, "%s: op %d has a fixed geometry", fn, (int)op);
+        return fail(QDPX_EUNSUPPORTED, "%s: op %d is not tuned here (QDPX_OP_BATCHED: qdpx_tune_batched)", fn,
+                    (int)op);
     hipStream_t st = (hipStream_t)stream;
     if (stream_capturing(st)) return fail(QDPX_ECAPTURE, "%s: stream is capturing", fn);
     const Geo g = make_geo(geom->L);
@@ -938,6 +960,98 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     ctx->tuned[key] = Tuned{best_cfg, kSrcTuned};
     log_cfg("tuned", key, best_cfg);
     // a context with a launch table keeps what it tuned for later processes
+    if (!ctx->cache_path.empty()) return save_table(ctx, ctx->cache_path, fn);
+    return QDPX_OK;
+}
+
+// Times the batched call on the caller's batch of extents with temporary
+// links filled with a constant byte pattern (the cost does not depend on the
+// values): 256- or 512-thread blocks and 1 to 8 groups per ticket; keeps the
+// fastest under the first lattice's extents.
+extern "C" int qdpx_tune_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec, qdpx_linkfmt fmt,
+                                 int n_steps, void *stream) {
+    const char *fn = "qdpx_tune_batched";
+    QDPX_CHECK_CTX(fn);
+    if (int r = batched_check_geoms(n_lat, geoms, fn)) return r;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    if (n_steps < 1 || n_steps > kBatchMaxSteps)
+        return fail(QDPX_EINVAL, "%s: n_steps = %d outside [1, %d]", fn, n_steps, kBatchMaxSteps);
+    hipStream_t st = (hipStream_t)stream;
+    if (stream_capturing(st)) return fail(QDPX_ECAPTURE, "%s: stream is capturing", fn);
+    std::vector<void *> bufs;
+    auto alloc = [&](size_t n) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        if (hipMemsetAsync(p, 0x3c, n, st) != hipSuccess) return nullptr;
+        return p;
+    };
+    std::vector<const void *> in(n_lat);
+    std::vector<void *> out(n_lat);
+    const size_t wb = batched_ws_bytes(n_lat, geoms, prec, fmt, n_steps);
+    void *work = alloc(wb);
+    void *plaq = alloc(sizeof(double) * 3 * (size_t)n_lat);
+    bool ok = work && plaq;
+    for (int i = 0; i < n_lat && ok; ++i) {
+        const size_t lb = qdpx_links_bytes(&geoms[i], prec, fmt);
+        in[i] = alloc(lb);
+        out[i] = alloc(lb);
+        ok = in[i] && out[i];
+    }
+    const TuneKey key{(int)QDPX_OP_BATCHED, (int)prec, (int)fmt, {geoms[0].L[0], geoms[0].L[1], geoms[0].L[2], geoms[0].L[3]}};
+    const auto saved = ctx->tuned.find(key) == ctx->tuned.end() ? Tuned{} : ctx->tuned[key];
+    const bool had = ctx->tuned.count(key) != 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        // the device tables built for the temporary buffers
+        for (auto it = ctx->batch_tables.begin(); it != ctx->batch_tables.end();) {
+            if (it->first.v.size() > 3 && it->first.v[3] == (uint64_t)(uintptr_t)work) {
+                (void)hipFree(it->second);
+                it = ctx->batch_tables.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        for (void *p : bufs) (void)hipFree(p);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (had) ctx->tuned[key] = saved;
+        else ctx->tuned.erase(key);
+    };
+    if (!ok) {
+        cleanup();
+        return fail(QDPX_ENOMEM, "%s: could not allocate tuning buffers", fn);
+    }
+    auto run = [&](const LaunchCfg &c) -> bool {
+        ctx->tuned[key] = Tuned{c, kSrcSet};
+        return qdpx_ape_smear_batched(ctx, n_lat, geoms, prec, fmt, in.data(), out.data(), 0.5, n_steps,
+                                      (double *)plaq, work, wb, stream) == QDPX_OK;
+    };
+    std::vector<LaunchCfg> cands;
+    for (int b : {256, 512})
+        for (int n : {1, 2, 4, 8}) cands.push_back(LaunchCfg{b, n, 1, 1});
+    std::vector<float> best_ms(cands.size(), 1e30f);
+    for (int pass = 0; pass < 3; ++pass)
+        for (size_t i = 0; i < cands.size(); ++i) {
+            if (!run(cands[i])) continue;  // warm-up (builds the table on the first pass)
+            bool good = hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 3; ++r) good = run(cands[i]) && good;
+            good = hipEventRecord(e1, st) == hipSuccess && good;
+            good = hipEventSynchronize(e1) == hipSuccess && good;
+            float ms = 0.f;
+            good = hipEventElapsedTime(&ms, e0, e1) == hipSuccess && good;
+            if (good) best_ms[i] = std::min(best_ms[i], ms / 3);
+        }
+    size_t bi = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+        if (best_ms[i] < best_ms[bi]) bi = i;
+    const float best = best_ms[bi];
+    cleanup();
+    if (best >= 1e30f) return fail(QDPX_EHIP, "%s: no candidate geometry ran", fn);
+    ctx->tuned[key] = Tuned{cands[bi], kSrcTuned};
+    log_cfg("tuned", key, cands[bi]);
     if (!ctx->cache_path.empty()) return save_table(ctx, ctx->cache_path, fn);
     return QDPX_OK;
 }

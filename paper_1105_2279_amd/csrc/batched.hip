@@ -1,15 +1,17 @@
 // Persistent batched APE smearing: many independent lattices of any extents,
-// n_steps APE steps each and the final plaquettes, in one launch.
+// n_steps APE steps each in one persistent launch, then the final plaquettes.
 //
-// The launch walks through phases: the n APE steps, then (with plaquettes)
-// the plaquette traces of the outputs and the per-lattice finalisation.
-// Within a phase the work items are (lattice, column, run of t-rows): a
-// column is one brick of one z plane, so one item walks a column through t
-// and reuses each t neighbour from L1/L2 right after loading it.  Each XCD
-// has its own queue (ticket counter) holding the columns c with c % 8 equal
-// to its id, read from the XCC_ID hardware register; a block drains its own
-// XCD's queue first and then takes items from the other queues, so the load
-// still balances.  Which queue a block uses only affects speed.
+// The persistent launch walks through phases, one per APE step.  Within a
+// phase the work items are runs of 64-site groups of one lattice.  A
+// lattice's groups form a (column, t-row) grid, a column being one brick (or
+// run of 64 sites) of one z plane; its columns are split into 8 contiguous
+// ranges, one per XCD, and XCD x's queue (ticket counter) walks its range
+// t-row by t-row, so a group's x, y and z neighbours are queued a few items
+// away and its t neighbours one range further, all on the XCD whose L2 holds
+// them (the slab walk of the single-lattice step, per lattice).  A block
+// reads its XCD from the XCC_ID hardware register, drains its own queue first
+// and then takes items from the other queues, so the load still balances;
+// which queue a block uses only affects speed.
 //
 // When a block finds every queue of the phase empty it publishes how many
 // items it finished (one release) and waits until the phase's completion
@@ -19,6 +21,13 @@
 // per item, matters on the multi-XCD MI355X: an agent-scope acquire
 // invalidates the XCD's L2.  Every wait is bounded; on timeout the block
 // records the failure in the status word and leaves, so the grid drains.
+//
+// The plaquettes of the outputs follow as two ordinary launches (the traces
+// of every group of every lattice, then one reducing block per lattice) with
+// exactly the arithmetic of the single-lattice path: the FP64 products of the
+// standalone plaquette for FP32 links, the owned-plane traces of the FP64
+// step for FP64 links.  Keeping them out of the persistent kernel keeps its
+// register budget that of the step alone.
 #include "ape_device.hpp"
 #include "qdpx_impl.hpp"
 #include "reduce_device.hpp"
@@ -33,29 +42,12 @@ __global__ void __launch_bounds__(256) k_batched_init(unsigned *__restrict__ cou
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) counters[i] = 0u;
 }
 
-// Reduce lattice L's plaquette partials exactly as the two finalisation
-// kernels of the single-lattice path do.
-__device__ void batched_finalize(const BatchLat &L, double *out, double *lds, double (*stage)[kBatchMaxStage]) {
-    const int n = 4 * L.ngroups;
-    const int nb = (n + kFinPerBlock - 1) / kFinPerBlock;
-    double res[2];
-    for (int comp = 0; comp < 2; ++comp) {
-        for (int b = 0; b < nb; ++b) {
-            const double v = fin_stage_a(L.partials + (int64_t)comp * n, n, b, lds);
-            if (threadIdx.x == 0) stage[comp][b] = v;
-        }
-        __syncthreads();
-        res[comp] = fin_stage_b(stage[comp], nb, lds);
-    }
-    if (threadIdx.x == 0) fin_write(res, 1, (double)L.g.V, out);
-}
-
 // XCD this block runs on (XCC_ID hardware register, bits 3:0).
 __device__ __forceinline__ int xcd_id() {
     return (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kXcds - 1));
 }
 
-// Take the next ticket of queue q (thread 0), broadcast it to the block.
+// Take the next ticket of counter (thread 0) and broadcast it to the block.
 __device__ __forceinline__ unsigned take_ticket(unsigned *counter, unsigned *s_ticket) {
     if (threadIdx.x == 0) *s_ticket = atomicAdd(counter, 1u);
     __syncthreads();
@@ -64,78 +56,73 @@ __device__ __forceinline__ unsigned take_ticket(unsigned *counter, unsigned *s_t
     return r;
 }
 
+// Lattice whose entry base(q) is the last one <= r (bases ascending).
+template <typename F> __device__ __forceinline__ int find_lattice(int n_lat, int r, F base) {
+    int lo = 0, hi = n_lat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base(mid) <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // The lattice table comes as its own const __restrict__ argument: the compiler
 // may then read it (at wave-uniform indices) with scalar loads, as the
 // single-lattice kernels read their geometry from the kernel arguments.
-template <typename R, int NR>
-__global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat *__restrict__ lats) {
+// GPB 64-site groups are processed at once per block (4 waves each).
+template <typename R, int NR, int GPB>
+__global__ void __launch_bounds__(256 * GPB) k_ape_batched(BatchArgs a, const BatchLat *__restrict__ lats) {
     __shared__ unsigned s_ticket;
     __shared__ int s_ok;
-    __shared__ double lds[kReduceBlock / 64];
-    __shared__ double stage[2][kBatchMaxStage];
-    __shared__ nv4_t<R> own[sizeof(R) == 4 ? 4 * 3 * 64 : 1];  // the group's own links (FP32)
+    __shared__ nv4_t<R> own[GPB][sizeof(R) == 4 ? 4 * 3 * 64 : 1];  // each group's own links (FP32)
     // mu is wave-uniform; readfirstlane lets the compiler keep it in an SGPR
-    const int mu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int mu = w & 3, half = w >> 2;
     const int xid = __builtin_amdgcn_readfirstlane(xcd_id());
-    const int nph = a.n_phases + (a.plaq ? 1 : 0);  // steps, plaquette traces, finalisation
+    const int nph = a.n_steps;
     unsigned *status = a.counters + 1;
     unsigned *tickets = a.counters + 2;             // [nph][kXcds]
     unsigned *done = a.counters + 2 + nph * kXcds;  // [nph]
+    const int per_ticket = a.group_chunk;           // groups per ticket
     for (int phase = 0; phase < nph; ++phase) {
-        const bool fin = a.plaq && phase == nph - 1;
         unsigned mine = 0;
-        if (fin) {
+        // step p reads the output of step p-1: step k writes to U_out when
+        // n_steps-1-k is even, else to the lattice's scratch links
+        const int src_odd = (a.n_steps - phase) & 1, dst_odd = (a.n_steps - 1 - phase) & 1;
+        for (int k = 0; k < kXcds; ++k) {
+            const int q = (xid + k) & (kXcds - 1);  // own queue first, then the others
             for (;;) {
-                const unsigned r = take_ticket(tickets + phase * kXcds, &s_ticket);
-                if (r >= (unsigned)a.n_lat) break;
+                const unsigned r = take_ticket(tickets + phase * kXcds + q, &s_ticket);
+                if (r >= (unsigned)a.xtotal[q]) break;
                 ++mine;
-                batched_finalize(lats[r], a.plaq + 3 * r, lds, stage);
-            }
-        } else {
-            // step p reads the output of step p-1: step k writes to U_out when
-            // n_steps-1-k is even, else to the lattice's scratch links
-            const bool ape = phase < a.n_steps;
-            const int src_odd = (a.n_steps - phase) & 1, dst_odd = (a.n_steps - 1 - phase) & 1;
-            for (int k = 0; k < kXcds; ++k) {
-                const int q = (xid + k) & (kXcds - 1);  // own queue first, then the others
-                for (;;) {
-                    const unsigned r = take_ticket(tickets + phase * kXcds + q, &s_ticket);
-                    if (r >= (unsigned)a.xtotal[q]) break;
-                    ++mine;
-                    int lo = 0, hi = a.n_lat - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (lats[mid].xbase[q] <= (int)r) lo = mid;
-                        else hi = mid - 1;
+                const BatchLat &L =
+                    lats[find_lattice(a.n_lat, (int)r, [&](int i) { return lats[i].xbase[q]; })];  // read in place
+                const int ncols = L.xcol1[q] - L.xcol0[q];
+                const int j0 = ((int)r - L.xbase[q]) * per_ticket;
+                const int j1 = min(j0 + per_ticket, ncols * L.nrow);
+                const void *src = (phase == 0) ? L.in : (src_odd == 0 ? L.out : L.tmp);
+                void *dst = dst_odd == 0 ? L.out : L.tmp;
+                const LinksRO<R, NR> U{(const vec2_t<R> *)src, L.g.S};
+                const LinksWO<R, NR> O{(vec2_t<R> *)dst, L.g.S};
+                // GPB groups at a time, half h of the block taking j0 + h, ...
+                // (no early exit: every wave meets every barrier)
+#pragma unroll 1
+                for (int jj = j0; jj < j1; jj += GPB) {
+                    const int j = jj + half;
+                    const bool valid = j < j1;
+                    int grp = 0;
+                    if (valid) {
+                        const int row = L.dcols[q].div(j);
+                        grp = (L.xcol0[q] + (j - row * ncols)) + L.ncol * row;
                     }
-                    const BatchLat &L = lats[lo];  // read in place: a private copy would live in scratch
-                    const int rr = (int)r - L.xbase[q];
-                    const int col = q + kXcds * (rr / L.nchunk);
-                    const int row0 = (rr % L.nchunk) * a.group_chunk;
-                    const int row1 = min(row0 + a.group_chunk, L.nrow);
-                    const void *src = (phase == 0) ? L.in : (src_odd == 0 ? L.out : L.tmp);
-                    void *dst = ape ? (dst_odd == 0 ? L.out : L.tmp) : nullptr;
-                    const LinksRO<R, NR> U{(const vec2_t<R> *)src, L.g.S};
-                    const LinksWO<R, NR> O{(vec2_t<R> *)dst, L.g.S};
-                    if (ape) {
-#pragma unroll 1
-                        for (int row = row0; row < row1; ++row) {
-                            const int grp = col + L.ncol * row;
-                            if constexpr (sizeof(R) == 4) {  // own links staged in LDS, as the single-lattice step
-                                // (take_ticket's barriers separate items; rows of one item need their own)
-                                if (row > row0) __syncthreads();
-                                stage_own_link(L.g, U, grp, mu, lane, own);
-                                __syncthreads();
-                                ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, own);
-                            } else {
-                                ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane);
-                            }
-                        }
+                    if constexpr (sizeof(R) == 4) {  // own links staged in LDS, as the single-lattice step
+                        if (jj > j0) __syncthreads();  // take_ticket's barriers separate items
+                        if (valid) stage_own_link(L.g, U, grp, mu, lane, own[half]);
+                        __syncthreads();
+                        if (valid) ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, own[half]);
                     } else {
-#pragma unroll 1
-                        for (int row = row0; row < row1; ++row)
-                            ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, 0xFu, L.partials, col + L.ncol * row, mu,
-                                                        lane);
+                        if (valid) ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane);
                     }
                 }
             }
@@ -144,7 +131,7 @@ __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat
         const unsigned nitems = (unsigned)a.items_per_phase;
         __syncthreads();  // every wave of the block has issued its stores
         if (threadIdx.x == 0) {
-            __threadfence();  // release this block's links / partials of the phase device-wide
+            __threadfence();  // release this block's links of the phase device-wide
             atomicAdd(done + phase, mine);
             unsigned spins = 0;
             int ok = 1;
@@ -164,16 +151,74 @@ __global__ void __launch_bounds__(256) k_ape_batched(BatchArgs a, const BatchLat
     }
 }
 
+// Plaquette traces of every lattice's output links into its partials, the
+// single-lattice arithmetic and partial layout: FP32 links as k_plaquette
+// (four groups per block, one per wave, partials[grp] and [ngroups + grp]);
+// FP64 links as the APE kernel's plaquette-only mode (one group per block,
+// one direction per wave, four partials per group).
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_batched_plaq(BatchArgs a, const BatchLat *__restrict__ lats) {
+    const int b = blockIdx.x;
+    const BatchLat &L = lats[find_lattice(a.n_lat, b, [&](int i) { return lats[i].pbase; })];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const LinksRO<R, NR> U{(const vec2_t<R> *)L.out, L.g.S};
+    if constexpr (sizeof(R) == 4) {
+        const int grp = (b - L.pbase) * 4 + w;
+        if (grp >= L.ngroups) return;
+        double sp = 0.0, tp = 0.0;
+        Site x;
+        if (group_site(L.g, grp, lane, x)) plaquette_site(L.g, U, x, sp, tp);
+        sp = wave_sum(sp);
+        tp = wave_sum(tp);
+        if (lane == 0) {
+            L.partials[grp] = sp;
+            L.partials[L.ngroups + grp] = tp;
+        }
+    } else {
+        const LinksWO<R, NR> O{nullptr, L.g.S};
+        ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, 0xFu, L.partials, b - L.pbase, w, lane);
+    }
+}
+
+// One block per lattice: its partials reduced exactly as the two
+// finalisation kernels of the single-lattice path do.
+__global__ void __launch_bounds__(kReduceBlock) k_batched_fin(const BatchLat *__restrict__ lats, int per_group,
+                                                             double *__restrict__ plaq) {
+    __shared__ double lds[kReduceBlock / 64];
+    __shared__ double stage[2][kBatchMaxStage];
+    const BatchLat &L = lats[blockIdx.x];
+    const int n = per_group * L.ngroups;
+    const int nb = (n + kFinPerBlock - 1) / kFinPerBlock;
+    double res[2];
+    for (int comp = 0; comp < 2; ++comp) {
+        for (int b = 0; b < nb; ++b) {
+            const double v = fin_stage_a(L.partials + (int64_t)comp * n, n, b, lds);
+            if (threadIdx.x == 0) stage[comp][b] = v;
+        }
+        __syncthreads();
+        res[comp] = fin_stage_b(stage[comp], nb, lds);
+    }
+    if (threadIdx.x == 0) fin_write(res, 1, (double)L.g.V, plaq + 3 * blockIdx.x);
+}
+
 int batched_max_stage_groups() { return kBatchMaxStage * kFinPerBlock / 4; }
 
-int batched_resident_blocks(int prec, int nrows) {
+int batched_plaq_blocks(int prec, int ngroups) { return prec == 0 ? ngroups : (ngroups + 3) / 4; }
+
+template <typename R, int NR> static hipError_t resident(int gpb, int *per_cu) {
+    if (gpb == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ape_batched<R, NR, 2>, 512, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ape_batched<R, NR, 1>, 256, 0);
+}
+
+int batched_resident_blocks(int prec, int nrows, int block) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int gpb = block / 256;
     hipError_t e;
-    if (prec == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ape_batched<double, 3>, 256, 0);
-    else if (nrows == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ape_batched<float, 3>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ape_batched<float, 2>, 256, 0);
+    if (prec == 0) e = resident<double, 3>(gpb, &per_cu);
+    else if (nrows == 3) e = resident<float, 3>(gpb, &per_cu);
+    else e = resident<float, 2>(gpb, &per_cu);
     // (the occupancy does not depend on the kernel's arguments)
     if (e != hipSuccess) return 0;
     return cus * std::max(per_cu, 1);
@@ -181,12 +226,22 @@ int batched_resident_blocks(int prec, int nrows) {
 
 int batched_counter_words(int max_phases) { return 2 + (kXcds + 1) * (max_phases + 1); }
 
-hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int grid, hipStream_t st) {
-    const int ncount = batched_counter_words(a.n_phases);
+template <typename R, int NR>
+static void launch_all(const BatchArgs &a, int block, int grid, hipStream_t st) {
+    if (block == 512) k_ape_batched<R, NR, 2><<<grid, 512, 0, st>>>(a, a.lats);
+    else k_ape_batched<R, NR, 1><<<grid, 256, 0, st>>>(a, a.lats);
+    if (a.plaq) {
+        k_batched_plaq<R, NR><<<a.plaq_blocks, 256, 0, st>>>(a, a.lats);
+        k_batched_fin<<<a.n_lat, kReduceBlock, 0, st>>>(a.lats, sizeof(R) == 4 ? 1 : 4, a.plaq);
+    }
+}
+
+hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int block, int grid, hipStream_t st) {
+    const int ncount = batched_counter_words(a.n_steps);
     k_batched_init<<<std::min((ncount + 255) / 256, 1024), 256, 0, st>>>(a.counters, ncount);
-    if (prec == 0) k_ape_batched<double, 3><<<grid, 256, 0, st>>>(a, a.lats);
-    else if (nrows == 3) k_ape_batched<float, 3><<<grid, 256, 0, st>>>(a, a.lats);
-    else k_ape_batched<float, 2><<<grid, 256, 0, st>>>(a, a.lats);
+    if (prec == 0) launch_all<double, 3>(a, block, grid, st);
+    else if (nrows == 3) launch_all<float, 3>(a, block, grid, st);
+    else launch_all<float, 2>(a, block, grid, st);
     return hipGetLastError();
 }
 

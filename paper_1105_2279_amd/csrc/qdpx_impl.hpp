@@ -85,9 +85,10 @@ constexpr int kXcds = 8;
 
 // One lattice of a batch (device table entry).  Its 64-site groups form a
 // (column, t-row) grid, group = col + ncol * row, where a column is one
-// brick (or run of groups) of one z plane and rows step in t; see
-// batch_columns() on the host.  Column c belongs to the queue of XCD c % 8,
-// so a column's t neighbours are always handled, and cached, on one XCD.
+// brick (or run of groups) of one z plane and rows step in t.  The columns
+// are split into 8 contiguous ranges [xcol0[x], xcol1[x]), one per XCD
+// queue; queue x walks its range t-row by t-row (group j of the queue is
+// row j / cols, column xcol0 + j % cols), in tickets of group_chunk groups.
 struct BatchLat {
     Geo g;
     const void *in;    // caller's input links
@@ -96,8 +97,10 @@ struct BatchLat {
     double *partials;  // 2 * 4 * ngroups plaquette partials in the workspace
     int ngroups;       // 64-site groups
     int ncol, nrow;    // group grid
-    int nchunk;        // items per column (rows per item = group_chunk)
-    int xbase[kXcds];  // first item of this lattice in each XCD's queue
+    int xcol0[kXcds], xcol1[kXcds];  // each XCD queue's column range
+    FastDiv dcols[kXcds];            // division by the range's width
+    int xbase[kXcds];  // first ticket of this lattice in each XCD's queue
+    int pbase;         // first block of this lattice in the plaquette launch
 };
 
 struct BatchArgs {
@@ -105,15 +108,18 @@ struct BatchArgs {
     unsigned *counters;    // [1] status, then per phase 8 ticket counters and a completion counter
     double *plaq;          // nullable, [n_lat][3]
     double c1, c2;
-    int n_lat, n_steps, n_phases, group_chunk;
-    int xtotal[kXcds];     // items in each XCD's queue per phase
+    int n_lat, n_steps, group_chunk;
+    int xtotal[kXcds];     // tickets in each XCD's queue per phase
     int items_per_phase;   // sum of xtotal
+    int plaq_blocks;       // blocks of the plaquette launch
     unsigned spin_limit;
 };
 
 int batched_max_stage_groups();
 int batched_counter_words(int max_phases);
-int batched_resident_blocks(int prec, int nrows);
-hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int grid, hipStream_t st);
+int batched_plaq_blocks(int prec, int ngroups);
+// resident blocks of the persistent kernel with `block` (256 or 512) threads
+int batched_resident_blocks(int prec, int nrows, int block);
+hipError_t launch_ape_batched(const BatchArgs &a, int prec, int nrows, int block, int grid, hipStream_t st);
 
 }  // namespace qdpx

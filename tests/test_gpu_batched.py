@@ -74,13 +74,14 @@ def test_batched_bit_identical_to_single(prec, fmt, n):
     assert np.max(np.abs(plaq[6:9].cpu().numpy() - oracle.plaquette(Vref))) < tol
 
 
+@pytest.mark.parametrize("block", [256, 512])
 @pytest.mark.parametrize("chunk", [1, 3, 64])
-def test_batched_group_chunk_does_not_change_results(chunk):
+def test_batched_geometry_does_not_change_results(block, chunk):
     c = q.Context(0)
     prec, fmt = q.F32, q.LINK12
     Uds = [q.links_to_device(c, L, latgen.haar_links(L, 200 + i), prec, fmt, dev()) for i, L in enumerate(MIXED)]
     ref_outs, ref_plaq, _ = run_batched(c, MIXED, Uds, prec, fmt, 2)
-    q.qdpx_tune_set(c, q.OP_BATCHED, MIXED[0], prec, fmt, 256, chunk, 0)
+    q.qdpx_tune_set(c, q.OP_BATCHED, MIXED[0], prec, fmt, block, chunk, 1)
     outs, plaq, work = run_batched(c, MIXED, Uds, prec, fmt, 2)
     torch.cuda.synchronize()
     assert status_of(work) == 0
@@ -88,6 +89,31 @@ def test_batched_group_chunk_does_not_change_results(chunk):
         assert same_links(c, L, a, b, prec, fmt)
     assert torch.equal(plaq, ref_plaq)
     c.close()
+
+
+@pytest.mark.parametrize("prec,fmt", [(q.F64, q.LINK18), (q.F32, q.LINK12)], ids=["f64_18", "f32_12"])
+def test_batched_autotuner(prec, fmt, tmp_path):
+    """qdpx_tune_batched picks a geometry on the batch itself, writes it to
+    the context's launch table, and the tuned batch gives the same bits."""
+    table = str(tmp_path / "table.json")
+    c = q.Context(0, tune_cache=table)
+    Uds = [q.links_to_device(c, L, latgen.haar_links(L, 250 + i), prec, fmt, dev()) for i, L in enumerate(MIXED)]
+    ref_outs, ref_plaq, _ = run_batched(c, MIXED, Uds, prec, fmt, 2)
+    q.qdpx_tune_batched(c, MIXED, prec, fmt, 2)
+    assert q.qdpx_tune_source(c, q.OP_BATCHED, MIXED[0], prec, fmt) == "tuned"
+    block, chunk, _, _ = q.qdpx_tune_get(c, q.OP_BATCHED, MIXED[0], prec, fmt)
+    assert block in (256, 512) and chunk in (1, 2, 4, 8)
+    outs, plaq, work = run_batched(c, MIXED, Uds, prec, fmt, 2)
+    torch.cuda.synchronize()
+    assert status_of(work) == 0
+    for L, a, b in zip(MIXED, outs, ref_outs):
+        assert same_links(c, L, a, b, prec, fmt)
+    assert torch.equal(plaq, ref_plaq)
+    c.close()
+    c2 = q.Context(0, tune_cache=table)
+    assert q.qdpx_tune_get(c2, q.OP_BATCHED, MIXED[0], prec, fmt) == (block, chunk, 1, 1)
+    assert q.qdpx_tune_source(c2, q.OP_BATCHED, MIXED[0], prec, fmt) == "table"
+    c2.close()
 
 
 def test_batched_graph_replay():

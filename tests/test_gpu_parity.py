@@ -175,6 +175,39 @@ def test_degenerate_w_gives_nan(prec, fmt):
     assert link_err(V[~bad], Vref[~bad]) < tol(prec)
 
 
+@pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
+def test_step_plaquettes_are_the_fp64_plaquette_of_the_links(prec, fmt):
+    """The plaquettes qdpx_ape_smear reports for its input and for every
+    step's output are the FP64 plaquette (qdpx_plaquette) of those links:
+    the same values bit for bit for FP32 links, to FP64 rounding for FP64
+    links (whose per-step traces are fused into the step kernel)."""
+    L = (16, 8, 8, 8)
+    U = latgen.haar_links(L, 71)
+    c = ctx()
+    cur = q.links_to_device(c, L, U, prec, fmt, dev())
+    work_p = q.alloc_workspace(q.OP_PLAQ, L, prec, fmt, 1, dev())
+    n = 3
+    full = torch.zeros(3 * (n + 1), dtype=torch.float64, device=dev())
+    out = q.alloc_links(L, prec, fmt, dev())
+    q.qdpx_ape_smear(c, L, prec, fmt, cur, out, 0.5, n, full, q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev()))
+    ref = []
+    for k in range(n + 1):  # plaquette of the input, then of each step's output
+        p = torch.zeros(3, dtype=torch.float64, device=dev())
+        q.qdpx_plaquette(c, L, prec, fmt, cur, p, work_p)
+        ref.append(p)
+        if k < n:
+            nxt = q.alloc_links(L, prec, fmt, dev())
+            q.qdpx_ape_smear(c, L, prec, fmt, cur, nxt, 0.5, 1, None, q.alloc_workspace(q.OP_APE, L, prec, fmt, 1,
+                                                                                           dev()))
+            cur = nxt
+    ref = torch.cat(ref)
+    torch.cuda.synchronize()
+    if prec == q.F32:
+        assert torch.equal(full, ref), (full - ref).abs().max()
+    else:
+        assert float((full - ref).abs().max()) < 1e-14
+
+
 def test_plaquette_unit_links_exact():
     L = (4, 4, 4, 8)
     for prec, fmt in FORMATS:
