@@ -43,12 +43,16 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
         }
         return;
     }
+    // FP64 steps exchange each lane's backward link through LDS (one
+    // kF64BackPerWave region per wave, sized at launch)
+    extern __shared__ double2 back64[];
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
         const int grp = xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
-        ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane);
+        ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, nullptr,
+                                     back64 + w * kF64BackPerWave);
     }
 }
 
@@ -65,10 +69,11 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     const int per_block = gpb * cfg.nsite;
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
-#define QDPX_APE_LAUNCH(R, NR, NS, M, P)                                                                       \
-    k_ape_step<R, NR, NS, M, P><<<grid, cfg.block, 0, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},     \
-                                                         LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2, mask,  \
-                                                         partials, xcd, cfg.tw)
+    const size_t lds64 = (prec == 0 && !proj) ? sizeof(double2) * kF64BackPerWave * (cfg.block / 64) : 0;
+#define QDPX_APE_LAUNCH(R, NR, NS, M, P)                                                                        \
+    k_ape_step<R, NR, NS, M, P><<<grid, cfg.block, lds64, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},  \
+                                                             LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,     \
+                                                             mask, partials, xcd, cfg.tw)
 #define QDPX_APE_M64(NS)                                                       \
     if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1);                         \
     else if (mode == kPlaqOnly) QDPX_APE_LAUNCH(double, 3, NS, kPlaqOnly, 0);  \

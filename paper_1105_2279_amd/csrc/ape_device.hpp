@@ -428,7 +428,253 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
     return plq;
 }
 
-// One wave's share of a step: direction mu of the 64 sites of group grp.
+// ------------------------------------------------------------- FP64 step
+// The FP64 step puts the four directions of 16 sites in one wave: lane L of
+// the group's wave w handles site 16 w + (L & 15) of the group (group_site's
+// lane index) and direction mu = L >> 4.  In phase p = 0, 1, 2 the lane forms
+// the two staples of plane nu = mu ^ (p + 1) while its partner lane
+// L ^ 16 (p + 1) (same site, direction nu) forms those of plane mu.  The two
+// upper staples U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag and U_mu(x) U_nu(x+mu)
+// U_mu(x+nu)^dag are made of the same four links, so each lane loads one
+// neighbour link, U_mu(x+nu), and takes U_nu(x+mu) and rows 0 and 1 of
+// U_nu(x) from its partner by cross-lane exchange; the lower staple's
+// U_nu(x-nu) is the partner's backward link, which every lane loads once
+// and shares through LDS.  A link update then issues 96 vector loads of 16
+// bytes instead of 151: the vector-memory pipeline, not the arithmetic,
+// bounds the FP64 step.  The fused plaquette takes each plane once, in the
+// lane of its lower direction.  Direction-dependent addresses differ
+// between lanes here, so they are formed in 64 bits per lane.
+
+constexpr int kF64BackPerWave = 9 * 64;  // double2 per wave: one backward link per lane
+
+__device__ __forceinline__ int sel4(int i, int a, int b, int c, int d) {
+    return i == 0 ? a : i == 1 ? b : i == 2 ? c : d;
+}
+// x +- mu for a per-lane mu (selects instead of indexing the geometry)
+__device__ __forceinline__ int hop_fwd_v(const Geo &g, int s, int cmu, int mu) {
+    const int L = sel4(mu, g.L[0], g.L[1], g.L[2], g.L[3]), st = sel4(mu, g.st[0], g.st[1], g.st[2], g.st[3]);
+    return (cmu == L - 1) ? s - (L - 1) * st : s + st;
+}
+__device__ __forceinline__ int hop_bwd_v(const Geo &g, int s, int cmu, int mu) {
+    const int L = sel4(mu, g.L[0], g.L[1], g.L[2], g.L[3]), st = sel4(mu, g.st[0], g.st[1], g.st[2], g.st[3]);
+    return (cmu == 0) ? s + (L - 1) * st : s - st;
+}
+
+// Element c of the FP64 link at site s of a direction whose array starts at
+// the per-lane pointer dir (U.p + mu * 9 * S): the element offset c * S is
+// wave-uniform, the site offset per lane.
+__device__ __forceinline__ Cx<double> ld_lane(const double2 *dir, int64_t S, int c, int s) {
+    const nv2_t<double> v = *gptr<nv2_t<double>>(dir + (c * S + s));
+    return Cx<double>{v.x, v.y};
+}
+__device__ __forceinline__ void st_lane(double2 *dir, int64_t S, int c, int s, const Cx<double> &z) {
+    store_stream<double>((void *)(dir + (c * S + s)), z.re, z.im);
+}
+__device__ __forceinline__ Cx<double> xchg(const Cx<double> &z, int m) {
+    return Cx<double>{__shfl_xor(z.re, m, 64), __shfl_xor(z.im, m, 64)};
+}
+
+// One wave's share of an FP64 step (modes as ape_group): the four directions
+// of 16 sites of group grp.  back: this wave's kF64BackPerWave LDS entries.
+// Partials (plaquette modes): partials[grp*4 + w] (spatial planes) and
+// partials[4*ngroups + grp*4 + w] (temporal planes) of the INPUT links.
+template <int MODE>
+__device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double, 3> &U, const LinksWO<double, 3> &out,
+                                              double c1, double c2, unsigned mask, double *__restrict__ partials,
+                                              int grp, int w, int lane, double2 *back) {
+    const int ngroups = num_groups(g);
+    const int mu = lane >> 4;
+    Site x;
+    const bool live = group_site(g, grp, 16 * w + (lane & 15), x);
+    if (!live) x.init(g, 0);  // padding lanes load from site 0 and store nothing
+    const int s = x.s;
+    const int cmu = coord(x, mu);
+    const bool smear = MODE == kPlaqOnly || ((mask >> mu) & 1u);
+    const int64_t S9 = 9 * U.S;
+    const double2 *dmu = U.p + mu * S9;  // this lane's direction
+    if constexpr (MODE != kPlaqOnly) {
+        // the backward link U_mu(x-mu), read by the lanes of the other directions
+        const int sb = hop_bwd_v(g, s, cmu, mu);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const Cx<double> z = ld_lane(dmu, U.S, c, sb);
+            back[c * 64 + lane] = double2{z.re, z.im};
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    Cx<double> S[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S[i][j] = Cx<double>{0.0, 0.0};
+    double sp = 0.0, tp = 0.0;
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) {
+        const int xm = 16 * (p + 1);
+        const int nu = mu ^ (p + 1);
+        // plane (mu, nu) is smeared for this lane exactly when it is for the
+        // partner (both directions in the mask)
+        const bool act = smear && (MODE == kPlaqOnly || ((mask >> nu) & 1u));
+        const bool own_plane = mu < nu;  // the plaquette of the plane is taken here
+        const int cnu = coord(x, nu);
+        // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag.  B = U_mu(x+nu) is loaded by
+        // every lane (the partner needs it); rows of U_nu(x) (the partner's
+        // own rows) and of U_nu(x+mu) (the partner's B) are exchanged one at
+        // a time as the products consume them.
+        M3<double> B;
+        const int s_nu = hop_fwd_v(g, s, cnu, nu);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) B.e[c / 3][c % 3] = ld_lane(dmu, U.S, c, s_nu);
+        const double2 *dnu = U.p + nu * S9;
+        Cx<double> T[2][3];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            Cx<double> a[3];  // row i of U_nu(x)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a[k] = ld_lane(dnu, U.S, 3 * i + k, s);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                Cx<double> t{0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cmac(t, a[k], B.e[k][j]);
+                T[i][j] = t;
+            }
+        }
+        // X = T U_nu(x+mu)^dag: X_ij = sum_k T_ik conj(C_jk), C row j from the
+        // partner; every upper staple is formed on its own and then added, so
+        // the smeared link does not depend on whether the plaquette is taken.
+        Cx<double> X[2][3];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) X[i][j] = Cx<double>{0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<double> cj[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cj[k] = xchg(B.e[j][k], xm);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cmac_cb(X[i][j], T[i][k], cj[k]);
+        }
+        if (act) {
+            if constexpr (MODE != kApe) {
+                if (own_plane) {
+                    M23<double> uu, xx;  // rows 0 and 1 of U_mu(x) and of X
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            uu.e[i][j] = ld_lane(dmu, U.S, 3 * i + j, s);
+                            xx.e[i][j] = X[i][j];
+                        }
+                    const double pl = retrace_rows01(uu, xx);
+                    if (nu == 3) tp += pl;
+                    else sp += pl;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    S[i][j].re += X[i][j].re;
+                    S[i][j].im += X[i][j].im;
+                }
+        }
+        if constexpr (MODE != kPlaqOnly) {
+            // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu, by rows k:
+            // T2_ij = sum_k conj(LA_ki) LB_kj with LA = U_nu(x-nu), the
+            // partner's backward link (columns 0 and 1 from LDS), then
+            // S_ij += sum_k T2_ik LC_kj
+            __builtin_amdgcn_sched_barrier(0);  // the lower staple's loads stay below the upper one
+            if (act) {
+                const int sy = hop_bwd_v(g, s, cnu, nu);
+                const int syf = hop_fwd_v(g, sy, cmu, mu);  // y has the same mu-coordinate as x
+                Cx<double> T2[2][3];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) T2[i][j] = Cx<double>{0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Cx<double> la[2], lb[3];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const double2 v = back[(3 * k + i) * 64 + (lane ^ xm)];
+                        la[i] = Cx<double>{v.x, v.y};
+                    }
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) lb[j] = ld_lane(dmu, U.S, 3 * k + j, sy);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) cmac_ca(T2[i][j], la[i], lb[j]);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Cx<double> lc[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) lc[j] = ld_lane(dnu, U.S, 3 * k + j, syf);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) cmac(S[i][j], T2[i][k], lc[j]);
+                }
+            }
+        }
+    }
+    if constexpr (MODE != kPlaqOnly) {
+        // the next group's backward links overwrite these: every lane has read
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (live) {
+            double2 *omu = out.p + mu * S9;
+            Cx<double> u0[2][3];  // rows 0 and 1 of U_mu(x)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) u0[a][b] = ld_lane(dmu, U.S, 3 * a + b, s);
+            if (!smear) {  // a direction outside the mask is copied
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) st_lane(omu, out.S, 3 * a + b, s, u0[a][b]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) st_lane(omu, out.S, 6 + b, s, ld_lane(dmu, U.S, 6 + b, s));
+            } else {
+                Cx<double> wm[2][3], v[3][3];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        wm[i][j].re = fma(c2, S[i][j].re, c1 * u0[i][j].re);
+                        wm[i][j].im = fma(c2, S[i][j].im, c1 * u0[i][j].im);
+                    }
+                reunitarise(wm, v);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) st_lane(omu, out.S, 3 * a + b, s, v[a][b]);
+            }
+        }
+    }
+    if constexpr (MODE != kApe) {
+        if (!live) sp = tp = 0.0;
+        sp = wave_sum(sp);
+        tp = wave_sum(tp);
+        if (lane == 0) {
+            partials[grp * 4 + w] = sp;
+            partials[4 * ngroups + grp * 4 + w] = tp;
+        }
+    }
+}
+
+// One wave's share of a step: direction mu of the 64 sites of group grp
+// (FP64 with the row projection: ape_group_f64, wave mu of the group).
 // Writes the smeared links (modes kApe, kApePlaq; a direction outside mask
 // is copied unchanged, mask is 0xF in kApePlaq) and, in the plaquette
 // modes, the owned planes' trace sum of the INPUT links for (grp, mu):
@@ -438,8 +684,14 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
 template <typename R, int NR, int MODE, int PROJ = 0>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
                                           double c2, unsigned mask, double *__restrict__ partials, int grp, int mu,
-                                          int lane, const nv4_t<R> *own = nullptr) {
+                                          int lane, const nv4_t<R> *own = nullptr, double2 *back64 = nullptr) {
     static_assert(PROJ == 0 || MODE == kApe, "the polar projection runs without the fused plaquette");
+    if constexpr (sizeof(R) == 8 && PROJ == 0) {
+        // FP64 with the row projection: four directions per wave (mu is
+        // then the wave's index within the group)
+        ape_group_f64<MODE>(g, U, out, c1, c2, mask, partials, grp, mu, lane, back64);
+        return;
+    }
     const int ngroups = num_groups(g);
     double p = 0.0;
     Site x;

@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(256 * GPB) k_ape_batched(BatchArgs a, const Ba
     __shared__ unsigned s_ticket;
     __shared__ int s_ok;
     __shared__ nv4_t<R> own[GPB][sizeof(R) == 4 ? 4 * 3 * 64 : 1];  // each group's own links (FP32)
+    __shared__ double2 back64[sizeof(R) == 8 ? 4 * GPB * kF64BackPerWave : 1];  // FP64: backward links
     // mu is wave-uniform; readfirstlane lets the compiler keep it in an SGPR
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int mu = w & 3, half = w >> 2;
@@ -122,7 +123,9 @@ __global__ void __launch_bounds__(256 * GPB) k_ape_batched(BatchArgs a, const Ba
                         __syncthreads();
                         if (valid) ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, own[half]);
                     } else {
-                        if (valid) ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane);
+                        if (valid)
+                            ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, nullptr,
+                                                   back64 + w * kF64BackPerWave);
                     }
                 }
             }
