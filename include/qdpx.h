@@ -195,6 +195,20 @@ int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pre
                              const void *U, const void *psi, const void *phi, double a, uint32_t dir_mask,
                              int sign, void *chi, double *norm2, void *work, size_t work_bytes, void *stream);
 
+/* The shift expression above for callers that cannot allocate or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels, with the |chi|^2 partials in a
+ * scratch array of fixed size that the library keeps in every device's
+ * memory for the life of the process (4 MiB per device).  Arguments as for
+ * qdpx_eval_shift_mul_axpy without work/work_bytes.  Lattices of more than
+ * 2^25 sites are refused with QDPX_EINVAL.  Allocates nothing and issues no
+ * memset.  Every call on one device shares that device's array: calls that
+ * may overlap on one device (other streams, other host threads) race and
+ * must be serialised by the caller. */
+int qdpx_eval_shift_mul_axpy_noalloc(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
+                                     const void *U, const void *psi, const void *phi, double a, uint32_t dir_mask,
+                                     int sign, void *chi, double *norm2, void *stream);
+
 /* ------------------------------------------------------- expression chain
  * n_iter repetitions of  chi_k = sum_mu U_mu(x) psi_{k-1}(x+mu) + a*phi(x);
  *                        psi_k = psi_{k-1} - c * chi_k

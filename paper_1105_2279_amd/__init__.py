@@ -41,6 +41,7 @@ EXPORTS = (
     "qdpx_eval_shift_mul_axpy", "qdpx_shift_chain", "qdpx_ape_smear", "qdpx_plaquette",
     "qdpx_ape_smear_batched", "qdpx_tune", "qdpx_tune_get", "qdpx_tune_set",
     "qdpx_eval_hop", "qdpx_jacobi_smear", "qdpx_tune_save", "qdpx_tune_batched",
+    "qdpx_eval_shift_mul_axpy_noalloc",
     "qdpx_jit_generate", "qdpx_jit_compile", "qdpx_jit_info", "qdpx_jit_eval",
 )
 
@@ -96,6 +97,8 @@ def lib():
         "qdpx_unpack_fermion": (i32, [_P, _G, _P, i32, _P, _P]),
         "qdpx_eval_shift_mul_axpy": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, ctypes.c_uint32, i32, _P, _P, _P, sz,
                                            _P]),
+        "qdpx_eval_shift_mul_axpy_noalloc": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, ctypes.c_uint32, i32, _P, _P,
+                                                   _P]),
         "qdpx_shift_chain": (i32, [_P, _G, i32, i32, _P, _P, _P, dbl, dbl, i32, _P, _P, sz, _P]),
         "qdpx_ape_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, ctypes.c_uint32, i32, _P, _P, sz, _P]),
         "qdpx_plaquette": (i32, [_P, _G, i32, i32, _P, _P, _P, sz, _P]),
@@ -249,6 +252,13 @@ def qdpx_eval_shift_mul_axpy(ctx, L, prec, fmt, U, psi, phi, a, chi, norm2=None,
     _check(lib().qdpx_eval_shift_mul_axpy(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(psi),
                                           _ptr(phi), float(a), int(dir_mask), int(sign), _ptr(chi), _ptr(norm2),
                                           _ptr(work), _nbytes(work), _stream(stream)), "qdpx_eval_shift_mul_axpy")
+
+
+def qdpx_eval_shift_mul_axpy_noalloc(ctx, L, prec, fmt, U, psi, phi, a, chi, norm2=None, stream=None, dir_mask=0xF,
+                                     sign=1):
+    _check(lib().qdpx_eval_shift_mul_axpy_noalloc(ctx.handle, ctypes.byref(geom(L)), prec, fmt, _ptr(U), _ptr(psi),
+                                                  _ptr(phi), float(a), int(dir_mask), int(sign), _ptr(chi),
+                                                  _ptr(norm2), _stream(stream)), "qdpx_eval_shift_mul_axpy_noalloc")
 
 
 def qdpx_shift_chain(ctx, L, prec, fmt, U, psi, phi, a, c, n_iter, norms=None, work=None, stream=None):

@@ -80,6 +80,7 @@ struct qdpx_ctx {
     int device = 0;
     std::string arch;        // gcnArchName of the device
     std::string cache_path;  // launch-table file ("" = none)
+    double *scratch = nullptr;  // this device's copy of `scratch` (no-allocation entry point)
     std::map<TuneKey, Tuned> tuned;
     std::map<BatchKey, void *> batch_tables;  // device tables of batched calls
 };
@@ -103,6 +104,16 @@ static void log_cfg(const char *what, const TuneKey &k, const LaunchCfg &c) {
 }
 
 static bool cfg_valid(qdpx_op op, const LaunchCfg &c);
+
+// Scratch memory of qdpx_eval_shift_mul_axpy_noalloc: the per-group |chi|^2
+// partials and the finalisation's stage-A sums of a lattice of at most
+// kNoAllocMaxSites sites (4 MiB).  Each device holds its own copy for the
+// life of the process; host code reaches it only through the device address
+// hipGetSymbolAddress gives (qdpx_create keeps it in the context), never
+// through the array's name.
+static const int kNoAllocMaxSites = 1 << 25;
+static const int kNoAllocDoubles = (kNoAllocMaxSites / 64) + (kNoAllocMaxSites / 64 + 4095) / 4096;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 extern "C" int qdpx_create(qdpx_ctx **out, int device, const char *tune_cache_path) {
     if (!out) return fail(QDPX_EINVAL, "qdpx_create: out is NULL");
@@ -137,10 +148,23 @@ extern "C" int qdpx_create(qdpx_ctx **out, int device, const char *tune_cache_pa
                             path.c_str(), op_name(t.op));
         }
     }
+    // this device's address of the scratch array, looked up with the device current
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void *sp = nullptr;
+    e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    const hipError_t e2 = hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipSetDevice");
+    if (!sp) return fail(QDPX_EHIP, "qdpx_create: no device address for the scratch array");
     qdpx_ctx *c = new qdpx_ctx;
     c->device = device;
     c->arch = prop.gcnArchName;
     c->cache_path = path;
+    c->scratch = (double *)sp;
     for (const TuneEntry &t : entries) {
         const TuneKey k{t.op, t.prec, t.fmt, {t.L[0], t.L[1], t.L[2], t.L[3]}};
         c->tuned[k] = Tuned{t.cfg, kSrcTable};
@@ -428,6 +452,43 @@ extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qd
                               sign < 0 ? 1 : 0),
                  fn);
     if (norm2) QDPX_TRY_HIP(launch_finalize(part, shift_num_partials(g), 0, (double)g.V, norm2, st), fn);
+    return QDPX_OK;
+}
+
+// The shift expression without a caller workspace: the |chi|^2 partials go
+// to this device's scratch array (every partial and stage-A value is
+// rewritten by each call, so nothing needs clearing).
+extern "C" int qdpx_eval_shift_mul_axpy_noalloc(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec,
+                                                qdpx_linkfmt fmt, const void *U, const void *psi, const void *phi,
+                                                double a, uint32_t dir_mask, int sign, void *chi, double *norm2,
+                                                void *stream) {
+    const char *fn = "qdpx_eval_shift_mul_axpy_noalloc";
+    QDPX_CHECK_CTX(fn);
+    if (!geom_ok(geom, fn)) return QDPX_EINVAL;
+    if (int r = check_format(prec, fmt, fn)) return r;
+    const Geo g = make_geo(geom->L);
+    if (g.V > kNoAllocMaxSites)
+        return fail(QDPX_EINVAL, "%s: %d sites exceed the %d sites its fixed scratch memory holds", fn, g.V,
+                    kNoAllocMaxSites);
+    if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
+    if (sign != 1 && sign != -1) return fail(QDPX_EINVAL, "%s: sign %d is neither +1 nor -1", fn, sign);
+    if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
+    if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
+    if (!field_aligned(psi, prec) || !field_aligned(phi, prec) || !field_aligned(chi, prec))
+        return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+    const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
+    if (overlap(chi, fb, psi, fb) || overlap(chi, fb, phi, fb) || overlap(chi, fb, U, lb))
+        return fail(QDPX_EALIAS, "%s: chi overlaps an input", fn);
+    const int np = shift_num_partials(g);
+    if ((size_t)np + (size_t)finalize_stage_a_blocks(np) > (size_t)kNoAllocDoubles)
+        return fail(QDPX_EINVAL, "%s: scratch memory too small for %d partials", fn, np);
+    const LaunchCfg cfg = cfg_for(ctx, QDPX_OP_SHIFT, geom, prec, fmt);
+    hipStream_t st = (hipStream_t)stream;
+    double *part = norm2 ? ctx->scratch : nullptr;
+    QDPX_TRY_HIP(launch_shift(g, prec, nrows_of(fmt), U, psi, phi, a, 0, 0.0, chi, part, cfg, st, dir_mask,
+                              sign < 0 ? 1 : 0),
+                 fn);
+    if (norm2) QDPX_TRY_HIP(launch_finalize(part, np, 0, (double)g.V, norm2, st), fn);
     return QDPX_OK;
 }
 
