@@ -365,8 +365,11 @@ int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdp
  *   buf non-NULL the source is copied (QDPX_ENOMEM if it does not fit).
  * qdpx_jit_compile: generates the kernel, compiles it with hipRTC for the
  *   current device (packed FP32 disabled) or loads the code object from the
- *   on-disk cache (directory $QDPX_JIT_CACHE, else $HOME/.cache/qdpx-jit;
- *   file name a hash of source, options and architecture), and returns a
+ *   on-disk cache (directory $QDPX_JIT_CACHE, else $HOME/.cache/qdpx-jit,
+ *   created private to the user; neither variable set, or a directory that
+ *   others can write: no disk cache; file name a hash of source, options and
+ *   architecture; an entry is loaded only if it is a private regular file
+ *   holding this kernel's exact source, options and architecture), and returns a
  *   kernel handle valid for the context (released by qdpx_free_all /
  *   qdpx_destroy).  Not for a capturing stream (it may compile and loads a
  *   module).  EINVAL with the reason for a malformed expression.

@@ -30,6 +30,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <fcntl.h>
 #include <sys/stat.h>
 #include <unistd.h>
 #include <vector>
@@ -417,39 +418,89 @@ uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
     return h;
 }
 
+// Directory of the on-disk cache: $QDPX_JIT_CACHE, else $HOME/.cache/qdpx-jit;
+// "" (no disk cache) if neither is set.
 std::string cache_dir() {
     if (const char *d = std::getenv("QDPX_JIT_CACHE")) return d;
     if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/qdpx-jit";
-    return "/tmp/qdpx-jit";
+    return "";
 }
 
-void make_dirs(const std::string &path) {
+// A file or directory the cache may trust: owned by this user, not a
+// symbolic link, and writable by nobody else.
+bool private_entry(const struct stat &st) {
+    return st.st_uid == geteuid() && (st.st_mode & (S_IWGRP | S_IWOTH)) == 0;
+}
+
+// Creates the cache directory (and missing parents) private to this user and
+// checks that it is a directory only this user can write; false: do not use
+// the disk cache.
+bool private_dir(const std::string &path) {
     std::string cur;
     for (size_t i = 0; i < path.size(); ++i) {
         cur += path[i];
-        if (path[i] == '/' && cur.size() > 1) mkdir(cur.c_str(), 0755);
+        if (path[i] == '/' && cur.size() > 1) mkdir(cur.c_str(), 0700);
     }
-    mkdir(path.c_str(), 0755);
+    mkdir(path.c_str(), 0700);
+    struct stat st;
+    return lstat(path.c_str(), &st) == 0 && S_ISDIR(st.st_mode) && private_entry(st);
 }
 
-bool read_file(const std::string &p, std::vector<char> &out) {
-    FILE *f = std::fopen(p.c_str(), "rb");
-    if (!f) return false;
-    std::fseek(f, 0, SEEK_END);
-    const long n = std::ftell(f);
-    std::fseek(f, 0, SEEK_SET);
-    out.resize(n > 0 ? (size_t)n : 0);
-    const bool ok = n > 0 && std::fread(out.data(), 1, (size_t)n, f) == (size_t)n;
-    std::fclose(f);
-    return ok;
+// A cache entry is a header line, the generator's key text (source, options
+// and architecture) and the code object.  It is used only if it is a private
+// regular file whose stored key equals this kernel's key exactly, so neither
+// a hash collision nor a file left by someone else is ever loaded.
+const char kEntryMagic[] = "qdpx-jit-entry 1\n";
+
+bool read_entry(const std::string &p, const std::string &key, std::vector<char> &code) {
+    const int fd = open(p.c_str(), O_RDONLY | O_NOFOLLOW | O_CLOEXEC);
+    if (fd < 0) return false;
+    struct stat st;
+    std::vector<char> all;
+    bool ok = fstat(fd, &st) == 0 && S_ISREG(st.st_mode) && private_entry(st) && st.st_size > 0 &&
+              st.st_size < (1 << 28);
+    if (ok) {
+        all.resize((size_t)st.st_size);
+        size_t got = 0;
+        while (got < all.size()) {
+            const ssize_t n = read(fd, all.data() + got, all.size() - got);
+            if (n <= 0) break;
+            got += (size_t)n;
+        }
+        ok = got == all.size();
+    }
+    close(fd);
+    const size_t hm = sizeof kEntryMagic - 1;
+    if (!ok || all.size() < hm + 20 + key.size() || std::memcmp(all.data(), kEntryMagic, hm) != 0) return false;
+    char lenbuf[21];
+    std::memcpy(lenbuf, all.data() + hm, 20);
+    lenbuf[20] = '\0';
+    const unsigned long long klen = std::strtoull(lenbuf, nullptr, 10);
+    if (klen != key.size() || std::memcmp(all.data() + hm + 20, key.data(), key.size()) != 0) return false;
+    const size_t off = hm + 20 + key.size();
+    if (off >= all.size()) return false;
+    code.assign(all.begin() + (std::ptrdiff_t)off, all.end());
+    return true;
 }
 
-void write_file_atomic(const std::string &p, const std::vector<char> &data) {
+void write_entry_atomic(const std::string &p, const std::string &key, const std::vector<char> &code) {
     const std::string tmp = p + ".tmp" + std::to_string((long)getpid());
-    FILE *f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return;  // the cache is an optimisation: a failed write only costs a later recompile
-    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
-    std::fclose(f);
+    const int fd = open(tmp.c_str(), O_WRONLY | O_CREAT | O_EXCL | O_NOFOLLOW | O_CLOEXEC, 0600);
+    if (fd < 0) return;  // the cache is an optimisation: a failed write only costs a later recompile
+    char lenbuf[21];
+    std::snprintf(lenbuf, sizeof lenbuf, "%019zu\n", key.size());
+    std::string head = std::string(kEntryMagic) + lenbuf + key;
+    bool ok = true;
+    for (const auto &part : {std::make_pair((const char *)head.data(), head.size()),
+                             std::make_pair((const char *)code.data(), code.size())}) {
+        size_t put = 0;
+        while (ok && put < part.second) {
+            const ssize_t n = write(fd, part.first + put, part.second - put);
+            if (n <= 0) ok = false;
+            else put += (size_t)n;
+        }
+    }
+    ok = (close(fd) == 0) && ok;
     if (ok) std::rename(tmp.c_str(), p.c_str());
     else std::remove(tmp.c_str());
 }
@@ -541,17 +592,21 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
     for (int i = 0; i < kNumOptions; ++i) key_text += std::string(" ") + kOptions[i];
     char hex[32];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)fnv1a(key_text));
-    const std::string dir = cache_dir(), path = dir + "/" + hex + ".co";
+    const std::string dir = cache_dir();
+    const bool use_disk = !dir.empty() && private_dir(dir);
+    const std::string path = dir + "/" + hex + ".co";
     std::vector<char> code;
-    if (read_file(path, code)) {
-        // a cached object that no longer loads (a truncated or foreign file)
-        // is dropped and rebuilt; the failed load's error is cleared so that
-        // the next launch check does not report it
-        if (hipModuleLoadData(&k.module, code.data()) == hipSuccess) {
+    if (use_disk) {
+        struct stat st;
+        const bool present = lstat(path.c_str(), &st) == 0;
+        // an entry that is not this kernel's, or no longer loads (a truncated
+        // or foreign file), is dropped and rebuilt; a failed load's error is
+        // cleared so that the next launch check does not report it
+        if (read_entry(path, key_text, code) && hipModuleLoadData(&k.module, code.data()) == hipSuccess) {
             k.from_cache = true;
         } else {
             (void)hipGetLastError();
-            std::remove(path.c_str());
+            if (present) std::remove(path.c_str());
         }
     }
     if (!k.from_cache) {
@@ -574,8 +629,7 @@ extern "C" int qdpx_jit_compile(qdpx_ctx *ctx, const char *expr, qdpx_prec prec,
         code.resize(n);
         hiprtcGetCode(prog, code.data());
         hiprtcDestroyProgram(&prog);
-        make_dirs(dir);
-        write_file_atomic(path, code);
+        if (use_disk) write_entry_atomic(path, key_text, code);
     }
     hipError_t e = hipSuccess;
     if (!k.from_cache && (e = hipModuleLoadData(&k.module, code.data())) != hipSuccess) {

@@ -137,6 +137,36 @@ def test_jit_cache_rebuilds_an_unloadable_entry(tmp_path, monkeypatch):
         c.close()
 
 
+def test_jit_cache_loads_only_matching_private_entries(tmp_path, monkeypatch):
+    """An entry whose stored source differs from the kernel's (a hash
+    collision or a planted file) is never loaded, and a cache directory that
+    others can write is not used at all."""
+    cache = tmp_path / "cache"
+    monkeypatch.setenv("QDPX_JIT_CACHE", str(cache))
+    e = "(add (shift f0 + 3) (scale s0 f0))"
+    c1 = q.Context(0)
+    q.qdpx_jit_compile(c1, e, q.F32, q.LINK18, 1, 1)
+    (entry,) = list(cache.glob("*.co"))
+    blob = entry.read_bytes()
+    assert blob.startswith(b"qdpx-jit-entry 1\n")
+    entry.write_bytes(blob.replace(b"shift f0 + 3", b"shift f0 + 2", 1))  # another expression's text
+    entry.chmod(0o600)
+    c2 = q.Context(0)
+    k2 = q.qdpx_jit_compile(c2, e, q.F32, q.LINK18, 1, 1)
+    assert not q.qdpx_jit_info(c2, k2)[0]
+    c3 = q.Context(0)
+    assert q.qdpx_jit_info(c3, q.qdpx_jit_compile(c3, e, q.F32, q.LINK18, 1, 1))[0]  # rewritten, then reused
+    shared = tmp_path / "shared"
+    shared.mkdir(mode=0o777)
+    shared.chmod(0o777)
+    monkeypatch.setenv("QDPX_JIT_CACHE", str(shared))
+    c4 = q.Context(0)
+    q.qdpx_jit_compile(c4, e, q.F32, q.LINK18, 1, 1)
+    assert list(shared.glob("*")) == []
+    for c in (c1, c2, c3, c4):
+        c.close()
+
+
 def test_jit_graph_replay_matches_eager():
     L = (8, 8, 4, 8)
     c = ctx()
