@@ -149,7 +149,8 @@ def test_jit_cache_loads_only_matching_private_entries(tmp_path, monkeypatch):
     (entry,) = list(cache.glob("*.co"))
     blob = entry.read_bytes()
     assert blob.startswith(b"qdpx-jit-entry 1\n")
-    entry.write_bytes(blob.replace(b"shift f0 + 3", b"shift f0 + 2", 1))  # another expression's text
+    assert b"#define NROWS 3" in blob
+    entry.write_bytes(blob.replace(b"#define NROWS 3", b"#define NROWS 2", 1))  # another kernel's stored text
     entry.chmod(0o600)
     c2 = q.Context(0)
     k2 = q.qdpx_jit_compile(c2, e, q.F32, q.LINK18, 1, 1)
