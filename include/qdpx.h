@@ -265,7 +265,11 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
  * unchanged.  smear_mask: bit mu = direction mu; 0xF smears all four, 0x7
  * leaves the time direction alone (the role of the no-smear direction
  * argument of the smearing routine of section 7).  The projection is always
- * FP64.  With QDPX_F32 the staple products are evaluated in FP32.  U_in is
+ * FP64.  With QDPX_F32 the staple products are evaluated in FP32.  FP64
+ * steps with the Gram-Schmidt projection read rows 0 and 1 of every input
+ * link and take row 2 as conj(row0 x row1), rebuilt in FP64 (exact for SU(3)
+ * links; every smeared link's stored row 2 is that by construction); the
+ * other steps use the stored row 2 (LINK18) or rebuild it (LINK12).  U_in is
  * not modified; U_out must not overlap U_in.
  * projection: QDPX_PROJ_GRAM_SCHMIDT (the rows above; only rows 0 and 1 of
  * the staples are formed) or QDPX_PROJ_POLAR: V = W (W^dag W)^(-1/2)

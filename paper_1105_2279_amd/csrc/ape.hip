@@ -1,17 +1,18 @@
 // Single-lattice kernels: one APE step (for FP64 links optionally with the
-// plaquette of its input), the FP64 plaquette-only pass of the step's
-// arithmetic, and the standalone plaquette (FP64 products for every link
-// precision).
+// plaquette of its input) and the plaquette pass (FP64 products for every
+// link precision).
 #include "qdpx_impl.hpp"
 #include "ape_device.hpp"
 
 namespace qdpx {
 
-// One APE step (or, in kPlaqOnly mode, only the plaquette of the input).
-// Thread mapping: a block of 256*k threads (k = 1 or 2) holds k groups of 64
-// consecutive sites per iteration; wave w handles direction mu = w % 4 of
-// group w / 4, so the four links of a site are updated by four waves of the
-// same block, which share the neighbour loads in L1/L2.
+// One APE step (for FP64 links in kApePlaq mode with the plaquette of its
+// input).  Thread mapping: a block of 256*k threads (k = 1 or 2) holds k
+// groups of 64 consecutive sites per iteration; for FP32 links wave w
+// handles direction mu = w % 4 of group w / 4, so the four links of a site
+// are updated by four waves of the same block, which share the neighbour
+// loads in L1/L2; for FP64 links wave w % 4 of group w / 4 takes the four
+// directions of 16 of its sites (ape_group_f64).
 template <typename R, int NR, int NS, int MODE, int PROJ = 0>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
                                                   double c2, unsigned mask, double *__restrict__ partials, int xcd,
@@ -61,6 +62,7 @@ int ape_num_partials(const Geo &g) { return 4 * ((g.V + 63) / 64); }
 hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, void *Uout, double c1, double c2,
                            unsigned mask, double *partials, int mode, const LaunchCfg &cfg, hipStream_t st,
                            int proj) {
+    if (mode != kApe && mode != kApePlaq) return hipErrorInvalidValue;
     if (mode == kApePlaq && mask != 0xFu) return hipErrorInvalidValue;  // owned planes need every staple
     if (proj && mode != kApe) return hipErrorInvalidValue;             // polar: plaquettes in their own pass
     if (prec != 0 && mode != kApe) return hipErrorInvalidValue;        // FP32: plaquettes from k_plaquette
@@ -75,9 +77,8 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
                                                              LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,     \
                                                              mask, partials, xcd, cfg.tw)
 #define QDPX_APE_M64(NS)                                                       \
-    if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1);                         \
-    else if (mode == kPlaqOnly) QDPX_APE_LAUNCH(double, 3, NS, kPlaqOnly, 0);  \
-    else if (mode == kApePlaq) QDPX_APE_LAUNCH(double, 3, NS, kApePlaq, 0);    \
+    if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1);                      \
+    else if (mode == kApePlaq) QDPX_APE_LAUNCH(double, 3, NS, kApePlaq, 0); \
     else QDPX_APE_LAUNCH(double, 3, NS, kApe, 0);
 #define QDPX_APE_M32(NR, NS)                          \
     if (proj) QDPX_APE_LAUNCH(float, NR, NS, kApe, 1); \
@@ -107,37 +108,26 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
 }
 
 // ---------------------------------------------------------------- plaquette
-// One site per lane, four 64-site groups (the brick groups of the step
-// kernels) per 256-thread block; the spatial and temporal sums of group grp
-// go to partials[grp] and partials[n + grp].
+// One 64-site group per 192-thread block, wave w taking its two planes
+// (plaquette_wave).  FP32 links: at most 128 registers, four waves per SIMD
+// (without the bound the compiler takes 130 for three).
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) k_plaquette(Geo g, LinksRO<R, NR> U, double *__restrict__ partials) {
-    const int lane = threadIdx.x & 63;
-    const int grp = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int n = (g.V + 63) >> 6;
-    if (grp >= n) return;
-    double sp = 0.0, tp = 0.0;
-    Site x;
-    if (group_site(g, grp, lane, x)) plaquette_site(g, U, x, sp, tp);
-    sp = wave_sum(sp);
-    tp = wave_sum(tp);
-    if (lane == 0) {
-        partials[grp] = sp;
-        partials[n + grp] = tp;
-    }
+__global__ void __launch_bounds__(64 * kPlaqWavesPerGroup) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+k_plaquette(Geo g, LinksRO<R, NR> U, double *__restrict__ partials) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    plaquette_wave(g, U, (int)blockIdx.x, w, (int)(threadIdx.x & 63), partials);
 }
 
-int plaquette_num_partials(const Geo &g) { return (g.V + 63) / 64; }
+int plaquette_num_partials(const Geo &g) { return kPlaqWavesPerGroup * ((g.V + 63) / 64); }
 
 hipError_t launch_plaquette(const Geo &g, int prec, int nrows, const void *U, double *partials, hipStream_t st) {
-    const int groups = (g.V + 63) / 64;
-    const dim3 grid((groups + 3) / 4);
+    const dim3 grid((g.V + 63) / 64), block(64 * kPlaqWavesPerGroup);
     if (prec == 0)
-        k_plaquette<double, 3><<<grid, 256, 0, st>>>(g, LinksRO<double, 3>{(const double2 *)U, g.S}, partials);
+        k_plaquette<double, 3><<<grid, block, 0, st>>>(g, LinksRO<double, 3>{(const double2 *)U, g.S}, partials);
     else if (nrows == 3)
-        k_plaquette<float, 3><<<grid, 256, 0, st>>>(g, LinksRO<float, 3>{(const float2 *)U, g.S}, partials);
+        k_plaquette<float, 3><<<grid, block, 0, st>>>(g, LinksRO<float, 3>{(const float2 *)U, g.S}, partials);
     else
-        k_plaquette<float, 2><<<grid, 256, 0, st>>>(g, LinksRO<float, 2>{(const float2 *)U, g.S}, partials);
+        k_plaquette<float, 2><<<grid, block, 0, st>>>(g, LinksRO<float, 2>{(const float2 *)U, g.S}, partials);
     return hipGetLastError();
 }
 

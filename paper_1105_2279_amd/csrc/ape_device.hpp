@@ -114,100 +114,84 @@ __device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s,
     if constexpr (NR == 2) rebuild_row2(m);
 }
 
-// Row i of link (mu, s) in FP64: a stored row widened, or (LINK12, i = 2)
-// rebuilt in FP64 from the widened rows 0 and 1, as load_f64 forms it.
-template <typename R, int NR, int I>
-__device__ __forceinline__ void row_f64(const LinksRO<R, NR> &U, int mu, int s, Cx<double> (&r)[3]) {
-    if constexpr (I < 2 || NR == 3) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Cx<R> z = U.ld(mu, I, b, s);
-            r[b] = Cx<double>{(double)z.re, (double)z.im};
-        }
-    } else {
-        M3<double> m;
-        Cx<R> e[2][3];
-        U.template load_rows<false, 2>(mu, s, e);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m.e[a][b] = Cx<double>{(double)e[a][b].re, (double)e[a][b].im};
-        rebuild_row2(m);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) r[b] = m.e[2][b];
-    }
-}
-
 // Re Tr P_{mu nu}(x) = Re Tr[(U_mu(x) U_nu(x+mu)) (U_nu(x) U_mu(x+nu))^dag] of
 // the stored links widened to FP64 (row 2 rebuilt in FP64 for LINK12), every
-// product and sum in FP64: the plaquette of the standalone pass, of the FP32
-// steps' per-step plaquettes and of the batched FP32 plaquettes, one
-// function so that they agree bit for bit.  s_mu = x+mu, s_nu = x+nu.  Rows of
-// U_mu(x) and U_nu(x) are loaded as they are needed, so that only the two
-// neighbour links and one product are held in FP64 at a time.
+// product and sum in FP64: the plaquette pass behind every plaquette of
+// FP32 links (standalone, per step, batched) and of FP64 links outside the
+// fused step.  s_mu = x+mu, s_nu = x+nu.  Each link is loaded once, whole.
 template <typename R, int NR>
 __device__ __forceinline__ double plaquette_plane(const LinksRO<R, NR> &U, int mu, int nu, int s, int s_mu,
                                                   int s_nu) {
     M3<double> m;  // U_mu(x) U_nu(x+mu)
     {
-        M3<double> b;
+        M3<double> a, b;
+        load_f64(U, mu, s, a);
         load_f64(U, nu, s_mu, b);
-        Cx<double> a[3];
-#define QDPX_PLAQ_ROW_M(I)                                                           \
-        row_f64<R, NR, I>(U, mu, s, a);                                              \
-        for (int j = 0; j < 3; ++j) {                                                \
-            Cx<double> t{0.0, 0.0};                                                  \
-            for (int k = 0; k < 3; ++k) cmac(t, a[k], b.e[k][j]);                     \
-            m.e[I][j] = t;                                                           \
-        }
-        QDPX_PLAQ_ROW_M(0)
-        QDPX_PLAQ_ROW_M(1)
-        QDPX_PLAQ_ROW_M(2)
-#undef QDPX_PLAQ_ROW_M
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                Cx<double> t{0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cmac(t, a.e[i][k], b.e[k][j]);
+                m.e[i][j] = t;
+            }
     }
-    M3<double> c;  // U_mu(x+nu)
+    M3<double> c, d;  // U_mu(x+nu), U_nu(x)
     load_f64(U, mu, s_nu, c);
+    load_f64(U, nu, s, d);
     double p = 0.0;
-    Cx<double> d[3];
-#define QDPX_PLAQ_ROW_N(I)                                                               \
-    row_f64<R, NR, I>(U, nu, s, d);                                                      \
-    for (int j = 0; j < 3; ++j) {                                                        \
-        Cx<double> n{0.0, 0.0};                                                          \
-        for (int k = 0; k < 3; ++k) cmac(n, d[k], c.e[k][j]);                            \
-        p = fma(m.e[I][j].re, n.re, fma(m.e[I][j].im, n.im, p));                          \
-    }
-    QDPX_PLAQ_ROW_N(0)
-    QDPX_PLAQ_ROW_N(1)
-    QDPX_PLAQ_ROW_N(2)
-#undef QDPX_PLAQ_ROW_N
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<double> n{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(n, d.e[i][k], c.e[k][j]);
+            p = fma(m.e[i][j].re, n.re, fma(m.e[i][j].im, n.im, p));
+        }
     return p;
 }
 
-// Spatial (nu < 3) and temporal (nu = 3) plaquette sums of site x over the
-// six planes, planes (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) added in that order.
-template <typename R, int NR>
-__device__ __forceinline__ void plaquette_site(const Geo &g, const LinksRO<R, NR> &U, const Site &x, double &sp,
-                                               double &tp) {
-    sp = tp = 0.0;
-#pragma unroll 1
-    for (int mu = 0; mu < 3; ++mu) {
-        const int s_mu = hop_fwd(g, x.s, coord(x, mu), mu);
-#pragma unroll 1
-        for (int nu = mu + 1; nu < 4; ++nu) {
-            const double p = plaquette_plane(U, mu, nu, x.s, s_mu, hop_fwd(g, x.s, coord(x, nu), nu));
-            if (nu == 3) tp += p;
-            else sp += p;
-        }
-    }
+template <typename R, int NR, int MU, int NU>
+__device__ __forceinline__ double plaquette_at(const Geo &g, const LinksRO<R, NR> &U, const Site &x) {
+    return plaquette_plane(U, MU, NU, x.s, hop_fwd(g, x.s, x.c[MU], MU), hop_fwd(g, x.s, x.c[NU], NU));
 }
 
-// Plaquette planes are shared out over the four direction waves so that each
-// of the six planes is counted once and each wave's planes are all spatial or
-// all temporal: wave 0 owns (0,1), (0,2); wave 1 owns (1,2); wave 2 owns
-// (2,3); wave 3 owns (3,0), (3,1).  Ownership is wave-uniform.
-__device__ __forceinline__ bool owns_plane(int mu, int nu) {
-    return (mu == 0 && (nu == 1 || nu == 2)) || (mu == 1 && nu == 2) || (mu == 2 && nu == 3) ||
-           (mu == 3 && nu < 2);
+// The plaquette pass: three waves per 64-site group, each lane taking one
+// spatial and one temporal plane of its site, wave 0 planes (0,1) and (2,3),
+// wave 1 (0,2) and (1,3), wave 2 (1,2) and (0,3) (directions known at
+// compile time, three times the waves of a site-per-lane loop over six
+// planes).  Wave w of group grp writes its spatial sum to partials[3 grp + w]
+// and its temporal sum to partials[3 ngroups + 3 grp + w]; every launch that
+// reports a plaquette of stored links goes through here, so they all agree
+// bit for bit.
+constexpr int kPlaqWavesPerGroup = 3;
+
+template <typename R, int NR>
+__device__ __forceinline__ void plaquette_wave(const Geo &g, const LinksRO<R, NR> &U, int grp, int w, int lane,
+                                               double *__restrict__ partials) {
+    double sp = 0.0, tp = 0.0;
+    Site x;
+    if (group_site(g, grp, lane, x)) {
+        if (w == 0) {
+            sp = plaquette_at<R, NR, 0, 1>(g, U, x);
+            tp = plaquette_at<R, NR, 2, 3>(g, U, x);
+        } else if (w == 1) {
+            sp = plaquette_at<R, NR, 0, 2>(g, U, x);
+            tp = plaquette_at<R, NR, 1, 3>(g, U, x);
+        } else {
+            sp = plaquette_at<R, NR, 1, 2>(g, U, x);
+            tp = plaquette_at<R, NR, 0, 3>(g, U, x);
+        }
+    }
+    sp = wave_sum(sp);
+    tp = wave_sum(tp);
+    if (lane == 0) {
+        const int n3 = kPlaqWavesPerGroup * num_groups(g);
+        partials[kPlaqWavesPerGroup * grp + w] = sp;
+        partials[n3 + kPlaqWavesPerGroup * grp + w] = tp;
+    }
 }
 
 // Re Tr[U X^dag] for U, X in SU(3) from their rows 0 and 1 alone.  With
@@ -279,20 +263,14 @@ __device__ __forceinline__ void stage_own_link(const Geo &g, const LinksRO<R, NR
 }
 
 // Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
-// in mask (bits 0..3; all four for the fused plaquette).  With PLQ, plq
-// receives the sum over the planes this wave owns of Re Tr[U_mu(x) X^dag],
-// X the plane's upper staple, which is the trace of the plaquette
-// P_{mu nu}(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag; u0 holds
-// rows 0 and 1 of U_mu(x).
-template <typename R, int NR, bool PLQ>
+// in mask (bits 0..3).
+template <typename R, int NR>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  unsigned mask, M23<R> &S, const M23<R> &u0, double &plq,
-                                                  const nv4_t<R> *own = nullptr) {
+                                                  unsigned mask, M23<R> &S, const nv4_t<R> *own = nullptr) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
-    plq = 0.0;
     const int s = x.s;
     const int s_mu = hop_fwd(g, s, site_coord<R>(x, mu), mu);
 #pragma unroll 1
@@ -310,26 +288,22 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             mul_23_33(A, B, T);
             M3<R> C;
             U.full(nu, s_mu, C);
-            if (owns_plane(mu, nu)) {
-                // Owned planes are formed on their own and then added, with or
-                // without the plaquette, so the staple sum S (and hence the
-                // smeared link) is bit-identical whether or not PLQ is set.
-                M23<R> X;
+            if (nu < mu) {
+            M23<R> X;
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
-                acc_23_33dag(X, T, C);
-                if constexpr (PLQ) plq += retrace_rows01(u0, X);
+                for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
+            acc_23_33dag(X, T, C);
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        S.e[i][j].re += X.e[i][j].re;
-                        S.e[i][j].im += X.e[i][j].im;
-                    }
+                for (int j = 0; j < 3; ++j) {
+                    S.e[i][j].re += X.e[i][j].re;
+                    S.e[i][j].im += X.e[i][j].im;
+                }
             } else {
-                acc_23_33dag(S, T, C);
+            acc_23_33dag(S, T, C);
             }
         }
         // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
@@ -395,38 +369,7 @@ __device__ __forceinline__ void store_narrowed(const LinksWO<R, NR> &out, int mu
 }
 
 // What one (64-site group, direction) wave computes.
-enum ApeMode { kApe = 0, kApePlaq = 1, kPlaqOnly = 2 };
-
-// The owned planes' plaquette traces only: the same arithmetic as the PLQ
-// branch of staple_sum_rows01, so both give the same value bit for bit.
-template <typename R, int NR>
-__device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                   const M23<R> &u0) {
-    double plq = 0.0;
-    const int s = x.s;
-    const int s_mu = hop_fwd(g, s, site_coord<R>(x, mu), mu);
-#pragma unroll 1
-    for (int k = 0; k < 3; ++k) {
-        const int nu = k + (k >= mu);
-        if (!owns_plane(mu, nu)) continue;
-        M23<R> A;
-        U.rows01(nu, s, A);
-        M3<R> B;
-        U.full(mu, hop_fwd(g, s, site_coord<R>(x, nu), nu), B);
-        M23<R> T;
-        mul_23_33(A, B, T);
-        M3<R> C;
-        U.full(nu, s_mu, C);
-        M23<R> X;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
-        acc_23_33dag(X, T, C);
-        plq += retrace_rows01(u0, X);
-    }
-    return plq;
-}
+enum ApeMode { kApe = 0, kApePlaq = 1 };
 
 // ------------------------------------------------------------- FP64 step
 // The FP64 step puts the four directions of 16 sites in one wave: lane L of
@@ -439,13 +382,14 @@ __device__ __forceinline__ double owned_plaquettes(const Geo &g, const LinksRO<R
 // neighbour link, U_mu(x+nu), and takes U_nu(x+mu) and rows 0 and 1 of
 // U_nu(x) from its partner by cross-lane exchange; the lower staple's
 // U_nu(x-nu) is the partner's backward link, which every lane loads once
-// and shares through LDS.  A link update then issues 96 vector loads of 16
-// bytes instead of 151: the vector-memory pipeline, not the arithmetic,
-// bounds the FP64 step.  The fused plaquette takes each plane once, in the
+// and shares through LDS.  Every link is read as its rows 0 and 1, row 2
+// rebuilt in FP64.  A link update then issues 84 vector loads of 16 bytes
+// instead of 151: the memory pipeline, not the arithmetic, bounds the FP64
+// step.  The fused plaquette takes each plane once, in the
 // lane of its lower direction.  Direction-dependent addresses differ
 // between lanes here, so they are formed in 64 bits per lane.
 
-constexpr int kF64BackPerWave = 9 * 64;  // double2 per wave: one backward link per lane
+constexpr int kF64BackPerWave = 6 * 64;  // double2 per wave: columns 0 and 1 of one backward link per lane
 
 __device__ __forceinline__ int sel4(int i, int a, int b, int c, int d) {
     return i == 0 ? a : i == 1 ? b : i == 2 ? c : d;
@@ -473,11 +417,19 @@ __device__ __forceinline__ void st_lane(double2 *dir, int64_t S, int c, int s, c
 __device__ __forceinline__ Cx<double> xchg(const Cx<double> &z, int m) {
     return Cx<double>{__shfl_xor(z.re, m, 64), __shfl_xor(z.im, m, 64)};
 }
+// FP64 link at site s: rows 0 and 1 loaded, row 2 rebuilt as conj(row0 x row1)
+// (exact for SU(3) links; a smeared link's stored row 2 is that by
+// construction), so each neighbour link moves 96 bytes instead of 144.
+__device__ __forceinline__ void ld_lane_rows01(const double2 *dir, int64_t S, int s, M3<double> &m) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) m.e[c / 3][c % 3] = ld_lane(dir, S, c, s);
+    rebuild_row2(m);
+}
 
-// One wave's share of an FP64 step (modes as ape_group): the four directions
-// of 16 sites of group grp.  back: this wave's kF64BackPerWave LDS entries.
-// Partials (plaquette modes): partials[grp*4 + w] (spatial planes) and
-// partials[4*ngroups + grp*4 + w] (temporal planes) of the INPUT links.
+// One wave's share of an FP64 step: the four directions of 16 sites of
+// group grp.  back: this wave's kF64BackPerWave LDS entries.  In kApePlaq
+// mode also the plaquette traces of the INPUT links: partials[grp*4 + w]
+// (spatial planes) and partials[4*ngroups + grp*4 + w] (temporal planes).
 template <int MODE>
 __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double, 3> &U, const LinksWO<double, 3> &out,
                                               double c1, double c2, unsigned mask, double *__restrict__ partials,
@@ -489,17 +441,20 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
     if (!live) x.init(g, 0);  // padding lanes load from site 0 and store nothing
     const int s = x.s;
     const int cmu = coord(x, mu);
-    const bool smear = MODE == kPlaqOnly || ((mask >> mu) & 1u);
+    const bool smear = (mask >> mu) & 1u;
     const int64_t S9 = 9 * U.S;
     const double2 *dmu = U.p + mu * S9;  // this lane's direction
-    if constexpr (MODE != kPlaqOnly) {
-        // the backward link U_mu(x-mu), read by the lanes of the other directions
+    {
+        // columns 0 and 1 of the backward link U_mu(x-mu) (all the lower
+        // staple reads), for the lanes of the other directions: entry
+        // 2k + i holds element (k, i)
         const int sb = hop_bwd_v(g, s, cmu, mu);
+        M3<double> bl;
+        ld_lane_rows01(dmu, U.S, sb, bl);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            const Cx<double> z = ld_lane(dmu, U.S, c, sb);
-            back[c * 64 + lane] = double2{z.re, z.im};
-        }
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) back[(2 * k + i) * 64 + lane] = double2{bl.e[k][i].re, bl.e[k][i].im};
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -516,7 +471,7 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
         const int nu = mu ^ (p + 1);
         // plane (mu, nu) is smeared for this lane exactly when it is for the
         // partner (both directions in the mask)
-        const bool act = smear && (MODE == kPlaqOnly || ((mask >> nu) & 1u));
+        const bool act = smear && ((mask >> nu) & 1u);
         const bool own_plane = mu < nu;  // the plaquette of the plane is taken here
         const int cnu = coord(x, nu);
         // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag.  B = U_mu(x+nu) is loaded by
@@ -525,8 +480,7 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
         // a time as the products consume them.
         M3<double> B;
         const int s_nu = hop_fwd_v(g, s, cnu, nu);
-#pragma unroll
-        for (int c = 0; c < 9; ++c) B.e[c / 3][c % 3] = ld_lane(dmu, U.S, c, s_nu);
+        ld_lane_rows01(dmu, U.S, s_nu, B);
         const double2 *dnu = U.p + nu * S9;
         Cx<double> T[2][3];
 #pragma unroll
@@ -584,7 +538,7 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
                     S[i][j].im += X[i][j].im;
                 }
         }
-        if constexpr (MODE != kPlaqOnly) {
+        {
             // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu, by rows k:
             // T2_ij = sum_k conj(LA_ki) LB_kj with LA = U_nu(x-nu), the
             // partner's backward link (columns 0 and 1 from LDS), then
@@ -603,21 +557,30 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
                     Cx<double> la[2], lb[3];
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
-                        const double2 v = back[(3 * k + i) * 64 + (lane ^ xm)];
+                        const double2 v = back[(2 * k + i) * 64 + (lane ^ xm)];
                         la[i] = Cx<double>{v.x, v.y};
                     }
+                    if (k < 2) {
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) lb[j] = ld_lane(dmu, U.S, 3 * k + j, sy);
+                        for (int j = 0; j < 3; ++j) lb[j] = ld_lane(dmu, U.S, 3 * k + j, sy);
+                    } else {  // row 2 of U_mu(y), rebuilt from its rows 0 and 1
+                        M3<double> m;
+                        ld_lane_rows01(dmu, U.S, sy, m);
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) lb[j] = m.e[2][j];
+                    }
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
 #pragma unroll
                         for (int j = 0; j < 3; ++j) cmac_ca(T2[i][j], la[i], lb[j]);
                 }
+                M3<double> LC;
+                ld_lane_rows01(dnu, U.S, syf, LC);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     Cx<double> lc[3];
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) lc[j] = ld_lane(dnu, U.S, 3 * k + j, syf);
+                    for (int j = 0; j < 3; ++j) lc[j] = LC.e[k][j];
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -626,7 +589,7 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
             }
         }
     }
-    if constexpr (MODE != kPlaqOnly) {
+    {
         // the next group's backward links overwrite these: every lane has read
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -673,13 +636,10 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
     }
 }
 
-// One wave's share of a step: direction mu of the 64 sites of group grp
-// (FP64 with the row projection: ape_group_f64, wave mu of the group).
-// Writes the smeared links (modes kApe, kApePlaq; a direction outside mask
-// is copied unchanged, mask is 0xF in kApePlaq) and, in the plaquette
-// modes, the owned planes' trace sum of the INPUT links for (grp, mu):
-// partials[grp*4 + mu] (spatial planes, waves 0 and 1) and
-// partials[4*ngroups + grp*4 + mu] (temporal planes, waves 2 and 3).
+// One wave's share of a step: direction mu of the 64 sites of group grp,
+// the smeared links written (a direction outside mask is copied unchanged).
+// FP64 links with the row projection go to ape_group_f64 (mu is then the
+// wave's index within the group), which also has the plaquette modes.
 // Depends only on (grp, mu), never on the launch geometry.
 template <typename R, int NR, int MODE, int PROJ = 0>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
@@ -692,16 +652,12 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
         ape_group_f64<MODE>(g, U, out, c1, c2, mask, partials, grp, mu, lane, back64);
         return;
     }
-    const int ngroups = num_groups(g);
-    double p = 0.0;
+    static_assert(MODE == kApe || (sizeof(R) == 8 && PROJ == 0),
+                  "plaquettes of FP32 links come from the plaquette pass");
     Site x;
     if (group_site(g, grp, lane, x)) {
         const int s = x.s;
-        if constexpr (MODE == kPlaqOnly) {
-            M23<R> u0;
-            U.rows01(mu, s, u0);
-            p = owned_plaquettes(g, U, x, mu, u0);
-        } else if (!((mask >> mu) & 1u)) {  // wave-uniform: not smeared
+        if (!((mask >> mu) & 1u)) {  // wave-uniform: not smeared
             M3<R> u;
             U.full(mu, s, u);
             out.store(mu, s, u.e);
@@ -721,16 +677,9 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             store_narrowed(out, mu, s, v);
         } else {
             M23<R> S, u0;
-            if constexpr (MODE == kApePlaq) {  // the plaquette needs u0 in the staple loop
-                if (own) own_rows01(own, mu, u0);
-                else U.rows01(mu, s, u0);
-                staple_sum_rows01<R, NR, true>(g, U, x, mu, mask, S, u0, p, own);
-            } else {
-                double unused;
-                staple_sum_rows01<R, NR, false>(g, U, x, mu, mask, S, u0, unused, own);
-                if (own) own_rows01(own, mu, u0);
-                else U.rows01(mu, s, u0);
-            }
+            staple_sum_rows01<R, NR>(g, U, x, mu, mask, S, own);
+            if (own) own_rows01(own, mu, u0);
+            else U.rows01(mu, s, u0);
             Cx<double> wm[2][3], v[3][3];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -741,14 +690,6 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
                 }
             reunitarise(wm, v);
             store_narrowed(out, mu, s, v);
-        }
-    }
-    if constexpr (MODE != kApe) {
-        p = wave_sum(p);
-        if (lane == 0) {
-            const bool temporal = mu >= 2;
-            partials[grp * 4 + mu] = temporal ? 0.0 : p;
-            partials[4 * ngroups + grp * 4 + mu] = temporal ? p : 0.0;
         }
     }
 }

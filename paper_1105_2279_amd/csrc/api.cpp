@@ -645,21 +645,16 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     // d = number of smeared directions (alpha/6 for all four).
     const int d = __builtin_popcount(smear_mask);
     const double c1 = 1.0 - alpha, c2 = d > 1 ? alpha / (2.0 * (d - 1)) : 0.0;
-    // Plaquettes.  FP32 links: the standalone plaquette pass (FP64 products
-    // of the widened links) on the input and on every step's output, so each
-    // value is the one qdpx_plaquette gives on those links.  FP64 links: with
-    // every direction smeared and the Gram-Schmidt projection, step k also
-    // reduces the plaquette of its own input (fused into the APE kernel) and
-    // only the last output needs the plaquette-only pass; otherwise every
-    // plaquette is that pass (the same per-plane arithmetic, so the values
-    // agree bit for bit).
+    // Plaquettes: the standalone plaquette pass (FP64 products of the
+    // widened links), so each value is the one qdpx_plaquette gives on those
+    // links, on the input and on every step's output; except that FP64 steps
+    // with every direction smeared and the Gram-Schmidt projection reduce the
+    // plaquette of their own input inside the APE kernel (the same value to
+    // the rounding of FP64), so only the last output needs the pass.
     const bool f32 = (prec == QDPX_F32);
     const bool fused = !f32 && (smear_mask == 0xFu) && !polar;
     auto plaquette_of = [&](const void *links, double *out) -> int {
-        if (f32) return plaquette_into(g, prec, fmt, links, out, part, st, fn);
-        QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), links, nullptr, c1, c2, 0xFu, part, 2, cfg, st), fn);
-        QDPX_TRY_HIP(launch_finalize(part, ape_num_partials(g), 1, (double)g.V, out, st), fn);
-        return QDPX_OK;
+        return plaquette_into(g, prec, fmt, links, out, part, st, fn);
     };
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {

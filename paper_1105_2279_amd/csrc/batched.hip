@@ -24,10 +24,9 @@
 //
 // The plaquettes of the outputs follow as two ordinary launches (the traces
 // of every group of every lattice, then one reducing block per lattice) with
-// exactly the arithmetic of the single-lattice path: the FP64 products of the
-// standalone plaquette for FP32 links, the owned-plane traces of the FP64
-// step for FP64 links.  Keeping them out of the persistent kernel keeps its
-// register budget that of the step alone.
+// exactly the arithmetic and partial layout of the standalone plaquette
+// pass, in FP64 for every link precision.  Keeping them out of the
+// persistent kernel keeps its register budget that of the step alone.
 #include "ape_device.hpp"
 #include "qdpx_impl.hpp"
 #include "reduce_device.hpp"
@@ -35,7 +34,8 @@
 namespace qdpx {
 
 // Largest number of stage-A values a lattice's plaquette reduction may need
-// (held in LDS): 4*ngroups <= kBatchMaxStage * kFinPerBlock.
+// (held in LDS): 3*ngroups <= kBatchMaxStage * kFinPerBlock (bounded with 4
+// partials per group).
 constexpr int kBatchMaxStage = 64;
 
 __global__ void __launch_bounds__(256) k_batched_init(unsigned *__restrict__ counters, int n) {
@@ -154,33 +154,17 @@ __global__ void __launch_bounds__(256 * GPB) k_ape_batched(BatchArgs a, const Ba
     }
 }
 
-// Plaquette traces of every lattice's output links into its partials, the
-// single-lattice arithmetic and partial layout: FP32 links as k_plaquette
-// (four groups per block, one per wave, partials[grp] and [ngroups + grp]);
-// FP64 links as the APE kernel's plaquette-only mode (one group per block,
-// one direction per wave, four partials per group).
+// Plaquette traces of every lattice's output links into its partials: one
+// 64-site group per block, the single-lattice plaquette pass's arithmetic
+// and partial layout (plaquette_wave), so each lattice's plaquette is the
+// one qdpx_plaquette gives for its links, bit for bit.
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) k_batched_plaq(BatchArgs a, const BatchLat *__restrict__ lats) {
+__global__ void __launch_bounds__(64 * kPlaqWavesPerGroup) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+k_batched_plaq(BatchArgs a, const BatchLat *__restrict__ lats) {
     const int b = blockIdx.x;
     const BatchLat &L = lats[find_lattice(a.n_lat, b, [&](int i) { return lats[i].pbase; })];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const LinksRO<R, NR> U{(const vec2_t<R> *)L.out, L.g.S};
-    if constexpr (sizeof(R) == 4) {
-        const int grp = (b - L.pbase) * 4 + w;
-        if (grp >= L.ngroups) return;
-        double sp = 0.0, tp = 0.0;
-        Site x;
-        if (group_site(L.g, grp, lane, x)) plaquette_site(L.g, U, x, sp, tp);
-        sp = wave_sum(sp);
-        tp = wave_sum(tp);
-        if (lane == 0) {
-            L.partials[grp] = sp;
-            L.partials[L.ngroups + grp] = tp;
-        }
-    } else {
-        const LinksWO<R, NR> O{nullptr, L.g.S};
-        ape_group<R, NR, kPlaqOnly>(L.g, U, O, a.c1, a.c2, 0xFu, L.partials, b - L.pbase, w, lane);
-    }
+    plaquette_wave(L.g, LinksRO<R, NR>{(const vec2_t<R> *)L.out, L.g.S}, b - L.pbase, w, lane, L.partials);
 }
 
 // One block per lattice: its partials reduced exactly as the two
@@ -206,7 +190,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_batched_fin(const BatchLat *__
 
 int batched_max_stage_groups() { return kBatchMaxStage * kFinPerBlock / 4; }
 
-int batched_plaq_blocks(int prec, int ngroups) { return prec == 0 ? ngroups : (ngroups + 3) / 4; }
+int batched_plaq_blocks(int, int ngroups) { return ngroups; }
 
 template <typename R, int NR> static hipError_t resident(int gpb, int *per_cu) {
     if (gpb == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ape_batched<R, NR, 2>, 512, 0);
@@ -234,8 +218,8 @@ static void launch_all(const BatchArgs &a, int block, int grid, hipStream_t st) 
     if (block == 512) k_ape_batched<R, NR, 2><<<grid, 512, 0, st>>>(a, a.lats);
     else k_ape_batched<R, NR, 1><<<grid, 256, 0, st>>>(a, a.lats);
     if (a.plaq) {
-        k_batched_plaq<R, NR><<<a.plaq_blocks, 256, 0, st>>>(a, a.lats);
-        k_batched_fin<<<a.n_lat, kReduceBlock, 0, st>>>(a.lats, sizeof(R) == 4 ? 1 : 4, a.plaq);
+        k_batched_plaq<R, NR><<<a.plaq_blocks, 64 * kPlaqWavesPerGroup, 0, st>>>(a, a.lats);
+        k_batched_fin<<<a.n_lat, kReduceBlock, 0, st>>>(a.lats, kPlaqWavesPerGroup, a.plaq);
     }
 }
 

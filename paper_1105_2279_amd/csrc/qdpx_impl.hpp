@@ -68,8 +68,9 @@ hipError_t launch_hop(const Geo &g, int prec, int nrows, const void *U, const vo
 hipError_t launch_finalize(const double *partials, int n, int mode, double volume, double *out, hipStream_t st);
 
 // ---- ape.hip
-// One APE step.  mode 0: links only; mode 1: also the plaquette traces of
-// the INPUT links into partials; mode 2: only those traces (Uout unused).
+// One APE step.  mode 0: links only; mode 1 (FP64 links, Gram-Schmidt
+// projection, every direction smeared): also the plaquette traces of the
+// INPUT links into partials.
 // partials hold ape_num_partials(g) values per component (spatial,
 // temporal), reduced by launch_finalize(partials, ape_num_partials(g), 1, V, out).
 int ape_num_partials(const Geo &g);

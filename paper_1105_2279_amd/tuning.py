@@ -11,7 +11,9 @@ table stored with the package for the benchmark's shapes.
 
     python -m paper_1105_2279_amd.tuning [--out PATH]
 
-tunes the shapes listed in ``SHAPES`` on the current GPU into that table.
+tunes the shapes listed in ``SHAPES``, and the batched call on the
+benchmark's batch of 64 lattices (``BATCH_FORMATS``), on the current GPU into
+that table.  Batched entries are keyed by the first lattice's extents.
 """
 
 from __future__ import annotations
@@ -20,11 +22,12 @@ import argparse
 import json
 import os
 
-from . import (F32, F64, LINK12, LINK18, OP_APE, OP_CHAIN, OP_JACOBI, OP_SHIFT, Context, _tune_get, qdpx_tune)
+from . import (F32, F64, LINK12, LINK18, OP_APE, OP_BATCHED, OP_CHAIN, OP_JACOBI, OP_SHIFT, Context, _tune_get,
+               qdpx_tune, qdpx_tune_batched)
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_table_mi355x.json")
 
-_OPS = {"APE": OP_APE, "SHIFT": OP_SHIFT, "CHAIN": OP_CHAIN, "JACOBI": OP_JACOBI}
+_OPS = {"APE": OP_APE, "SHIFT": OP_SHIFT, "CHAIN": OP_CHAIN, "JACOBI": OP_JACOBI, "BATCHED": OP_BATCHED}
 _PRECS = {"F64": F64, "F32": F32}
 _FMTS = {"LINK18": LINK18, "LINK12": LINK12}
 _FORMATS = (("F32", "LINK12"), ("F64", "LINK18"), ("F32", "LINK18"))
@@ -34,6 +37,9 @@ _TABLE1 = ((8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 32), (20, 20, 20, 40), 
 SHAPES = ([("APE", p, f, (32, 32, 32, 64)) for p, f in _FORMATS]
           + [("SHIFT", p, f, (32, 32, 32, 64)) for p, f in _FORMATS]
           + [("JACOBI", p, f, L) for L in _TABLE1 for p, f in _FORMATS])
+# The batched call: 5 APE steps over the benchmark's 64 lattices.
+BATCH_FORMATS = (("F32", "LINK12"), ("F64", "LINK18"))
+BATCH_STEPS = 5
 
 
 def _key(op, prec, fmt, L):
@@ -79,6 +85,16 @@ def main():
         qdpx_tune(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])  # written to the table by the library
         cfg, _ = _tune_get(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])
         print(f"{op} {prec} {fmt} {L}: {cfg}", flush=True)
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from latgen import batch_extents  # the benchmark's batch of extents
+
+    Ls = batch_extents()
+    for prec, fmt in BATCH_FORMATS:
+        qdpx_tune_batched(ctx, Ls, _PRECS[prec], _FMTS[fmt], BATCH_STEPS)
+        cfg, _ = _tune_get(ctx, OP_BATCHED, Ls[0], _PRECS[prec], _FMTS[fmt])
+        print(f"BATCHED {prec} {fmt} {len(Ls)} lattices from {tuple(Ls[0])}: {cfg}", flush=True)
     ctx.close()
     print(f"wrote {args.out}", flush=True)
 
