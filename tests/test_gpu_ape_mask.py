@@ -64,13 +64,18 @@ def test_masked_links_do_not_depend_on_plaquette_request(prec, fmt):
 
 @pytest.mark.parametrize("prec,fmt", FORMATS, ids=FORMAT_IDS)
 def test_plaquette_pass_equals_fused(prec, fmt):
-    """The input plaquette from the separate pass (partial mask) equals, bit
-    for bit, the one fused into the full-mask smearing kernel."""
+    """The input plaquette with a partial mask (always the plaquette pass)
+    equals the full-mask one: bit for bit for FP32 links (the same pass), to
+    FP64 rounding for FP64 links (whose full-mask steps fuse it into the step
+    kernel through the row identity)."""
     L = (8, 8, 8, 8)
     U = latgen.haar_links(L, 4300)
     _, _, p_masked = run(L, U, prec, fmt, 1, 0x7)
     _, _, p_full = run(L, U, prec, fmt, 1, 0xF)
-    assert np.array_equal(p_masked[0], p_full[0])
+    if prec == q.F32:
+        assert np.array_equal(p_masked[0], p_full[0])
+    else:
+        assert np.max(np.abs(p_masked[0] - p_full[0])) < 1e-14
 
 
 def test_full_mask_is_the_default():
