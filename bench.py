@@ -102,8 +102,9 @@ def parse():
     p.add_argument("--profile", action="store_true",
                    help="short run for hardware-counter profiling: one 1 GiB device copy (the calibration "
                         "kernel of known size), then two plaquette-free calls and two timed steps (10 APE steps and "
-                        "the plaquette) of each APE link format, then four Jacobi hop launches per format; no JSON "
-                        "line")
+                        "the plaquette) of each APE link format, then four Jacobi hop launches per format, four "
+                        "shift-expression launches (FP64-18, FP32-12), two batched calls on the 64-lattice batch "
+                        "(FP32-12, FP64-18); no JSON line")
     return p.parse_args()
 
 
@@ -232,6 +233,10 @@ def main():
                 q.qdpx_eval_hop(ctx, L, prec, fmt, dev_links[name], pd, h, 0xF, stream)
             torch.cuda.synchronize()
             del pd, h
+        # the shift expression of the bench line, four launches per format
+        profile_shift(torch, q, ctx, dev, stream, latgen)
+        # the batched call on the 64-lattice batch, two calls per format
+        profile_batched(torch, q, ctx, dev, stream, latgen)
         torch.cuda.synchronize()
         log("profile run done")
         ctx.close()
@@ -321,6 +326,7 @@ def main():
     roofline = roof("f32_12")
 
     # --------------------------------------------------------- extras
+    batch_check = None
     extras = {
         "fp64_18_link_updates_per_s": results["f64_18"],
         "fp32_18_link_updates_per_s": results["f32_18"],
@@ -348,7 +354,8 @@ def main():
     }
     if not args.no_extras:
         extras.update(shift_extras(torch, q, ctx, dev, stream, latgen, np))
-        extras.update(batched_extras(torch, q, ctx, dev, stream, latgen))
+        bx, batch_check = batched_extras(torch, q, ctx, dev, stream, latgen)
+        extras.update(bx)
         extras.update(jacobi_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(jit_extras(torch, q, ctx, dev, stream, latgen))
         extras.update(pack_extras(torch, q, ctx, dev, stream, latgen, U))
@@ -359,6 +366,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu, oracle_err = cpu_baseline(U, steps, samp_sites, samp_mus)
         extras["errors_per_step_32x32x32x64"].update(oracle_err)
+        if batch_check is not None:
+            extras["batched_64_lattices"].update(batch_oracle_check(batch_check))
         extras["cpu_oracle_host"] = cpu_host_context(latgen)
 
     line = {
@@ -389,6 +398,75 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+SHIFT_FORMATS = (("f64_18", "F64", "LINK18", 1152), ("f32_12", "F32", "LINK12", 480))
+
+
+_SHIFT_HOST = {}
+
+
+def shift_inputs(torch, q, ctx, dev, latgen, Ls, prec, fmt):
+    """Links, psi and phi of the shift expression on the device (host arrays generated once per shape)."""
+    if Ls not in _SHIFT_HOST:
+        seeds = latgen.SEEDS["shift_16x16x16x32"]
+        _SHIFT_HOST[Ls] = (latgen.haar_links(Ls, seeds["links"]), latgen.dirac_field(Ls, seeds["psi"]),
+                           latgen.dirac_field(Ls, seeds["phi"]))
+    U, psi, phi = _SHIFT_HOST[Ls]
+    return (q.links_to_device(ctx, Ls, U, prec, fmt, dev), q.fermion_to_device(ctx, Ls, psi, prec, dev),
+            q.fermion_to_device(ctx, Ls, phi, prec, dev))
+
+
+def profile_shift(torch, q, ctx, dev, stream, latgen):
+    Ls = (32, 32, 32, 64)
+    for name, p, f, _ in SHIFT_FORMATS:
+        prec, fmt = getattr(q, p), getattr(q, f)
+        Ud, pd, fd = shift_inputs(torch, q, ctx, dev, latgen, Ls, prec, fmt)
+        chi = q.alloc_fermion(Ls, prec, dev)
+        n2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
+        cfg, src = tuning_ensure(q, ctx, q.OP_SHIFT, prec, fmt, Ls)
+        log(f"profile shift {name}: launch {cfg} ({src})")
+        for _ in range(4):
+            q.qdpx_eval_shift_mul_axpy(ctx, Ls, prec, fmt, Ud, pd, fd, 0.3, chi, n2, work, stream)
+        torch.cuda.synchronize()
+        del Ud, pd, fd, chi, work
+
+
+def profile_batched(torch, q, ctx, dev, stream, latgen):
+    """The batched call on the benchmark's 64 lattices, two calls per format.
+    The counters measure cost, which does not depend on the link values, so
+    the links are drawn from one pool of 2^20 Haar matrices instead of
+    generated lattice by lattice (seconds instead of a minute per pass)."""
+    import numpy as np
+
+    Ls = latgen.batch_extents()
+    pool = latgen.haar_su3(np.random.default_rng(latgen.SEEDS["batch_64"]["first_lattice"]), 1 << 20)
+
+    def links(i, L):
+        n = 4 * latgen.volume(L)
+        idx = (np.arange(n, dtype=np.int64) * 7919 + 104729 * i) % len(pool)
+        return pool[idx].reshape(L[3], L[2], L[1], L[0], 4, 3, 3)
+
+    for name, prec, fmt in (("f32_12", q.F32, q.LINK12), ("f64_18", q.F64, q.LINK18)):
+        src = q.qdpx_tune_source(ctx, q.OP_BATCHED, Ls[0], prec, fmt)
+        if src == "default":  # tuning launches the same kernels: keep them out of the counted run
+            raise SystemExit("profile: the launch table holds no batched entry for this batch; run the tuner first")
+        Uds = [q.links_to_device(ctx, L, links(i, L), prec, fmt, dev) for i, L in enumerate(Ls)]
+        outs = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
+        plaq = torch.zeros(3 * len(Ls), dtype=torch.float64, device=dev)
+        work = q.alloc_workspace(q.OP_BATCHED, Ls, prec, fmt, len(Ls), dev)
+        log(f"profile batched {name}: launch {q.qdpx_tune_get(ctx, q.OP_BATCHED, Ls[0], prec, fmt)} ({src})")
+        for _ in range(2):
+            q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, 5, plaq, work, stream)
+        torch.cuda.synchronize()
+        del Uds, outs, work
+
+
+def tuning_ensure(q, ctx, op, prec, fmt, Ls):
+    from paper_1105_2279_amd import tuning
+
+    return tuning.ensure(ctx, op, prec, fmt, Ls)
 
 
 def pack_extras(torch, q, ctx, dev, stream, latgen, U):
@@ -423,14 +501,9 @@ def shift_extras(torch, q, ctx, dev, stream, latgen, np):
     Ls = (32, 32, 32, 64)
     V = latgen.volume(Ls)
     out = {}
-    seeds = latgen.SEEDS["shift_16x16x16x32"]
-    U = latgen.haar_links(Ls, seeds["links"])
-    psi = latgen.dirac_field(Ls, seeds["psi"])
-    phi = latgen.dirac_field(Ls, seeds["phi"])
-    for name, prec, fmt, bytes_site in (("f64_18", q.F64, q.LINK18, 1152), ("f32_12", q.F32, q.LINK12, 480)):
-        Ud = q.links_to_device(ctx, Ls, U, prec, fmt, dev)
-        pd = q.fermion_to_device(ctx, Ls, psi, prec, dev)
-        fd = q.fermion_to_device(ctx, Ls, phi, prec, dev)
+    for name, p, f, bytes_site in SHIFT_FORMATS:
+        prec, fmt = getattr(q, p), getattr(q, f)
+        Ud, pd, fd = shift_inputs(torch, q, ctx, dev, latgen, Ls, prec, fmt)
         chi = q.alloc_fermion(Ls, prec, dev)
         n2 = torch.zeros(1, dtype=torch.float64, device=dev)
         work = q.alloc_workspace(q.OP_SHIFT, Ls, prec, fmt, 1, dev)
@@ -711,62 +784,90 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
 
 def batched_extras(torch, q, ctx, dev, stream, latgen):
     """64 lattices with extents drawn from 8^4, 12^3x24, 16^3x32, 24^3x48; 5 APE
-    steps + final plaquettes, FP32-12: one persistent launch replayed from a
-    captured HIP graph, against the loop of 64 single-lattice calls."""
-    prec, fmt, n = q.F32, q.LINK12, 5
+    steps + final FP64 plaquettes, FP32-12 and FP64-18: the batched call (its
+    launch geometry from the autotuner on this batch) replayed from a
+    captured HIP graph, against the loop of 64 single-lattice calls (5 steps
+    and the plaquette of the result each) in both formats.  Returns the
+    extras and lattice 0's links (input, FP32-12 and FP64-18 results) for the
+    oracle check of the cpu_baseline leg."""
+    import numpy as np
+
+    n = 5
     Ls = latgen.batch_extents()
     seed0 = latgen.SEEDS["batch_64"]["first_lattice"]
     t = time.time()
-    Uds = [q.links_to_device(ctx, L, latgen.haar_links(L, seed0 + i), prec, fmt, dev) for i, L in enumerate(Ls)]
+    hosts = [latgen.haar_links(L, seed0 + i) for i, L in enumerate(Ls)]
     log(f"batched: generated 64 lattices in {time.time() - t:.1f} s")
     sites = sum(latgen.volume(L) for L in Ls)
     updates = 4.0 * sites * n
-    outs = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
-    plaq = torch.zeros(3 * len(Ls), dtype=torch.float64, device=dev)
-    work = q.alloc_workspace(q.OP_BATCHED, Ls, prec, fmt, len(Ls), dev)
-
-    def batched():
-        q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, stream)
-
-    batched()  # first call builds the device table
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    s = torch.cuda.Stream()
-    s.wait_stream(stream)
-    with torch.cuda.graph(g, stream=s):
-        q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, s)
-    g.replay()
-    torch.cuda.synchronize()
     reps = 10
-    ms_graph = time_calls(torch, g.replay, reps, stream) / reps
-    status = int(work[4:8].cpu().numpy().view("uint32")[0])
+    res, check = {}, {"U": hosts[0], "L": Ls[0]}
+    for name, prec, fmt in (("f32_12", q.F32, q.LINK12), ("f64_18", q.F64, q.LINK18)):
+        Uds = [q.links_to_device(ctx, L, U, prec, fmt, dev) for L, U in zip(Ls, hosts)]
+        # launch geometry: the stored one for this batch, else the autotuner now
+        src = q.qdpx_tune_source(ctx, q.OP_BATCHED, Ls[0], prec, fmt)
+        if src == "default":
+            q.qdpx_tune_batched(ctx, Ls, prec, fmt, n)
+            src = q.qdpx_tune_source(ctx, q.OP_BATCHED, Ls[0], prec, fmt)
+        geometry = q.qdpx_tune_get(ctx, q.OP_BATCHED, Ls[0], prec, fmt)
+        outs = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
+        plaq = torch.zeros(3 * len(Ls), dtype=torch.float64, device=dev)
+        work = q.alloc_workspace(q.OP_BATCHED, Ls, prec, fmt, len(Ls), dev)
+        q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, stream)  # builds the table
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.graph(g, stream=cs):
+            q.qdpx_ape_smear_batched(ctx, Ls, prec, fmt, Uds, outs, ALPHA, n, plaq, work, cs)
+        g.replay()
+        torch.cuda.synchronize()
+        ms_graph = time_calls(torch, g.replay, reps, stream) / reps
+        status = int(work[4:8].cpu().numpy().view("uint32")[0])
 
-    loop_out = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
-    loop_plaq = [torch.zeros(3 * (n + 1), dtype=torch.float64, device=dev) for _ in Ls]
-    loop_work = [q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev) for L in Ls]
+        loop_out = [q.alloc_links(L, prec, fmt, dev) for L in Ls]
+        loop_plaq = [torch.zeros(3, dtype=torch.float64, device=dev) for _ in Ls]
+        loop_work = [q.alloc_workspace(q.OP_APE, L, prec, fmt, n, dev) for L in Ls]
+        loop_wp = [q.alloc_workspace(q.OP_PLAQ, L, prec, fmt, 1, dev) for L in Ls]
 
-    def loop():
-        for i, L in enumerate(Ls):
-            q.qdpx_ape_smear(ctx, L, prec, fmt, Uds[i], loop_out[i], ALPHA, n, loop_plaq[i], loop_work[i], stream)
+        def loop():
+            for i, L in enumerate(Ls):
+                q.qdpx_ape_smear(ctx, L, prec, fmt, Uds[i], loop_out[i], ALPHA, n, None, loop_work[i], stream)
+                q.qdpx_plaquette(ctx, L, prec, fmt, loop_out[i], loop_plaq[i], loop_wp[i], stream)
 
-    loop()
-    torch.cuda.synchronize()
-    ms_loop = time_calls(torch, loop, reps, stream) / reps
-    same = all(torch.equal(plaq[3 * i:3 * i + 3], loop_plaq[i][3 * n:3 * n + 3]) for i in range(len(Ls)))
-    log(f"batched: graph {ms_graph:.2f} ms, loop {ms_loop:.2f} ms, status {status}, identical plaquettes {same}")
-    return {
-        "batched_64_lattices": {
-            "sites": sites,
-            "ape_steps": n,
+        loop()
+        torch.cuda.synchronize()
+        ms_loop = time_calls(torch, loop, reps, stream) / reps
+        same_links = all(np.array_equal(q.links_to_host(ctx, L, a, prec, fmt).view(np.float64),
+                                        q.links_to_host(ctx, L, b, prec, fmt).view(np.float64))
+                         for L, a, b in zip(Ls[:8], outs[:8], loop_out[:8]))
+        same_plaq = all(torch.equal(plaq[3 * i:3 * i + 3], loop_plaq[i]) for i in range(len(Ls)))
+        check[name] = q.links_to_host(ctx, Ls[0], outs[0], prec, fmt)
+        res[name] = {
+            "launch": {"block": geometry[0], "groups_per_ticket": geometry[1], "source": src},
             "link_updates_per_s_persistent_graph": updates / (ms_graph / 1e3),
             "link_updates_per_s_per_lattice_loop": updates / (ms_loop / 1e3),
             "ms_persistent_graph": ms_graph,
             "ms_per_lattice_loop": ms_loop,
             "speedup_vs_loop": ms_loop / ms_graph,
             "status": status,
-            "final_plaquettes_identical_to_loop": bool(same),
+            "links_identical_to_loop_first_8_lattices": bool(same_links),
+            "final_plaquettes_identical_to_loop": bool(same_plaq),
         }
-    }
+        log(f"batched {name}: graph {ms_graph:.2f} ms, loop {ms_loop:.2f} ms, geometry {geometry} ({src}), "
+            f"status {status}, identical links {same_links}, plaquettes {same_plaq}")
+        del Uds, outs, work, loop_out, loop_work, loop_wp, g
+    d32 = float(abs(check["f32_12"] - check["f64_18"]).max())
+    return {
+        "batched_64_lattices": {
+            "sites": sites,
+            "ape_steps": n,
+            **res,
+            "speedup_batched_f32_12_vs_f64_18_loop": res["f64_18"]["ms_per_lattice_loop"] / res["f32_12"]["ms_persistent_graph"],
+            "speedup_batched_f32_12_vs_batched_f64_18": res["f64_18"]["ms_persistent_graph"] / res["f32_12"]["ms_persistent_graph"],
+            "lattice0_max_abs_f32_12_minus_f64_18": d32,
+        }
+    }, check
 
 
 def cpu_baseline(U, steps, samp_sites, samp_mus):
@@ -812,6 +913,20 @@ def cpu_baseline(U, steps, samp_sites, samp_mus):
         "sample": f"{n} FP64 APE steps over the full {L[0]}^3x{L[3]} lattice ({4 * V * n} link updates) "
                   f"in {t:.2f} s",
     }, err
+
+
+def batch_oracle_check(check):
+    """Part of the cpu_baseline leg: the FP64 oracle's 5 steps on lattice 0 of
+    the batch against both formats' batched results."""
+    import numpy as np
+
+    import oracle
+
+    ref = oracle.ape_smear(check["U"], ALPHA, 5)
+    e32 = float(np.max(np.abs(check["f32_12"] - ref)))
+    e64 = float(np.max(np.abs(check["f64_18"] - ref)))
+    log(f"batch lattice 0 {check['L']}: oracle error FP32-12 {e32:.2e}, FP64 {e64:.2e}")
+    return {"lattice0": list(check["L"]), "lattice0_oracle_max_abs_f32_12": e32, "lattice0_oracle_max_abs_f64_18": e64}
 
 
 def error_sample(np, V, n=4096, seed=1305 + 77):
