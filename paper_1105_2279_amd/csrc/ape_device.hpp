@@ -289,21 +289,25 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
             M3<R> C;
             U.full(nu, s_mu, C);
             if (nu < mu) {
-            M23<R> X;
+                // Two wave-uniform code paths (this staple formed on its own,
+                // then added) keep the compiler from scheduling the plane as
+                // one block: 73 registers instead of 96 for LINK12 (six waves
+                // per SIMD instead of five, 3 % faster as measured).
+                M23<R> X;
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
-            acc_23_33dag(X, T, C);
+                    for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
+                acc_23_33dag(X, T, C);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    S.e[i][j].re += X.e[i][j].re;
-                    S.e[i][j].im += X.e[i][j].im;
-                }
+                    for (int j = 0; j < 3; ++j) {
+                        S.e[i][j].re += X.e[i][j].re;
+                        S.e[i][j].im += X.e[i][j].im;
+                    }
             } else {
-            acc_23_33dag(S, T, C);
+                acc_23_33dag(S, T, C);
             }
         }
         // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
