@@ -38,19 +38,22 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.64
 
 # Algorithmic work per link update of one APE step as implemented (rows 0
-# and 1 of the six staples, combination, FP64 projection, and for LINK12 the
-# rebuild of row 2 of the 15 full links each update loads).
+# and 1 of the six staples, combination, FP64 projection, and the rebuild of
+# row 2 of the links it reads as rows 0 and 1: the 15 full links of each
+# FP32-12 update, the 10 links each FP64 update reads (one backward link,
+# three per plane)).
 STAPLE_FLOPS = 6 * 2 * 18 * 8  # 6 staples x 2 products x 18 complex FMA x 8 flop
 COMBINE_FLOPS = 12 * 2 * 3
 PROJECT_FLOPS = 126
-REBUILD_FLOPS = 15 * 42
+REBUILD_FLOPS = 42
 FLOPS_PER_LINK = {
-    "f32_12": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + REBUILD_FLOPS,
-    "f64_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS,
+    "f32_12": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + 15 * REBUILD_FLOPS,
+    "f64_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + 10 * REBUILD_FLOPS,
     "f32_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS,
 }
-# Compulsory HBM bytes per link update: read the link once, write it once.
-BYTES_PER_LINK = {"f32_12": 2 * 48, "f64_18": 2 * 144, "f32_18": 2 * 72}
+# Compulsory HBM bytes per link update: read the link once (the FP64 step
+# reads rows 0 and 1 only), write it once.
+BYTES_PER_LINK = {"f32_12": 2 * 48, "f64_18": 96 + 144, "f32_18": 2 * 72}
 
 
 def log(*a):
@@ -647,8 +650,9 @@ N_CHAIN = 8
 
 
 def large_extras(torch, q, ctx, dev, stream, latgen, np):
-    """The large single lattice, 48^3x96: 20 APE steps with the plaquette of
-    every step, then the fused shift-expression chain psi <- psi - 0.1 chi,
+    """The large single lattice, 48^3x96: 20 APE steps and the plaquette of
+    the result (the per-step plaquettes from one more, untimed call), then
+    the fused shift-expression chain psi <- psi - 0.1 chi,
     chi = sum_mu U_mu(x) psi(x+mu) + 0.3 phi, 8 times on the smeared links;
     FP32-12 (FP64 projection and reductions) against the plain FP64-18 GPU
     path.  Haar links are timed (each call replayed from a HIP graph) and
@@ -672,7 +676,9 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
         Ud = q.links_to_device(ctx, Ls, U, prec, fmt, dev)
         Vd = q.alloc_links(Ls, prec, fmt, dev)
         work = q.alloc_workspace(q.OP_APE, Ls, prec, fmt, N_LARGE_APE, dev)
+        work_p = q.alloc_workspace(q.OP_PLAQ, Ls, prec, fmt, 1, dev)
         plaq = torch.zeros(3 * (N_LARGE_APE + 1), dtype=torch.float64, device=dev)
+        plaq_end = torch.zeros(3, dtype=torch.float64, device=dev)
         pd = q.fermion_to_device(ctx, Ls, psi, prec, dev)
         pd0 = pd.clone()
         fd = q.fermion_to_device(ctx, Ls, phi, prec, dev)
@@ -680,7 +686,11 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
         cwork = q.alloc_workspace(q.OP_CHAIN, Ls, prec, fmt, N_CHAIN, dev)
         torch.cuda.synchronize()
         graphs = []
-        for fn in (lambda st: q.qdpx_ape_smear(ctx, Ls, prec, fmt, Ud, Vd, ALPHA, N_LARGE_APE, plaq, work, st),
+        def smear_and_plaquette(st):
+            q.qdpx_ape_smear(ctx, Ls, prec, fmt, Ud, Vd, ALPHA, N_LARGE_APE, None, work, st)
+            q.qdpx_plaquette(ctx, Ls, prec, fmt, Vd, plaq_end, work_p, st)
+
+        for fn in (smear_and_plaquette,
                    lambda st: q.qdpx_shift_chain(ctx, Ls, prec, fmt, Vd, pd, fd, 0.3, 0.1, N_CHAIN, norms, cwork,
                                                  st)):
             g = torch.cuda.CUDAGraph()
@@ -695,8 +705,10 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
         torch.cuda.synchronize()
         ms_ape = time_calls(torch, g_ape.replay, 3, stream) / 3
         ms_chain = time_calls(torch, g_chain.replay, 3, stream) / 3
-        # the results: the smeared links are those of every replay; the chain
+        # the results: the smeared links are those of every replay (and of
+        # the untimed call that reports every step's plaquette); the chain
         # runs once more from the initial psi
+        q.qdpx_ape_smear(ctx, Ls, prec, fmt, Ud, Vd, ALPHA, N_LARGE_APE, plaq, work, stream)
         pd.copy_(pd0)
         g_chain.replay()
         torch.cuda.synchronize()
@@ -708,7 +720,9 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
         ups = 4.0 * V * N_LARGE_APE / (ms_ape / 1e3)
         res[name] = {
             "launch": {k: {"geometry": v[0], "source": v[1]} for k, v in launch.items()},
-            "ape_20_steps_ms": round(ms_ape, 3),
+            "ape_20_steps_and_plaquette_ms": round(ms_ape, 3),
+            "final_plaquette_of_timed_call": [float(x) for x in plaq_end.cpu().numpy()],
+            "final_plaquette_equals_per_step_call": bool(torch.equal(plaq_end, plaq[-3:])),
             "ape_link_updates_per_s": ups,
             "ape_hbm_gbs_algorithmic": round(2 * link_b * ups / 1e9, 1),
             "chain_8_iterations_ms": round(ms_chain, 3),
@@ -719,9 +733,9 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
             "max_det_defect": d,
             "chain_norms": norms_out[name].tolist(),
         }
-        log(f"large {name}: 20 APE steps {ms_ape:.2f} ms ({ups / 1e9:.2f} G link-updates/s), chain "
+        log(f"large {name}: 20 APE steps + plaquette {ms_ape:.2f} ms ({ups / 1e9:.2f} G link-updates/s), chain "
             f"{ms_chain:.2f} ms ({res[name]['chain_hbm_gbs_algorithmic']} GB/s)")
-        del Ud, Vd, work, pd, pd0, fd, cwork, g_ape, g_chain, graphs
+        del Ud, Vd, work, work_p, pd, pd0, fd, cwork, g_ape, g_chain, graphs
     d_links = float((full["f32_12"] - full["f64_18"]).abs().max())
     dpsi = psi_out["f32_12"] - psi_out["f64_18"]
     ref = psi_out["f64_18"]

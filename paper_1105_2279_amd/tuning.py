@@ -9,7 +9,7 @@ re-tuning (and timing and counter runs measure the same kernels).  Entries
 are keyed by (operation, precision, link format, extents).  ``TABLE`` is the
 table stored with the package for the benchmark's shapes.
 
-    python -m paper_1105_2279_amd.tuning [--out PATH]
+    python -m paper_1105_2279_amd.tuning [--out PATH] [--missing]
 
 tunes the shapes listed in ``SHAPES``, and the batched call on the
 benchmark's batch of 64 lattices (``BATCH_FORMATS``), on the current GPU into
@@ -36,7 +36,8 @@ _TABLE1 = ((8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 32), (20, 20, 20, 40), 
 # The shapes the benchmark launches.
 SHAPES = ([("APE", p, f, (32, 32, 32, 64)) for p, f in _FORMATS]
           + [("SHIFT", p, f, (32, 32, 32, 64)) for p, f in _FORMATS]
-          + [("JACOBI", p, f, L) for L in _TABLE1 for p, f in _FORMATS])
+          + [("JACOBI", p, f, L) for L in _TABLE1 for p, f in _FORMATS]
+          + [(op, p, f, (48, 48, 48, 96)) for op in ("APE", "CHAIN") for p, f in _FORMATS[:2]])
 # The batched call: 5 APE steps over the benchmark's 64 lattices.
 BATCH_FORMATS = (("F32", "LINK12"), ("F64", "LINK18"))
 BATCH_STEPS = 5
@@ -76,12 +77,16 @@ def ensure(ctx, op, prec, fmt, L):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--missing", action="store_true", help="tune only the shapes the table does not hold yet")
     args = ap.parse_args()
     import torch
 
     torch.cuda.init()
     ctx = Context(0, tune_cache=args.out)
+    have = read(args.out) if args.missing else {}
     for op, prec, fmt, L in SHAPES:
+        if _key(op, prec, fmt, L) in have:
+            continue
         qdpx_tune(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])  # written to the table by the library
         cfg, _ = _tune_get(ctx, _OPS[op], L, _PRECS[prec], _FMTS[fmt])
         print(f"{op} {prec} {fmt} {L}: {cfg}", flush=True)
@@ -92,6 +97,8 @@ def main():
 
     Ls = batch_extents()
     for prec, fmt in BATCH_FORMATS:
+        if _key("BATCHED", prec, fmt, Ls[0]) in have:
+            continue
         qdpx_tune_batched(ctx, Ls, _PRECS[prec], _FMTS[fmt], BATCH_STEPS)
         cfg, _ = _tune_get(ctx, OP_BATCHED, Ls[0], _PRECS[prec], _FMTS[fmt])
         print(f"BATCHED {prec} {fmt} {len(Ls)} lattices from {tuple(Ls[0])}: {cfg}", flush=True)
