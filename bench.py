@@ -156,7 +156,7 @@ def main():
     tuned = {}
     for name, (prec, fmt) in paths.items():
         cfg, src = tuning.ensure(ctx, q.OP_APE, prec, fmt, L)
-        tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window"), cfg), source=src)
+        tuned[name] = dict(zip(("block", "groups_per_wave", "xcd_map", "t_window", "lds_tile"), cfg), source=src)
         log(f"APE {name} launch: {tuned[name]}")
 
     works = {}

@@ -122,8 +122,9 @@ typedef struct qdpx_ctx qdpx_ctx;
  *   this context and by qdpx_tune_save.  Format: JSON
  *   {"device": "<gcnArchName>", "entries": [{"op": "APE", "prec": "F32",
  *   "fmt": "LINK12", "L": [Lx, Ly, Lz, Lt], "launch": [block,
- *   groups_per_wave, xcd_map, t_window]}, ...]}, op one of SHIFT CHAIN APE
- *   PLAQ BATCHED JACOBI, prec F64 or F32, fmt LINK18 or LINK12.
+ *   groups_per_wave, xcd_map, t_window, lds_tile]}, ...]}, op one of SHIFT
+ *   CHAIN APE PLAQ BATCHED JACOBI, prec F64 or F32, fmt LINK18 or LINK12
+ *   (a four-element "launch" is read with the default lds_tile).
  *   With the environment variable QDPX_LOG set (not "" or "0") the library
  *   prints one line on stderr per table read or write and per tuned geometry.
  * Returns QDPX_EINVAL for a null `out`, a device that does not exist, or a
@@ -400,7 +401,14 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * wave, the block order over the 8 XCDs (xcd_map 0: dispatch order; 1: each
  * XCD a contiguous range of groups; 2: each XCD a slab of z planes walked t
  * plane by t plane, used where the groups of a t plane split evenly over the
- * XCDs, else order 0), and the number of t planes walked together.
+ * XCDs, else order 0), the number of t planes walked together, and the LDS
+ * tile of the FP32 APE step with the Gram-Schmidt projection (lds_tile 0:
+ * every link loaded through the caches; 1: each 64-site group's own links,
+ * rows 0 and 1, staged in LDS once for the four direction waves; 2: also
+ * every site's backward links U_mu(x-mu), columns 0 and 1, which the lower
+ * staples of the other three directions read; 0 in every other case: the
+ * FP64 step always exchanges backward links through LDS, and the shift, hop
+ * and chain kernels meet their per-direction partial sums there).
  * This is the auto-tuning of the thread geometry the paper proposes
  * (sections 5.4 and 9).  Allocates and frees temporary device buffers and
  * synchronises the device, so it returns QDPX_ECAPTURE on a capturing
@@ -409,7 +417,8 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * qdpx_tune_get / qdpx_tune_set read and write the remembered choice
  * (every output pointer of qdpx_tune_get is nullable; *source receives 0
  * for the default geometry, 1 for one read from the launch table, 2 for one
- * qdpx_tune found, 3 for one qdpx_tune_set gave);
+ * qdpx_tune found, 3 for one qdpx_tune_set gave; a launch table written
+ * without lds_tile gives the default, 2 for the FP32 APE step, else 0);
  * t_window must divide Lt and only matters when Lx is a multiple of 8 and Ly
  * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED (tuned by
  * qdpx_tune_batched, which qdpx_tune refuses with QDPX_EUNSUPPORTED) block is
@@ -419,9 +428,9 @@ int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, 
               void *stream);
 int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                   int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window,
-                  int32_t *source);
+                  int32_t *lds_tile, int32_t *source);
 int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                  int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window);
+                  int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window, int32_t lds_tile);
 /* The autotuner of the batched call: times it on this batch of extents
  * (n_lat lattices, n_steps steps, temporary links) with 256- and 512-thread
  * blocks (one or two 64-site groups at a time) and 1, 2, 4 or 8 groups per

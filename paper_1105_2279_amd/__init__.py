@@ -112,11 +112,8 @@ def lib():
         "qdpx_jit_info": (i32, [_P, i32, ctypes.POINTER(i32), _P, sz]),
         "qdpx_jit_eval": (i32, [_P, i32, _G, _P, _P, _P, _P, _P, _P, sz, _P]),
         "qdpx_jacobi_smear": (i32, [_P, _G, i32, i32, _P, _P, dbl, i32, dbl, ctypes.c_uint32, _P, sz, _P]),
-        "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32, ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
-        "qdpx_tune_set": (i32, [_P, i32, _G, i32, i32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                ctypes.c_int32]),
+        "qdpx_tune_get": (i32, [_P, i32, _G, i32, i32] + [ctypes.POINTER(ctypes.c_int32)] * 6),
+        "qdpx_tune_set": (i32, [_P, i32, _G, i32, i32] + [ctypes.c_int32] * 5),
     }
     for name, (res, args) in sig.items():
         f = getattr(h, name)
@@ -348,14 +345,15 @@ TUNE_SOURCES = ("default", "table", "tuned", "set")
 
 
 def _tune_get(ctx, op, L, prec, fmt):
-    b, n, x, t, src = (ctypes.c_int32() for _ in range(5))
+    b, n, x, t, d, src = (ctypes.c_int32() for _ in range(6))
     _check(lib().qdpx_tune_get(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, ctypes.byref(b), ctypes.byref(n),
-                               ctypes.byref(x), ctypes.byref(t), ctypes.byref(src)), "qdpx_tune_get")
-    return (int(b.value), int(n.value), int(x.value), int(t.value)), TUNE_SOURCES[src.value]
+                               ctypes.byref(x), ctypes.byref(t), ctypes.byref(d), ctypes.byref(src)),
+           "qdpx_tune_get")
+    return (int(b.value), int(n.value), int(x.value), int(t.value), int(d.value)), TUNE_SOURCES[src.value]
 
 
 def qdpx_tune_get(ctx, op, L, prec, fmt):
-    """(block, sites_per_thread, xcd_map, t_window) remembered for this case."""
+    """(block, sites_per_thread, xcd_map, t_window, lds_tile) remembered for this case."""
     return _tune_get(ctx, op, L, prec, fmt)[0]
 
 
@@ -368,9 +366,12 @@ def qdpx_tune_save(ctx, path=None):
     _check(lib().qdpx_tune_save(ctx.handle, None if path is None else os.fsencode(path)), "qdpx_tune_save")
 
 
-def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map, t_window=1):
+def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map, t_window=1, lds_tile=None):
+    """lds_tile None: the default (2 for the FP32 APE step, else 0)."""
+    if lds_tile is None:
+        lds_tile = 2 if (op == OP_APE and prec == F32) else 0
     _check(lib().qdpx_tune_set(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, int(block),
-                               int(sites_per_thread), int(xcd_map), int(t_window)), "qdpx_tune_set")
+                               int(sites_per_thread), int(xcd_map), int(t_window), int(lds_tile)), "qdpx_tune_set")
 
 
 # ------------------------------------------------- host <-> device conveniences

@@ -13,7 +13,7 @@ namespace qdpx {
 // are updated by four waves of the same block, which share the neighbour
 // loads in L1/L2; for FP64 links wave w % 4 of group w / 4 takes the four
 // directions of 16 of its sites (ape_group_f64).
-template <typename R, int NR, int NS, int MODE, int PROJ = 0>
+template <typename R, int NR, int NS, int MODE, int PROJ = 0, int LDS = 0>
 __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, LinksWO<R, NR> out, double c1,
                                                   double c2, unsigned mask, double *__restrict__ partials, int xcd,
                                                   int tw) {
@@ -22,38 +22,51 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     const int mu = w & 3;
     const int gpb = blockDim.x >> 8;
     const int ngroups = (g.V + 63) >> 6;
-    // FP32 steps stage each group's four own links (rows 0 and 1) in LDS: the
-    // upper staple of direction nu starts from U_nu(x), the own link of wave
-    // nu, so each site loads it once instead of four times (a sixth fewer
-    // vector-memory instructions; 24 KB of LDS per 512-thread block).
+    // The LDS tile of FP32 steps (LDS = 1): each group's four own links (rows
+    // 0 and 1) staged once, since the upper staple of direction nu starts from
+    // U_nu(x), the own link of wave nu (24 KB per 512-thread block); LDS = 2
+    // adds each site's four backward links U_mu(x-mu) (columns 0 and 1), which
+    // the lower staples of the three other directions all read (another
+    // 24 KB).  Staged values are the ones the loads would give: every LDS
+    // level yields the same bits.
     static_assert(MODE == kApe || sizeof(R) == 8, "FP32 steps take their plaquettes from k_plaquette");
-    constexpr bool kShare = sizeof(R) == 4 && PROJ == 0;
-    if constexpr (kShare) {
-        // the four own links of each group, rows 0 and 1 as three pairs
-        __shared__ nv4_t<R> own[2][4 * 3 * 64];
-        nv4_t<R> *mine = own[w >> 2];
+    static_assert(LDS == 0 || (sizeof(R) == 4 && PROJ == 0), "LDS tiles belong to the FP32 row projection");
+    // Dynamic LDS, sized at launch: kF64BackPerWave double2 per wave (FP64), or
+    // per group the own links then (LDS = 2) the backward links, 4*3*64
+    // FP32 pairs each.
+    extern __shared__ double2 lds_dyn[];
+    if constexpr (LDS > 0) {
+        constexpr int kTile = 4 * 3 * 64;
+        nv4_t<R> *tiles = reinterpret_cast<nv4_t<R> *>(lds_dyn);
+        nv4_t<R> *mine = tiles + (w >> 2) * LDS * kTile;
+        nv4_t<R> *mine_back = LDS == 2 ? mine + kTile : nullptr;
 #pragma unroll 1
         for (int j = 0; j < NS; ++j) {  // no early exit: every wave meets every barrier
             const int i = (tile * NS + j) * gpb + (w >> 2);
             const bool valid = i < ngroups;
             const int grp = !valid ? 0 : xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
             if (j > 0) __syncthreads();  // the previous group's copies have been read
-            if (valid) stage_own_link(g, U, grp, mu, lane, mine);
+            if (valid) {
+                stage_own_link(g, U, grp, mu, lane, mine);
+                if constexpr (LDS == 2) stage_back_link(g, U, grp, mu, lane, mine_back);
+            }
             __syncthreads();
-            if (valid) ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, mine);
+            if (valid)
+                ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, mine, nullptr,
+                                             mine_back);
         }
         return;
     }
     // FP64 steps exchange each lane's backward link through LDS (one
-    // kF64BackPerWave region per wave, sized at launch)
-    extern __shared__ double2 back64[];
+    // kF64BackPerWave region per wave); FP32 steps without an LDS tile load
+    // every link
 #pragma unroll 1
     for (int j = 0; j < NS; ++j) {
         const int i = (tile * NS + j) * gpb + (w >> 2);
         if (i >= ngroups) return;
         const int grp = xcd == 2 ? slabwalk(g, i, gpb * NS) : traverse(g, i, tw);
         ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, nullptr,
-                                     back64 + w * kF64BackPerWave);
+                                     sizeof(R) == 8 ? lds_dyn + w * kF64BackPerWave : nullptr);
     }
 }
 
@@ -71,18 +84,22 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     const int per_block = gpb * cfg.nsite;
     const dim3 grid((groups + per_block - 1) / per_block);
     const int xcd = launch_order(g, cfg, per_block);
-    const size_t lds64 = (prec == 0 && !proj) ? sizeof(double2) * kF64BackPerWave * (cfg.block / 64) : 0;
-#define QDPX_APE_LAUNCH(R, NR, NS, M, P)                                                                        \
-    k_ape_step<R, NR, NS, M, P><<<grid, cfg.block, lds64, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S},  \
-                                                             LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,     \
-                                                             mask, partials, xcd, cfg.tw)
-#define QDPX_APE_M64(NS)                                                       \
-    if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1);                      \
-    else if (mode == kApePlaq) QDPX_APE_LAUNCH(double, 3, NS, kApePlaq, 0); \
-    else QDPX_APE_LAUNCH(double, 3, NS, kApe, 0);
-#define QDPX_APE_M32(NR, NS)                          \
-    if (proj) QDPX_APE_LAUNCH(float, NR, NS, kApe, 1); \
-    else QDPX_APE_LAUNCH(float, NR, NS, kApe, 0);
+    const int lds_level = (prec != 0 && !proj) ? cfg.lds : 0;
+    const size_t lds64 = (prec == 0 && !proj) ? sizeof(double2) * kF64BackPerWave * (cfg.block / 64)
+                                              : (size_t)16 * 4 * 3 * 64 * lds_level * gpb;
+#define QDPX_APE_LAUNCH(R, NR, NS, M, P, T)                                                                      \
+    k_ape_step<R, NR, NS, M, P, T><<<grid, cfg.block, lds64, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S}, \
+                                                                LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,   \
+                                                                mask, partials, xcd, cfg.tw)
+#define QDPX_APE_M64(NS)                                                         \
+    if (proj) QDPX_APE_LAUNCH(double, 3, NS, kApe, 1, 0);                      \
+    else if (mode == kApePlaq) QDPX_APE_LAUNCH(double, 3, NS, kApePlaq, 0, 0); \
+    else QDPX_APE_LAUNCH(double, 3, NS, kApe, 0, 0);
+#define QDPX_APE_M32(NR, NS)                                           \
+    if (proj) QDPX_APE_LAUNCH(float, NR, NS, kApe, 1, 0);              \
+    else if (lds_level == 2) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 2); \
+    else if (lds_level == 1) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 1); \
+    else QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 0);
 #define QDPX_APE_NS(M)                             \
     switch (cfg.nsite) {                           \
     case 2: M(2) break;                            \

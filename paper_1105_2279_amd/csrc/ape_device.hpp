@@ -1,6 +1,7 @@
 // Device-side APE smearing work shared by the single-lattice kernels and
 // the persistent batched kernel: staple sums restricted to rows 0 and 1,
-// the owned-plane plaquette traces and the per-64-site-group step.
+// the per-64-site-group step (with the FP64 step's fused plaquette traces)
+// and the plaquette pass.
 //
 // APE step, per link (x, mu), all from the unsmeared field U:
 //   S = sum_{nu != mu} [ U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu) ]
@@ -262,11 +263,49 @@ __device__ __forceinline__ void stage_own_link(const Geo &g, const LinksRO<R, NR
     }
 }
 
+// Columns 0 and 1 of the backward link U_mu(x-mu) of group grp's sites (row
+// 2 rebuilt for LINK12), all the lower staples of the other three
+// directions read of it, into back[(mu*3 + k)*64 + lane] as (U_k0, U_k1)
+// pairs; back_cols01 of the block's other direction waves reads them after a
+// barrier.  The same loads and rebuild as U.full in the lower staple, so the
+// staged values are the ones it would form.
+template <typename R, int NR>
+__device__ __forceinline__ void stage_back_link(const Geo &g, const LinksRO<R, NR> &U, int grp, int mu, int lane,
+                                                nv4_t<R> *back) {
+    Site x;
+    if (!group_site(g, grp, lane, x)) return;
+    M3<R> A;
+    U.full(mu, hop_bwd(g, x.s, coord(x, mu), mu), A);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        nv4_t<R> v;
+        v.x = A.e[k][0].re;
+        v.y = A.e[k][0].im;
+        v.z = A.e[k][1].re;
+        v.w = A.e[k][1].im;
+        back[(mu * 3 + k) * 64 + lane] = v;
+    }
+}
+
+// Columns 0 and 1 of U_nu(x-nu) from the block's LDS copy (column 2 unset:
+// the lower staple's (A^dag)(rows 0,1) reads only these).
+template <typename R> __device__ __forceinline__ void back_cols01(const nv4_t<R> *back, int nu, M3<R> &A) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const nv4_t<R> v = back[(nu * 3 + k) * 64 + lane];
+        A.e[k][0] = Cx<R>{v.x, v.y};
+        A.e[k][1] = Cx<R>{v.z, v.w};
+    }
+}
+
 // Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
-// in mask (bits 0..3).
+// in mask (bits 0..3).  own / back: the group's own links and backward links
+// staged in LDS (FP32), or nullptr to load them.
 template <typename R, int NR>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  unsigned mask, M23<R> &S, const nv4_t<R> *own = nullptr) {
+                                                  unsigned mask, M23<R> &S, const nv4_t<R> *own = nullptr,
+                                                  const nv4_t<R> *back = nullptr) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -314,7 +353,8 @@ __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R,
         {
             const int y = hop_bwd(g, s, site_coord<R>(x, nu), nu);
             M3<R> A;
-            U.full(nu, y, A);
+            if (back) back_cols01(back, nu, A);  // wave nu's backward link, staged in LDS
+            else U.full(nu, y, A);
             M3<R> B;
             U.full(mu, y, B);
             M23<R> T;
@@ -648,7 +688,8 @@ __device__ __forceinline__ void ape_group_f64(const Geo &g, const LinksRO<double
 template <typename R, int NR, int MODE, int PROJ = 0>
 __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
                                           double c2, unsigned mask, double *__restrict__ partials, int grp, int mu,
-                                          int lane, const nv4_t<R> *own = nullptr, double2 *back64 = nullptr) {
+                                          int lane, const nv4_t<R> *own = nullptr, double2 *back64 = nullptr,
+                                          const nv4_t<R> *back = nullptr) {
     static_assert(PROJ == 0 || MODE == kApe, "the polar projection runs without the fused plaquette");
     if constexpr (sizeof(R) == 8 && PROJ == 0) {
         // FP64 with the row projection: four directions per wave (mu is
@@ -681,7 +722,7 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             store_narrowed(out, mu, s, v);
         } else {
             M23<R> S, u0;
-            staple_sum_rows01<R, NR>(g, U, x, mu, mask, S, own);
+            staple_sum_rows01<R, NR>(g, U, x, mu, mask, S, own, back);
             if (own) own_rows01(own, mu, u0);
             else U.rows01(mu, s, u0);
             Cx<double> wm[2][3], v[3][3];

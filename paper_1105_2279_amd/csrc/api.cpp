@@ -99,11 +99,18 @@ static const char *op_name(int op) {
 
 static void log_cfg(const char *what, const TuneKey &k, const LaunchCfg &c) {
     if (!log_on()) return;
-    fprintf(stderr, "qdpx: %s %s prec %d fmt %d L %dx%dx%dx%d: block %d, groups/wave %d, xcd map %d, t window %d\n",
-            what, op_name(k.op), k.prec, k.fmt, k.L[0], k.L[1], k.L[2], k.L[3], c.block, c.nsite, c.xcd, c.tw);
+    fprintf(stderr,
+            "qdpx: %s %s prec %d fmt %d L %dx%dx%dx%d: block %d, groups/wave %d, xcd map %d, t window %d, "
+            "LDS tile %d\n",
+            what, op_name(k.op), k.prec, k.fmt, k.L[0], k.L[1], k.L[2], k.L[3], c.block, c.nsite, c.xcd, c.tw, c.lds);
 }
 
-static bool cfg_valid(qdpx_op op, const LaunchCfg &c);
+// LDS tile of the FP32 APE step when nothing chose one: the group's own
+// links and backward links staged.  Every other case has no LDS tile level.
+static const int kDefaultApeLds = 2;
+static int default_lds(int op, int prec) { return (op == QDPX_OP_APE && prec == QDPX_F32) ? kDefaultApeLds : 0; }
+
+static bool cfg_valid(qdpx_op op, qdpx_prec prec, const LaunchCfg &c);
 
 // Scratch memory of qdpx_eval_shift_mul_axpy_noalloc: the per-group |chi|^2
 // partials and the finalisation's stage-A sums of a lattice of at most
@@ -140,10 +147,11 @@ extern "C" int qdpx_create(qdpx_ctx **out, int device, const char *tune_cache_pa
         if (log_on())
             fprintf(stderr, "qdpx: launch table %s: %s\n", path.c_str(),
                     r == 1 ? "no such file yet" : r == 2 ? "recorded on another architecture, ignored" : "read");
-        for (const TuneEntry &t : entries) {
+        for (TuneEntry &t : entries) {
+            if (t.cfg.lds < 0) t.cfg.lds = default_lds(t.op, t.prec);  // written before the LDS tile field
             bool extents_ok = true;
             for (int d = 0; d < 4; ++d) extents_ok = extents_ok && t.L[d] >= 2 && t.L[d] <= 4096;
-            if (!extents_ok || !cfg_valid((qdpx_op)t.op, t.cfg) || t.L[3] % t.cfg.tw != 0)
+            if (!extents_ok || !cfg_valid((qdpx_op)t.op, (qdpx_prec)t.prec, t.cfg) || t.L[3] % t.cfg.tw != 0)
                 return fail(QDPX_EINVAL, "qdpx_create: launch table %s holds an invalid geometry for op %s",
                             path.c_str(), op_name(t.op));
         }
@@ -344,6 +352,7 @@ static bool stream_capturing(hipStream_t st) {
 static LaunchCfg cfg_for(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt) {
     LaunchCfg c;
     if (op == QDPX_OP_BATCHED) c.nsite = 1;  // groups per ticket
+    c.lds = default_lds(op, prec);
     if (ctx) {
         TuneKey k{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}};
         auto it = ctx->tuned.find(k);
@@ -854,10 +863,12 @@ extern "C" int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom 
 }
 
 // ------------------------------------------------------------------- tuner
-static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
+static bool cfg_valid(qdpx_op op, qdpx_prec prec, const LaunchCfg &c) {
     if (c.block < 64 || c.block > 1024 || (c.block % 64)) return false;
     if (c.xcd < 0 || c.xcd > 2) return false;
     if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
+    // LDS tile: 0..2 for the FP32 APE step, none (0) elsewhere
+    if (op == QDPX_OP_APE && prec == QDPX_F32 ? (c.lds < 0 || c.lds > 2) : c.lds != 0) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN || op == QDPX_OP_JACOBI)  // four waves per group, one per direction
         return c.block == 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
@@ -868,7 +879,7 @@ static bool cfg_valid(qdpx_op op, const LaunchCfg &c) {
 
 extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
                              int32_t *block, int32_t *sites_per_thread, int32_t *xcd_map, int32_t *t_window,
-                             int32_t *source) {
+                             int32_t *lds_tile, int32_t *source) {
     const char *fn = "qdpx_tune_get";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -878,6 +889,7 @@ extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     if (sites_per_thread) *sites_per_thread = c.nsite;
     if (xcd_map) *xcd_map = c.xcd;
     if (t_window) *t_window = c.tw;
+    if (lds_tile) *lds_tile = c.lds;
     if (source) {
         auto it = ctx->tuned.find(TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}});
         *source = it == ctx->tuned.end() ? kSrcDefault : it->second.source;
@@ -886,7 +898,8 @@ extern "C" int qdpx_tune_get(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
 }
 
 extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
-                             int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window) {
+                             int32_t block, int32_t sites_per_thread, int32_t xcd_map, int32_t t_window,
+                             int32_t lds_tile) {
     const char *fn = "qdpx_tune_set";
     QDPX_CHECK_CTX(fn);
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
@@ -896,9 +909,11 @@ extern "C" int qdpx_tune_set(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, q
     c.nsite = sites_per_thread;
     c.xcd = xcd_map;
     c.tw = t_window;
-    if (!cfg_valid(op, c) || geom->L[3] % c.tw != 0)
-        return fail(QDPX_EINVAL, "%s: geometry (block %d, sites %d, xcd %d, t window %d) not valid for op %d", fn,
-                    block, sites_per_thread, xcd_map, t_window, (int)op);
+    c.lds = lds_tile;
+    if (!cfg_valid(op, prec, c) || geom->L[3] % c.tw != 0)
+        return fail(QDPX_EINVAL,
+                    "%s: geometry (block %d, sites %d, xcd %d, t window %d, LDS tile %d) not valid for op %d", fn,
+                    block, sites_per_thread, xcd_map, t_window, lds_tile, (int)op);
     ctx->tuned[TuneKey{(int)op, (int)prec, (int)fmt, {geom->L[0], geom->L[1], geom->L[2], geom->L[3]}}] =
         Tuned{c, kSrcSet};
     return QDPX_OK;
@@ -957,7 +972,8 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
             if (geom->L[3] % tw || (tw > 1 && (g.bwl == 0 || x == 2))) continue;
             if (op == QDPX_OP_APE) {
                 for (int b : blocks_ape)
-                    for (int n : ns_ape) cands.push_back(LaunchCfg{b, n, x, tw});
+                    for (int n : ns_ape)
+                        for (int t = 0; t <= (prec == QDPX_F32 ? 2 : 0); ++t) cands.push_back(LaunchCfg{b, n, x, tw, t});
             } else {
                 for (int n : ns_shift) cands.push_back(LaunchCfg{256, n, x, tw});
             }

@@ -4,7 +4,8 @@
 // sections 5.4 and 9).  The file is JSON with a fixed schema:
 //   {"device": "gfx950:...", "entries": [
 //     {"op": "APE", "prec": "F32", "fmt": "LINK12", "L": [32, 32, 32, 64],
-//      "launch": [block, groups_per_wave, xcd_map, t_window]}, ...]}
+//      "launch": [block, groups_per_wave, xcd_map, t_window, lds_tile]}, ...]}
+// (a four-element "launch" leaves lds_tile at -1: the operation's default).
 // Entries recorded on another architecture (the part of "device" before the
 // first ':') are ignored.  This reader accepts any JSON value where the
 // schema does not care (unknown keys are skipped) and rejects everything
@@ -180,17 +181,21 @@ struct Parser {
 
 std::string arch_base(const std::string &a) { return a.substr(0, a.find(':')); }
 
-bool int_array4(const JVal *v, int out[4]) {
-    if (!v || v->kind != JVal::kArr || v->arr.size() != 4) return false;
-    for (int d = 0; d < 4; ++d) {
+// An array of n integers (n in [nmin, nmax]); returns n, or 0 if v is not one.
+int int_array(const JVal *v, int *out, int nmin, int nmax) {
+    if (!v || v->kind != JVal::kArr || (int)v->arr.size() < nmin || (int)v->arr.size() > nmax) return 0;
+    const int n = (int)v->arr.size();
+    for (int d = 0; d < n; ++d) {
         const JVal &x = v->arr[d];
         if (x.kind != JVal::kNum || !(x.num > -2147483648.0 && x.num < 2147483648.0) ||
             x.num != (double)(int)x.num)
             return false;
         out[d] = (int)x.num;
     }
-    return true;
+    return n;
 }
+
+bool int_array4(const JVal *v, int out[4]) { return int_array(v, out, 4, 4) == 4; }
 
 }  // namespace
 
@@ -241,10 +246,10 @@ int tune_table_read(const char *path, const char *arch, std::vector<TuneEntry> &
         const JVal &e = ents->arr[i];
         const JVal *op = e.get("op"), *prec = e.get("prec"), *fmt = e.get("fmt");
         TuneEntry t;
-        int launch[4];
+        int launch[5] = {0, 0, 0, 0, -1};  // a table without the LDS tile field: -1, the default
         const bool ok = e.kind == JVal::kObj && op && op->kind == JVal::kStr && prec && prec->kind == JVal::kStr &&
                         fmt && fmt->kind == JVal::kStr && int_array4(e.get("L"), t.L) &&
-                        int_array4(e.get("launch"), launch) && (t.op = name_index(kOpNames, op->str)) >= 0 &&
+                        int_array(e.get("launch"), launch, 4, 5) > 0 && (t.op = name_index(kOpNames, op->str)) >= 0 &&
                         (t.prec = name_index(kPrecNames, prec->str)) >= 0 &&
                         (t.fmt = name_index(kFmtNames, fmt->str)) >= 0;
         if (!ok) {
@@ -256,6 +261,7 @@ int tune_table_read(const char *path, const char *arch, std::vector<TuneEntry> &
         t.cfg.nsite = launch[1];
         t.cfg.xcd = launch[2];
         t.cfg.tw = launch[3];
+        t.cfg.lds = launch[4];
         out.push_back(t);
     }
     return 0;
@@ -272,9 +278,9 @@ int tune_table_write(const char *path, const char *arch, const std::vector<TuneE
         char line[256];
         snprintf(line, sizeof line,
                  "%s\n  {\"op\": \"%s\", \"prec\": \"%s\", \"fmt\": \"%s\", \"L\": [%d, %d, %d, %d], "
-                 "\"launch\": [%d, %d, %d, %d]}",
+                 "\"launch\": [%d, %d, %d, %d, %d]}",
                  first ? "" : ",", kOpNames[t.op], kPrecNames[t.prec], kFmtNames[t.fmt], t.L[0], t.L[1], t.L[2], t.L[3],
-                 t.cfg.block, t.cfg.nsite, t.cfg.xcd, t.cfg.tw);
+                 t.cfg.block, t.cfg.nsite, t.cfg.xcd, t.cfg.tw, t.cfg.lds);
         s += line;
         first = false;
     }

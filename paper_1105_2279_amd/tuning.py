@@ -47,16 +47,28 @@ def _key(op, prec, fmt, L):
     return (op, prec, fmt, tuple(int(x) for x in L))
 
 
+def default_lds_tile(op, prec):
+    """The library's LDS tile for an entry stored without one."""
+    return 2 if (op == "APE" and prec == "F32") else 0
+
+
 def read(path=TABLE):
-    """{(op, prec, fmt, L): (block, groups_per_wave, xcd_map, t_window)} as
-    stored in the file; empty if there is no table (for inspection: contexts
-    read the file in the library)."""
+    """{(op, prec, fmt, L): (block, groups_per_wave, xcd_map, t_window, lds_tile)}
+    as stored in the file (lds_tile the default where an entry has none);
+    empty if there is no table (for inspection: contexts read the file in the
+    library)."""
     try:
         with open(path) as fh:
             rows = json.load(fh)["entries"]
     except FileNotFoundError:
         return {}
-    return {_key(r["op"], r["prec"], r["fmt"], r["L"]): tuple(r["launch"]) for r in rows}
+    out = {}
+    for r in rows:
+        launch = list(r["launch"])
+        if len(launch) == 4:
+            launch.append(default_lds_tile(r["op"], r["prec"]))
+        out[_key(r["op"], r["prec"], r["fmt"], r["L"])] = tuple(launch)
+    return out
 
 
 def context(device=0, path=TABLE):

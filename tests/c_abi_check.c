@@ -1,7 +1,9 @@
 /* A C program on the library's C ABI alone (no Python): a context created
  * from a launch-table file launches the stored geometry.
- *   1. a table holding one APE geometry for 8x8x8x8 FP64 is written;
- *   2. qdpx_create reads it: qdpx_tune_get reports that geometry, source 1;
+ *   1. a table holding APE geometries for 8x8x8x8 FP64 and 16x8x4x8 FP32-12
+ *      is written;
+ *   2. qdpx_create reads it: qdpx_tune_get reports that geometry, source 1
+ *      (an entry without the LDS tile field gets the default tile);
  *   3. unit links are packed and smeared one step in that geometry: they
  *      stay unit links (a fixed point of the step), plaquette 1;
  *   4. a geometry set on another shape is saved into the table and a second
@@ -46,20 +48,27 @@ int main(int argc, char **argv) {
     snprintf(text, sizeof text,
              "{\"device\": \"%s\", \"entries\": [\n"
              " {\"op\": \"APE\", \"prec\": \"F64\", \"fmt\": \"LINK18\", \"L\": [8, 8, 8, 8], "
-             "\"launch\": [512, 2, 0, 2]}\n]}\n",
+             "\"launch\": [512, 2, 0, 2]},\n"
+             " {\"op\": \"APE\", \"prec\": \"F32\", \"fmt\": \"LINK12\", \"L\": [16, 8, 4, 8], "
+             "\"launch\": [256, 1, 2, 1, 1]}\n]}\n",
              prop.gcnArchName);
     CHECK(write_text(table, text) == 0, "cannot write %s", table);
 
     qdpx_ctx *ctx = NULL;
     CHECK(qdpx_create(&ctx, 0, table) == QDPX_OK, "qdpx_create with a table");
     const qdpx_geom g = {{8, 8, 8, 8}};
-    int32_t b = 0, n = 0, x = 0, t = 0, src = -1;
-    CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g, QDPX_F64, QDPX_LINK18, &b, &n, &x, &t, &src) == QDPX_OK, "tune_get");
-    CHECK(b == 512 && n == 2 && x == 0 && t == 2 && src == 1, "stored geometry not read: %d %d %d %d source %d", b,
-          n, x, t, src);
-    CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &src) == QDPX_OK &&
-              src == 0 && b == 256,
+    int32_t b = 0, n = 0, x = 0, t = 0, d = -1, src = -1;
+    CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g, QDPX_F64, QDPX_LINK18, &b, &n, &x, &t, &d, &src) == QDPX_OK,
+          "tune_get");
+    CHECK(b == 512 && n == 2 && x == 0 && t == 2 && d == 0 && src == 1,
+          "stored geometry not read: %d %d %d %d %d source %d", b, n, x, t, d, src);
+    CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
+              src == 0 && b == 256 && d == 2,
           "an absent shape is not the default");
+    const qdpx_geom g3 = {{16, 8, 4, 8}};
+    CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g3, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
+              b == 256 && n == 1 && x == 2 && t == 1 && d == 1 && src == 1,
+          "stored LDS tile not read: %d %d %d %d %d source %d", b, n, x, t, d, src);
 
     /* unit links, one APE step in the stored geometry */
     const size_t V = 8 * 8 * 8 * 8, nreal = V * 4 * 18;
@@ -96,18 +105,23 @@ int main(int argc, char **argv) {
 
     /* a geometry set on another shape, saved and read back through the environment */
     const qdpx_geom g2 = {{16, 8, 4, 8}};
-    CHECK(qdpx_tune_set(ctx, QDPX_OP_SHIFT, &g2, QDPX_F32, QDPX_LINK12, 256, 4, 1, 2) == QDPX_OK, "tune_set");
+    CHECK(qdpx_tune_set(ctx, QDPX_OP_SHIFT, &g2, QDPX_F32, QDPX_LINK12, 256, 4, 1, 2, 0) == QDPX_OK, "tune_set");
+    CHECK(qdpx_tune_set(ctx, QDPX_OP_SHIFT, &g2, QDPX_F32, QDPX_LINK12, 256, 4, 1, 2, 1) == QDPX_EINVAL,
+          "an LDS tile outside the FP32 APE step accepted");
     CHECK(qdpx_tune_save(ctx, NULL) == QDPX_OK, "tune_save");
     qdpx_destroy(ctx);
     setenv("QDPX_TUNE_CACHE", table, 1);
     qdpx_ctx *ctx2 = NULL;
     CHECK(qdpx_create(&ctx2, 0, NULL) == QDPX_OK, "qdpx_create through QDPX_TUNE_CACHE");
-    CHECK(qdpx_tune_get(ctx2, QDPX_OP_SHIFT, &g2, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &src) == QDPX_OK &&
-              b == 256 && n == 4 && x == 1 && t == 2 && src == 1,
+    CHECK(qdpx_tune_get(ctx2, QDPX_OP_SHIFT, &g2, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
+              b == 256 && n == 4 && x == 1 && t == 2 && d == 0 && src == 1,
           "saved geometry not read back");
-    CHECK(qdpx_tune_get(ctx2, QDPX_OP_APE, &g, QDPX_F64, QDPX_LINK18, &b, &n, &x, &t, &src) == QDPX_OK && b == 512 &&
-              src == 1,
+    CHECK(qdpx_tune_get(ctx2, QDPX_OP_APE, &g, QDPX_F64, QDPX_LINK18, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
+              b == 512 && src == 1,
           "first geometry lost by the save");
+    CHECK(qdpx_tune_get(ctx2, QDPX_OP_APE, &g3, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
+              d == 1 && src == 1,
+          "LDS tile lost by the save");
     qdpx_destroy(ctx2);
 
     /* a malformed table, and an invalid geometry, are refused */

@@ -53,8 +53,8 @@ def test_launch_table_covers_benchmark_shapes():
     """The stored launch table holds a geometry for every shape the benchmark
     launches, each one the library's geometry check accepts: the block a
     multiple of 64 (256 or 512 for APE and the batched call, 256 with one
-    wave per direction otherwise), an XCD order in 0..2 and a t window
-    dividing Lt."""
+    wave per direction otherwise), an XCD order in 0..2, a t window dividing
+    Lt and an LDS tile only for the FP32 APE step."""
     from paper_1105_2279_amd import tuning
     table = tuning.read()
     import latgen
@@ -63,9 +63,10 @@ def test_launch_table_covers_benchmark_shapes():
         assert tuning._key(op, prec, fmt, L) in table, (op, prec, fmt, L)
     for prec, fmt in tuning.BATCH_FORMATS:
         assert tuning._key("BATCHED", prec, fmt, latgen.batch_extents()[0]) in table, (prec, fmt)
-    for (op, prec, fmt, L), (block, nsite, xcd, tw) in table.items():
+    for (op, prec, fmt, L), (block, nsite, xcd, tw, lds) in table.items():
         assert (prec, fmt) in (("F32", "LINK12"), ("F64", "LINK18"), ("F32", "LINK18"))
         assert xcd in (0, 1, 2) and tw in (1, 2, 4, 8, 16) and L[3] % tw == 0
+        assert lds in ((0, 1, 2) if (op, prec) == ("APE", "F32") else (0,))
         if op == "BATCHED":  # block, groups per ticket
             assert block in (256, 512) and nsite in (1, 2, 4, 8)
         elif op == "APE":

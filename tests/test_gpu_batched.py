@@ -101,7 +101,7 @@ def test_batched_autotuner(prec, fmt, tmp_path):
     ref_outs, ref_plaq, _ = run_batched(c, MIXED, Uds, prec, fmt, 2)
     q.qdpx_tune_batched(c, MIXED, prec, fmt, 2)
     assert q.qdpx_tune_source(c, q.OP_BATCHED, MIXED[0], prec, fmt) == "tuned"
-    block, chunk, _, _ = q.qdpx_tune_get(c, q.OP_BATCHED, MIXED[0], prec, fmt)
+    block, chunk, _, _, _ = q.qdpx_tune_get(c, q.OP_BATCHED, MIXED[0], prec, fmt)
     assert block in (256, 512) and chunk in (1, 2, 4, 8)
     outs, plaq, work = run_batched(c, MIXED, Uds, prec, fmt, 2)
     torch.cuda.synchronize()
@@ -111,7 +111,7 @@ def test_batched_autotuner(prec, fmt, tmp_path):
     assert torch.equal(plaq, ref_plaq)
     c.close()
     c2 = q.Context(0, tune_cache=table)
-    assert q.qdpx_tune_get(c2, q.OP_BATCHED, MIXED[0], prec, fmt) == (block, chunk, 1, 1)
+    assert q.qdpx_tune_get(c2, q.OP_BATCHED, MIXED[0], prec, fmt) == (block, chunk, 1, 1, 0)
     assert q.qdpx_tune_source(c2, q.OP_BATCHED, MIXED[0], prec, fmt) == "table"
     c2.close()
 

@@ -302,11 +302,13 @@ def test_geometries_are_bit_identical(L):
     psi, phi = latgen.dirac_field(L, 62), latgen.dirac_field(L, 63)
     c = ctx()
     results_ape, results_shift = [], []
-    for block, ns, xcd, tw in [(256, 1, 1, 1), (256, 1, 0, 2), (512, 2, 1, 4), (256, 4, 0, 8), (256, 2, 2, 1),
-                               (512, 1, 2, 1)]:
+    # the LDS tile of the FP32 step (0 none, 1 own links, 2 own and backward
+    # links) is one more launch choice that must not change a bit
+    for block, ns, xcd, tw, lds in [(256, 1, 1, 1, 2), (256, 1, 0, 2, 1), (512, 2, 1, 4, 0), (256, 4, 0, 8, 2),
+                                    (256, 2, 2, 1, 0), (512, 1, 2, 1, 1), (512, 2, 2, 1, 2)]:
         if L[3] % tw:
             tw = 2
-        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd, tw)
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd, tw, lds)
         results_ape.append(ape(L, U, q.F32, q.LINK12, 2))
     for block, ns, xcd, tw in [(256, 1, 1, 1), (256, 8, 0, 2), (256, 2, 1, 8), (256, 4, 0, 2), (256, 2, 2, 1)]:
         if L[3] % tw:
@@ -325,11 +327,11 @@ def test_tuner_picks_a_valid_geometry():
     c = q.Context(0)
     L = (8, 8, 8, 8)
     q.qdpx_tune(c, q.OP_APE, L, q.F32, q.LINK12)
-    b, n, x, tw = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
-    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1, 2) and tw in (1, 2, 4, 8)
+    b, n, x, tw, lds = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
+    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1, 2) and tw in (1, 2, 4, 8) and lds in (0, 1, 2)
     q.qdpx_tune(c, q.OP_SHIFT, L, q.F64, q.LINK18)
-    b, n, x, tw = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
-    assert b == 256 and n in (1, 2, 4, 8) and x in (0, 1, 2) and tw in (1, 2, 4, 8)
+    b, n, x, tw, lds = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
+    assert b == 256 and n in (1, 2, 4, 8) and x in (0, 1, 2) and tw in (1, 2, 4, 8) and lds == 0
     c.close()
 
 
@@ -407,6 +409,11 @@ def test_validation_errors():
     with pytest.raises(q.QdpxError) as e:
         q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1, 1)
     assert e.value.code == -1
+    for op, prec, fmt, lds in ((q.OP_APE, q.F32, q.LINK12, 3), (q.OP_APE, q.F64, q.LINK18, 1),
+                               (q.OP_SHIFT, q.F32, q.LINK12, 1)):  # LDS tiles only for the FP32 APE step
+        with pytest.raises(q.QdpxError) as e:
+            q.qdpx_tune_set(c, op, L, prec, fmt, 256, 1, 1, 1, lds)
+        assert e.value.code == -1
 
 
 def test_misaligned_links_rejected():

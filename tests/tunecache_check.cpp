@@ -51,6 +51,7 @@ int main(int argc, char **argv) {
             t.cfg.nsite = 1 + op % 3;
             t.cfg.xcd = op % 3;
             t.cfg.tw = 1 << (op % 4);
+            t.cfg.lds = (op + prec) % 3;
             in.push_back(t);
         }
     EXPECT(tune_table_write(path.c_str(), "gfx950:sramecc+:xnack-", in, err) == 0, "write failed: %s\n", err.c_str());
@@ -60,7 +61,7 @@ int main(int argc, char **argv) {
         const TuneEntry &a = in[i], &b = out[i];
         EXPECT(a.op == b.op && a.prec == b.prec && a.fmt == b.fmt && a.L[0] == b.L[0] && a.L[1] == b.L[1] &&
                    a.L[2] == b.L[2] && a.L[3] == b.L[3] && a.cfg.block == b.cfg.block && a.cfg.nsite == b.cfg.nsite &&
-                   a.cfg.xcd == b.cfg.xcd && a.cfg.tw == b.cfg.tw,
+                   a.cfg.xcd == b.cfg.xcd && a.cfg.tw == b.cfg.tw && a.cfg.lds == b.cfg.lds,
                "entry %zu differs after the round trip\n", i);
     }
     EXPECT(tune_table_read(path.c_str(), "gfx942:sramecc+", out, err) == 2 && out.empty(),
@@ -73,8 +74,13 @@ int main(int argc, char **argv) {
         "                 \"launch\": [512, 1, 2, 1], \"note\": \"tuned\"} ] }\n";
     put(path, good);
     EXPECT(tune_table_read(path.c_str(), "gfx950", out, err) == 0 && out.size() == 1 && out[0].op == 2 &&
-               out[0].prec == 1 && out[0].fmt == 1 && out[0].L[3] == 64 && out[0].cfg.block == 512 && out[0].cfg.xcd == 2,
-           "a table with extra keys was not read: %s\n", err.c_str());
+               out[0].prec == 1 && out[0].fmt == 1 && out[0].L[3] == 64 && out[0].cfg.block == 512 &&
+               out[0].cfg.xcd == 2 && out[0].cfg.lds == -1,
+           "a table with extra keys (and no LDS tile field) was not read: %s\n", err.c_str());
+    put(path, "{\"device\": \"gfx950\", \"entries\": [{\"op\": \"APE\", \"prec\": \"F32\", \"fmt\": \"LINK12\", "
+              "\"L\": [8, 8, 8, 8], \"launch\": [256, 1, 1, 1, 2]}]}");
+    EXPECT(tune_table_read(path.c_str(), "gfx950", out, err) == 0 && out.size() == 1 && out[0].cfg.lds == 2,
+           "the LDS tile field was not read: %s\n", err.c_str());
 
     const char *bad[] = {
         "",
@@ -99,6 +105,10 @@ int main(int argc, char **argv) {
         "{\"device\": \"gfx950\", \"entries\": [{\"op\": \"APE\", \"prec\": \"F32\", \"fmt\": \"LINK12\", "
         "\"L\": [8, 8, 8, 8], \"launch\": [256, 1, 1, 1]}",
         "{\"device\": \"gfx950\", \"entries\": [1, 2]}",
+        "{\"device\": \"gfx950\", \"entries\": [{\"op\": \"APE\", \"prec\": \"F32\", \"fmt\": \"LINK12\", "
+        "\"L\": [8, 8, 8, 8], \"launch\": [256, 1, 1, 1, 2, 0]}]}",
+        "{\"device\": \"gfx950\", \"entries\": [{\"op\": \"APE\", \"prec\": \"F32\", \"fmt\": \"LINK12\", "
+        "\"L\": [8, 8, 8, 8], \"launch\": [256, 1, 1]}]}",
         "{\"device\": \"gfx950\", \"entries\": [{\"op\": \"APE\",}]}",
         "{\"device\": \"gfx\\q950\", \"entries\": []}",
         "[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[[]]]]]]]]]]]]]]]]]]]]]]]]]]]]]]"
