@@ -1003,19 +1003,21 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
     };
     // Warm-up: about 30 launches of the default geometry, so that the first
     // candidates are not timed at idle clocks.  First pass: every candidate
-    // once (after one warm-up launch).  Second pass: the eight fastest again,
-    // interleaved over seven passes, keeping each one's best pass, so that a
-    // single slow or fast sample does not decide.
+    // once (after one warm-up launch), ten launches.  Second pass: the
+    // sixteen fastest again, interleaved over nine passes, keeping each one's
+    // best pass, so that neither a single slow or fast sample nor the clock
+    // drifting during the first pass decides (candidates within a few per
+    // cent of each other are common).
     for (int r = 0; r < 30; ++r) (void)run(LaunchCfg{});
     std::vector<std::pair<float, int>> r1;
     for (size_t i = 0; i < cands.size(); ++i) {
         if (run(cands[i]) != hipSuccess) continue;
-        r1.push_back({time_cfg(cands[i], 5), (int)i});
+        r1.push_back({time_cfg(cands[i], 10), (int)i});
     }
     std::sort(r1.begin(), r1.end());
-    const size_t keep = std::min<size_t>(8, r1.size());
+    const size_t keep = std::min<size_t>(16, r1.size());
     std::vector<float> best_ms(keep, 1e30f);
-    for (int pass = 0; pass < 7; ++pass)
+    for (int pass = 0; pass < 9; ++pass)
         for (size_t k = 0; k < keep; ++k) best_ms[k] = std::min(best_ms[k], time_cfg(cands[r1[k].second], 10));
     LaunchCfg best_cfg;
     float best = 1e30f;
