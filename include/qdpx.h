@@ -283,14 +283,13 @@ int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx
  * plaq (nullable, device double[3*(n_steps+1)]) receives the plaquette
  * triple (total, spatial, temporal; normalised as in qdpx_plaquette; all six
  * planes whatever the mask) of the input and of every step's output, every
- * product and sum in FP64.  QDPX_F32: each triple is qdpx_plaquette's pass
- * on those links (the FP32 entries widened to FP64), bit for bit.  QDPX_F64:
- * with smear_mask 0xF and the Gram-Schmidt projection the traces of a step's
- * input are fused into that step's kernel (each plaquette from rows 0 and 1
- * of its two halves, exact for SU(3) links) and the last output's take a
- * pass of their own with the same arithmetic; they agree with qdpx_plaquette
- * to FP64 rounding.  The smeared links do not depend on whether plaq is
- * requested.
+ * product and sum in FP64: qdpx_plaquette's pass on those links (FP32
+ * entries widened to FP64), bit for bit; except that FP64 links with
+ * smear_mask 0xF and the Gram-Schmidt projection fuse the traces of a
+ * step's input into that step's kernel (each plaquette from rows 0 and 1 of
+ * its two halves, exact for SU(3) links), which agree with qdpx_plaquette
+ * to FP64 rounding (the last output's triple is the pass).  The smeared
+ * links do not depend on whether plaq is requested.
  * A W whose row 0 or projected row 1 vanishes gives NaN entries.
  * work: >= qdpx_workspace_bytes(QDPX_OP_APE, ..., n_steps). */
 int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_linkfmt fmt,
@@ -343,7 +342,8 @@ int qdpx_plaquette(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec prec, qdpx_li
  * one z plane each) are split into 8 contiguous ranges, one per XCD queue,
  * walked t-row by t-row.  Threads per block (256 or 512) and groups per
  * ticket come from qdpx_tune_batched, or qdpx_tune_set(ctx, QDPX_OP_BATCHED,
- * &geoms[0], prec, fmt, block, groups, 1, 1) (default 256 and 1). */
+ * &geoms[0], prec, fmt, block, groups, 1, 1, 0) (default 256 and 1).  The
+ * final plaquettes are qdpx_plaquette's pass on each lattice's output. */
 int qdpx_ape_smear_batched(qdpx_ctx *ctx, int n_lat, const qdpx_geom *geoms, qdpx_prec prec,
                            qdpx_linkfmt fmt, const void *const *U_in, void *const *U_out,
                            double alpha, int n_steps, double *plaq, void *work, size_t work_bytes,
