@@ -103,20 +103,23 @@ template <typename R> __device__ __forceinline__ void acc_33_33dag(M3<R> &S, con
             for (int k = 0; k < 3; ++k) cmac_cb(S.e[i][j], T.e[i][k], C.e[j][k]);
 }
 
-// Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12.
+// Full link in FP64: stored rows widened, row 2 rebuilt in FP64 for LINK12
+// and, as the FP64 step takes it, for FP64 links (rows 0 and 1 read, a third
+// fewer loads; the 18-real FP32 format is read whole).
 template <typename R, int NR>
 __device__ __forceinline__ void load_f64(const LinksRO<R, NR> &U, int mu, int s, M3<double> &m) {
+    constexpr int kRows = (NR == 2 || sizeof(R) == 8) ? 2 : 3;
     Cx<R> r[3][3];
-    U.template load_rows<false, NR>(mu, s, r);
+    U.template load_rows<false, kRows>(mu, s, r);
 #pragma unroll
-    for (int a = 0; a < NR; ++a)
+    for (int a = 0; a < kRows; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) m.e[a][b] = Cx<double>{(double)r[a][b].re, (double)r[a][b].im};
-    if constexpr (NR == 2) rebuild_row2(m);
+    if constexpr (kRows == 2) rebuild_row2(m);
 }
 
 // Re Tr P_{mu nu}(x) = Re Tr[(U_mu(x) U_nu(x+mu)) (U_nu(x) U_mu(x+nu))^dag] of
-// the stored links widened to FP64 (row 2 rebuilt in FP64 for LINK12), every
+// the stored links widened to FP64 (row 2 rebuilt in FP64, load_f64), every
 // product and sum in FP64: the plaquette pass behind every plaquette of
 // FP32 links (standalone, per step, batched) and of FP64 links outside the
 // fused step.  s_mu = x+mu, s_nu = x+nu.  Each link is loaded once, whole.

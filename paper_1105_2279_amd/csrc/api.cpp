@@ -662,15 +662,12 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
     // the rounding of FP64), so only the last output needs the pass.
     const bool f32 = (prec == QDPX_F32);
     const bool fused = !f32 && (smear_mask == 0xFu) && !polar;
-    auto plaquette_of = [&](const void *links, double *out) -> int {
-        return plaquette_into(g, prec, fmt, links, out, part, st, fn);
-    };
     const void *src = U_in;
     for (int k = 0; k < n_steps; ++k) {
         // the last step always lands in U_out
         void *dst = (((n_steps - 1 - k) & 1) == 0) ? U_out : tmp;
         if (plaq && !fused)
-            if (int r = plaquette_of(src, plaq + 3 * k)) return r;
+            if (int r = plaquette_into(g, prec, fmt, src, plaq + 3 * k, part, st, fn)) return r;
         QDPX_TRY_HIP(launch_ape_step(g, prec, nrows_of(fmt), src, dst, c1, c2, smear_mask,
                                      (plaq && fused) ? part : nullptr, (plaq && fused) ? 1 : 0, cfg, st, polar),
                      fn);
@@ -679,7 +676,7 @@ extern "C" int qdpx_ape_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pr
         src = dst;
     }
     if (plaq)
-        if (int r = plaquette_of(U_out, plaq + 3 * n_steps)) return r;
+        if (int r = plaquette_into(g, prec, fmt, U_out, plaq + 3 * n_steps, part, st, fn)) return r;
     return QDPX_OK;
 }
 
