@@ -403,7 +403,9 @@ def main():
     ctx.close()
 
 
-SHIFT_FORMATS = (("f64_18", "F64", "LINK18", 1152), ("f32_12", "F32", "LINK12", 480))
+# Algorithmic bytes per site of the shift expression: 4 links (FP64 links are
+# read as rows 0 and 1, 96 B each), psi, phi and chi once each.
+SHIFT_FORMATS = (("f64_18", "F64", "LINK18", 960), ("f32_12", "F32", "LINK12", 480))
 
 
 _SHIFT_HOST = {}
@@ -560,7 +562,7 @@ def jacobi_extras(torch, q, ctx, dev, stream, latgen):
 
     out = {}
     paths = (("sp_f32_12", q.F32, q.LINK12, 48, 96), ("sp_f32_18", q.F32, q.LINK18, 72, 96),
-             ("dp_f64_18", q.F64, q.LINK18, 144, 192))
+             ("dp_f64_18", q.F64, q.LINK18, 96, 192))  # link bytes read: FP64 rows 0 and 1
     for L, paper in JACOBI_PAPER_GFLOPS.items():
         V = latgen.volume(L)
         seeds = latgen.SEEDS["jacobi_table1"]
@@ -616,7 +618,8 @@ def jit_extras(torch, q, ctx, dev, stream, latgen):
     U = latgen.haar_links(Lj, 1305)
     psi = latgen.dirac_field(Lj, 1306)
     out = {}
-    for name, prec, fmt, link_b, ferm_b in (("f32_12", q.F32, q.LINK12, 48, 96), ("f64_18", q.F64, q.LINK18, 144, 192)):
+    # link bytes read: FP64 links as rows 0 and 1 (both kernels)
+    for name, prec, fmt, link_b, ferm_b in (("f32_12", q.F32, q.LINK12, 48, 96), ("f64_18", q.F64, q.LINK18, 96, 192)):
         t0 = time.perf_counter()
         k = q.qdpx_jit_compile(ctx, hop, prec, fmt, 1, 0)
         t_compile = time.perf_counter() - t0
@@ -668,7 +671,7 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
     psi = latgen.dirac_field(Ls, seeds["psi"])
     phi = latgen.dirac_field(Ls, seeds["phi"])
     log(f"large: generated 48^3x96 Haar links and fields in {time.time() - t:.1f} s")
-    paths = (("f32_12", q.F32, q.LINK12, 48, 480), ("f64_18", q.F64, q.LINK18, 144, 1152))
+    paths = (("f32_12", q.F32, q.LINK12, 48, 480), ("f64_18", q.F64, q.LINK18, 96, 960))  # bytes read per link, per site
     res, full, psi_out, norms_out = {}, {}, {}, {}
     for name, prec, fmt, link_b, site_b in paths:
         launch = {"ape": tuning.ensure(ctx, q.OP_APE, prec, fmt, Ls),
@@ -724,7 +727,7 @@ def large_extras(torch, q, ctx, dev, stream, latgen, np):
             "final_plaquette_of_timed_call": [float(x) for x in plaq_end.cpu().numpy()],
             "final_plaquette_equals_per_step_call": bool(torch.equal(plaq_end, plaq[-3:])),
             "ape_link_updates_per_s": ups,
-            "ape_hbm_gbs_algorithmic": round(2 * link_b * ups / 1e9, 1),
+            "ape_hbm_gbs_algorithmic": round(BYTES_PER_LINK[name] * ups / 1e9, 1),
             "chain_8_iterations_ms": round(ms_chain, 3),
             "chain_hbm_gbs_algorithmic": round(site_b * V * N_CHAIN / (ms_chain / 1e3) / 1e9, 1),
             "chain_hbm_frac": round(site_b * V * N_CHAIN / (ms_chain / 1e3) / 1e9 / PEAK_HBM_GBS, 4),

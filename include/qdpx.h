@@ -81,7 +81,13 @@ typedef enum {
 typedef enum { QDPX_F64 = 0, QDPX_F32 = 1 } qdpx_prec;
 
 /* LINK18 stores all 9 complex entries; LINK12 stores rows 0 and 1 only and
- * is accepted with QDPX_F32 only. */
+ * is accepted with QDPX_F32 only.  Links are taken to be SU(3): FP64 LINK18
+ * links are read as rows 0 and 1 with row 2 rebuilt as conj(row0 x row1)
+ * in FP64 by the shift, chain, hop, Jacobi, plaquette and run-time compiled
+ * kernels and by the Gram-Schmidt APE step (the stored row 2 equals it to
+ * rounding for SU(3) links; a third fewer bytes); FP32 LINK18 links are read
+ * whole, and the polar APE step and the pack/unpack calls read every stored
+ * element. */
 typedef enum { QDPX_LINK18 = 0, QDPX_LINK12 = 1 } qdpx_linkfmt;
 
 /* SU(3) projection of the APE combination W (qdpx_ape_smear). */

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
         if (live && ((mask >> mu) & 1u)) {  // wave-uniform
             const int f = bwd ? hop_bwd(g, s, cmu, mu) : hop_fwd(g, s, cmu, mu);
             M3<R> u;
-            U.full_stream(mu, bwd ? f : s, u);  // each link is read once
+            U.template su3<true>(mu, bwd ? f : s, u);  // each link is read once
             if (bwd) {  // U^dag: transpose and conjugate in registers
 #pragma unroll
                 for (int ca = 0; ca < 3; ++ca) {
@@ -386,8 +386,8 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
             // memory round trip per group
             const int f = hop_fwd(g, s, cmu, mu), bk = hop_bwd(g, s, cmu, mu);
             M3<R> uf, ub;
-            U.full(mu, s, uf);   // U_mu(x), also the backward link of x+mu
-            U.full(mu, bk, ub);  // U_mu(x-mu)
+            U.template su3<false>(mu, s, uf);   // U_mu(x), also the backward link of x+mu
+            U.template su3<false>(mu, bk, ub);  // U_mu(x-mu)
             Cx<R> pf[4][3], pb[4][3];
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)

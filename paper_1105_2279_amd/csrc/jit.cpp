@@ -274,7 +274,9 @@ __device__ __forceinline__ void ldspinor(const real2 *__restrict__ f, long long 
 // mu*3*NROWS*S on.  Double: one array of S entries per stored element c = 3a+b.
 // Float (PAIRED): elements 2k, 2k+1 share the 16-byte entry s of array k;
 // the ninth element of a three-row link has an array of its own after the
-// four pair arrays.  With NROWS = 2 the third row is conj(row0 x row1).
+// four pair arrays.  With NROWS = 2, and for double links (whose stored row 2
+// is that row to rounding for SU(3) links; rows 0 and 1 read, as the
+// hand-written FP64 kernels read them), the third row is conj(row0 x row1).
 typedef real real4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void ldlink(const real2 *__restrict__ U, long long S, int mu, int s, link &u) {
     const real2 *d = U + (long long)mu * 3 * NROWS * S;
@@ -289,11 +291,11 @@ __device__ __forceinline__ void ldlink(const real2 *__restrict__ U, long long S,
     if (NROWS == 3) u.e[2][2] = ldc(d + 8 * S, 0, 0, s);
 #else
 #pragma unroll
-    for (int a = 0; a < NROWS; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) u.e[a][b] = ldc(d, S, a * 3 + b, s);
 #endif
-    if (NROWS == 2) {
+    if (NROWS == 2 || !PAIRED) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const int i = (b + 1) % 3, j = (b + 2) % 3;

@@ -298,10 +298,14 @@ template <typename R, int NR> struct LinksRO {
                 for (int b = 0; b < 3; ++b) e[a][b] = ld<NT>(mu, a, b, s);
         }
     }
-    // full link read once per site (no neighbour reuse): streamed
-    __device__ __forceinline__ void full_stream(int mu, int s, M3<R> &m) const {
-        load_rows<true, NR>(mu, s, m.e);
-        if constexpr (NR == 2) rebuild_row2(m);
+    // The link as the shift and hop kernels read it: every stored row of
+    // FP32 18-real links, else rows 0 and 1 with row 2 rebuilt (12-real
+    // links; FP64 links, whose stored row 2 is conj(row0 x row1) to rounding
+    // for SU(3) links: a third fewer bytes for kernels bound by them).
+    template <bool NT> __device__ __forceinline__ void su3(int mu, int s, M3<R> &m) const {
+        constexpr int kRows = (NR == 3 && sizeof(R) == 4) ? 3 : 2;
+        load_rows<NT, kRows>(mu, s, m.e);
+        if constexpr (kRows == 2) rebuild_row2(m);
     }
     __device__ __forceinline__ void rows01(int mu, int s, M23<R> &m) const { load_rows<false, 2>(mu, s, m.e); }
     __device__ __forceinline__ void full(int mu, int s, M3<R> &m) const {
