@@ -31,10 +31,11 @@
  *     QDPX_F32  elements 2k and 2k+1 share one 16-byte entry (float4) of
  *               array k, [mu][k][S]; the ninth LINK18 element has an array
  *               of S float2 of its own after the four pair arrays.
- *   Either way a direction takes 3*rows*S complex slots.  Fermions:
- *   complex[spin][colour][S], complex = double2 (F64) or float2 (F32).
- *   Link fields and workspaces must be 16-byte aligned, Dirac fields
- *   aligned to their complex element (8 bytes F32, 16 bytes F64); other
+ *   Either way a direction takes 3*rows*S complex slots.  Fermions, with
+ *   component q = 3*spin + colour: QDPX_F64 one array of S double2 per
+ *   component, [q][S]; QDPX_F32 components 2k and 2k+1 share one 16-byte
+ *   entry (float4, q even in the low half) of array k, [k][S], k = 0..5.
+ *   Link fields, Dirac fields and workspaces must be 16-byte aligned; other
  *   pointers are refused with QDPX_EINVAL before anything is launched.
  *
  * Memory and streams.  Every pointer argument named *_dev, and every field

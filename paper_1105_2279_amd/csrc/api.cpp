@@ -284,11 +284,10 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Link fields are read and written with 16-byte accesses, Dirac fields one
-// complex element (8 or 16 bytes) at a time; workspaces that hold fields are
-// 16-byte aligned.
+// Link and Dirac fields are read with 16-byte accesses (FP32 Dirac-field
+// components in pairs); workspaces that hold fields are 16-byte aligned.
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
-static bool field_aligned(const void *p, qdpx_prec prec) { return ((uintptr_t)p % cplx_bytes(prec)) == 0; }
+static bool field_aligned(const void *p, qdpx_prec) { return aligned16(p); }
 
 extern "C" int64_t qdpx_site_stride(const qdpx_geom *geom) {
     if (!geom_ok(geom, "qdpx_site_stride")) return -1;
@@ -405,7 +404,7 @@ extern "C" int qdpx_pack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const dou
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, QDPX_LINK18, fn)) return r;
     if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
-    if (!field_aligned(soa, prec)) return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+    if (!field_aligned(soa, prec)) return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     const Geo g = make_geo(geom->L);
     if (overlap(aos, (size_t)g.V * 24 * 8, soa, qdpx_fermion_bytes(geom, prec)))
         return fail(QDPX_EALIAS, "%s: soa overlaps aos", fn);
@@ -420,7 +419,7 @@ extern "C" int qdpx_unpack_fermion(qdpx_ctx *ctx, const qdpx_geom *geom, const v
     if (!geom_ok(geom, fn)) return QDPX_EINVAL;
     if (int r = check_format(prec, QDPX_LINK18, fn)) return r;
     if (!aos || !soa) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
-    if (!field_aligned(soa, prec)) return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+    if (!field_aligned(soa, prec)) return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     const Geo g = make_geo(geom->L);
     if (overlap(aos, (size_t)g.V * 24 * 8, soa, qdpx_fermion_bytes(geom, prec)))
         return fail(QDPX_EALIAS, "%s: aos overlaps soa", fn);
@@ -442,7 +441,7 @@ extern "C" int qdpx_eval_shift_mul_axpy(qdpx_ctx *ctx, const qdpx_geom *geom, qd
     if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (!field_aligned(psi, prec) || !field_aligned(phi, prec) || !field_aligned(chi, prec))
-        return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+        return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     if (norm2 && !aligned16(work)) return fail(QDPX_EINVAL, "%s: workspace not 16-byte aligned", fn);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_SHIFT, geom, prec, fmt, 0);
     if (norm2 && (!work || work_bytes < need))
@@ -484,7 +483,7 @@ extern "C" int qdpx_eval_shift_mul_axpy_noalloc(qdpx_ctx *ctx, const qdpx_geom *
     if (!U || !psi || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (!field_aligned(psi, prec) || !field_aligned(phi, prec) || !field_aligned(chi, prec))
-        return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+        return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
     if (overlap(chi, fb, psi, fb) || overlap(chi, fb, phi, fb) || overlap(chi, fb, U, lb))
         return fail(QDPX_EALIAS, "%s: chi overlaps an input", fn);
@@ -511,7 +510,7 @@ extern "C" int qdpx_shift_chain(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec 
     if (!U || !psi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (!field_aligned(psi, prec) || !field_aligned(phi, prec))
-        return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+        return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     if (!aligned16(work)) return fail(QDPX_EINVAL, "%s: workspace not 16-byte aligned", fn);
     if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
     const size_t need = qdpx_workspace_bytes(QDPX_OP_CHAIN, geom, prec, fmt, n_iter);
@@ -546,7 +545,7 @@ extern "C" int qdpx_eval_hop(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec pre
     if (!U || !psi || !out) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
     if (!field_aligned(psi, prec) || !field_aligned(out, prec))
-        return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+        return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     if (dir_mask & ~0xFu) return fail(QDPX_EINVAL, "%s: dir_mask 0x%x has bits beyond the 4 directions", fn, dir_mask);
     const size_t fb = qdpx_fermion_bytes(geom, prec), lb = qdpx_links_bytes(geom, prec, fmt);
     if (overlap(out, fb, psi, fb) || overlap(out, fb, U, lb)) return fail(QDPX_EALIAS, "%s: out overlaps an input", fn);
@@ -567,7 +566,7 @@ extern "C" int qdpx_jacobi_smear(qdpx_ctx *ctx, const qdpx_geom *geom, qdpx_prec
     if (int r = check_format(prec, fmt, fn)) return r;
     if (!U || !chi) return fail(QDPX_EINVAL, "%s: NULL field pointer", fn);
     if (!aligned16(U)) return fail(QDPX_EINVAL, "%s: link field not 16-byte aligned", fn);
-    if (!field_aligned(chi, prec)) return fail(QDPX_EINVAL, "%s: field not aligned to its element size", fn);
+    if (!field_aligned(chi, prec)) return fail(QDPX_EINVAL, "%s: field not 16-byte aligned", fn);
     if (!aligned16(work)) return fail(QDPX_EINVAL, "%s: workspace not 16-byte aligned", fn);
     if (n_iter < 1) return fail(QDPX_EINVAL, "%s: n_iter = %d < 1", fn, n_iter);
     if (norm == 0.0) return fail(QDPX_EINVAL, "%s: norm is 0", fn);

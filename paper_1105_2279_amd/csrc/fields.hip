@@ -86,6 +86,13 @@ __global__ void __launch_bounds__(256) k_unpack_links(Geo g, const vec2_t<R> *__
         for (int b = 0; b < 3; ++b) aos[((int64_t)s * 4 + mu) * 9 + a * 3 + b] = double2{m.e[a][b].re, m.e[a][b].im};
 }
 
+// Index, in complex elements, of component comp of site s in the library's
+// Dirac-field layout (FermLayout: FP32 components paired in 16-byte entries).
+template <typename R> __device__ __forceinline__ int64_t fermion_index(int comp, int s, int64_t S) {
+    if constexpr (FermLayout<R>::kPaired) return ((int64_t)(comp >> 1) * S + s) * 2 + (comp & 1);
+    else return (int64_t)comp * S + s;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_pack_fermion(Geo g, const double2 *__restrict__ aos,
                                                       vec2_t<R> *__restrict__ soa) {
@@ -96,7 +103,7 @@ __global__ void __launch_bounds__(256) k_pack_fermion(Geo g, const double2 *__re
     vec2_t<R> o;
     o.x = (R)v.x;
     o.y = (R)v.y;
-    soa[(int64_t)comp * g.S + s] = o;
+    soa[fermion_index<R>(comp, s, g.S)] = o;
 }
 
 template <typename R>
@@ -105,7 +112,7 @@ __global__ void __launch_bounds__(256) k_unpack_fermion(Geo g, const vec2_t<R> *
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int comp = blockIdx.y;
     if (s >= g.V) return;
-    const vec2_t<R> v = soa[(int64_t)comp * g.S + s];
+    const vec2_t<R> v = soa[fermion_index<R>(comp, s, g.S)];
     aos[(int64_t)s * 12 + comp] = double2{(double)v.x, (double)v.y};
 }
 
@@ -162,8 +169,9 @@ hipError_t launch_unpack_fermion(const Geo &g, int prec, const void *soa, double
 // spinor components, so the four directions' loads are in flight together.
 // Either hop reads each link once per launch, so links are streamed.
 // The four partial products meet in LDS; after a barrier wave w adds them in
-// direction order for spin w, adds a phi, forms the FP64 |chi|^2 of its three
-// components, and stores spin w.  The four waves' norms are added in wave
+// direction order for the components it owns (FermLayout), adds a phi, forms
+// the FP64 |chi|^2 of those components and stores them.  The four waves'
+// norms are added in wave
 // order and reduced by a wave butterfly into one partial per group, so
 // every sum has a fixed order and nothing depends on the launch geometry.
 template <typename R, int NR, int MODE, int NS>
@@ -185,29 +193,16 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
         const bool live = group_site(g, grp, lane, x);
         const int s = x.s;
         const int cmu = coord(x, mu);
-        // spin mu's component bases (this wave stores spin mu), formed outside
-        // the per-lane branches; phi and (MODE 1) psi of spin mu are fetched
-        // now so that their latency overlaps the products and the exchange
-        const vec2_t<R> *fb[3], *pb[3];
-        vec2_t<R> *ob[3];
+        // phi and (MODE 1) psi of the components this wave stores are
+        // fetched now so that their latency overlaps the products and the
+        // exchange
+        constexpr int NO = FermLayout<R>::kOwn;
+        Cx<R> f0[NO], p0[NO];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            fb[cc] = phi.p ? phi.base(mu, cc) : nullptr;
-            pb[cc] = psi.base(mu, cc);
-            ob[cc] = out.base(mu, cc);
-        }
-        Cx<R> f0[3], p0[3];
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) f0[cc] = p0[cc] = Cx<R>{(R)0, (R)0};
-        if (live && phi.p) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) f0[cc] = phi.ld_at(fb[cc], s);
-        }
+        for (int t = 0; t < NO; ++t) f0[t] = p0[t] = Cx<R>{(R)0, (R)0};
+        if (live && phi.p) phi.ld_owned(mu, s, f0);
         if constexpr (MODE == 1) {
-            if (live) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) p0[cc] = psi.ld_at(pb[cc], s);
-            }
+            if (live) psi.ld_owned(mu, s, p0);
         }
         Cx<R> acc[4][3];
 #pragma unroll
@@ -231,10 +226,7 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
                 }
             }
             Cx<R> pf[4][3];
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int cb = 0; cb < 3; ++cb) pf[sp][cb] = psi.ld(sp, cb, f);
+            psi.ld_all(f, pf);
             __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
@@ -256,26 +248,31 @@ __global__ void __launch_bounds__(256) k_shift(Geo g, LinksRO<R, NR> U, FermRO<R
         __syncthreads();
         double n2 = 0.0;
         if (live) {
+            Cx<R> o[NO];
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
+            for (int t = 0; t < NO; ++t) {
                 Cx<R> v{(R)0, (R)0};
+                const int q = FermLayout<R>::owned(mu, t);
+                if (q >= 0) {  // wave-uniform
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {  // directions in order
-                    const vec2_t<R> q = part[w][3 * mu + cc][lane];
-                    v.re += q.x;
-                    v.im += q.y;
+                    for (int w = 0; w < 4; ++w) {  // directions in order
+                        const vec2_t<R> e = part[w][q][lane];
+                        v.re += e.x;
+                        v.im += e.y;
+                    }
+                    if (phi.p) {
+                        v.re = fma(a, f0[t].re, v.re);
+                        v.im = fma(a, f0[t].im, v.im);
+                    }
+                    n2 = fma((double)v.re, (double)v.re, fma((double)v.im, (double)v.im, n2));
+                    if constexpr (MODE == 1) {
+                        v.re = fma(-c, v.re, p0[t].re);
+                        v.im = fma(-c, v.im, p0[t].im);
+                    }
                 }
-                if (phi.p) {
-                    v.re = fma(a, f0[cc].re, v.re);
-                    v.im = fma(a, f0[cc].im, v.im);
-                }
-                n2 = fma((double)v.re, (double)v.re, fma((double)v.im, (double)v.im, n2));
-                if constexpr (MODE == 1) {
-                    v.re = fma(-c, v.re, p0[cc].re);
-                    v.im = fma(-c, v.im, p0[cc].im);
-                }
-                out.st_at(ob[cc], s, v);
+                o[t] = v;
             }
+            out.st_owned(mu, s, o);
         }
         if (partials) {
             nrm[mu][lane] = n2;
@@ -339,8 +336,9 @@ hipError_t launch_shift(const Geo &g, int prec, int nrows, const void *U, const 
 // components, so the four directions' loads are in flight at once rather
 // than one direction after another.  The four partial sums meet in LDS:
 // every wave writes its twelve components and, after a barrier, wave w adds
-// the four partials of spin w in direction order, applies s0, kappa and
-// norm, and stores spin w.  The order of every sum is fixed,
+// the four partials of the components it owns (FermLayout) in direction
+// order, applies s0, kappa and norm, and stores them.  The order of every
+// sum is fixed,
 // so each site's result does not depend on the launch geometry.
 template <typename R, int NR, int NS, bool DIV>
 __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> psi, FermRO<R> s0, R kappa, R norm,
@@ -364,23 +362,13 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = Cx<R>{(R)0, (R)0};
         const int cmu = coord(x, mu);
-        // spin mu's component bases (this wave stores spin mu), formed outside
-        // the per-lane branches; s0 of spin mu is fetched now so that its
+        // s0 of the components this wave stores is fetched now so that its
         // latency overlaps the hops and the exchange
-        const vec2_t<R> *zb[3];
-        vec2_t<R> *ob[3];
+        constexpr int NO = FermLayout<R>::kOwn;
+        Cx<R> z[NO];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            zb[cc] = s0.p ? s0.base(mu, cc) : nullptr;
-            ob[cc] = out.base(mu, cc);
-        }
-        Cx<R> z[3];
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) z[cc] = Cx<R>{(R)0, (R)0};
-        if (live && s0.p) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) z[cc] = s0.ld_at(zb[cc], s);
-        }
+        for (int t = 0; t < NO; ++t) z[t] = Cx<R>{(R)0, (R)0};
+        if (live && s0.p) s0.ld_owned(mu, s, z);
         if (live && ((mask >> mu) & 1u)) {
             // every load of this direction first, then the arithmetic: one
             // memory round trip per group
@@ -389,13 +377,8 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
             U.template su3<false>(mu, s, uf);   // U_mu(x), also the backward link of x+mu
             U.template su3<false>(mu, bk, ub);  // U_mu(x-mu)
             Cx<R> pf[4][3], pb[4][3];
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int cb = 0; cb < 3; ++cb) {
-                    pf[sp][cb] = psi.ld(sp, cb, f);
-                    pb[sp][cb] = psi.ld(sp, cb, bk);
-                }
+            psi.ld_all(f, pf);
+            psi.ld_all(bk, pb);
             __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
@@ -422,28 +405,33 @@ __global__ void __launch_bounds__(256) k_hop(Geo g, LinksRO<R, NR> U, FermRO<R> 
             }
         __syncthreads();
         if (live) {
+            Cx<R> o[NO];
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
+            for (int t = 0; t < NO; ++t) {
                 Cx<R> v{(R)0, (R)0};
+                const int q = FermLayout<R>::owned(mu, t);
+                if (q >= 0) {  // wave-uniform
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {  // directions in order
-                    const vec2_t<R> q = part[w][3 * mu + cc][lane];
-                    v.re += q.x;
-                    v.im += q.y;
+                    for (int w = 0; w < 4; ++w) {  // directions in order
+                        const vec2_t<R> e = part[w][q][lane];
+                        v.re += e.x;
+                        v.im += e.y;
+                    }
+                    if (s0.p) {
+                        v.re = fma(kappa, v.re, z[t].re);
+                        v.im = fma(kappa, v.im, z[t].im);
+                    } else {
+                        v.re *= kappa;
+                        v.im *= kappa;
+                    }
+                    if constexpr (DIV) {
+                        v.re = v.re / norm;
+                        v.im = v.im / norm;
+                    }
                 }
-                if (s0.p) {
-                    v.re = fma(kappa, v.re, z[cc].re);
-                    v.im = fma(kappa, v.im, z[cc].im);
-                } else {
-                    v.re *= kappa;
-                    v.im *= kappa;
-                }
-                if constexpr (DIV) {
-                    v.re = v.re / norm;
-                    v.im = v.im / norm;
-                }
-                out.st_at(ob[cc], s, v);
+                o[t] = v;
             }
+            out.st_owned(mu, s, o);
         }
     }
 }
@@ -490,10 +478,13 @@ __global__ void __launch_bounds__(256) k_copy_fermion(Geo g, const V *__restrict
     dst[o] = src[o];
 }
 
+// One 16-byte entry per (array, site): 12 arrays of double2 (FP64) or the
+// six paired arrays of FP32 fields.
 hipError_t launch_copy_fermion(const Geo &g, int prec, const void *src, void *dst, hipStream_t st) {
-    const dim3 grid = site_grid(g, 12);
-    if (prec == 0) k_copy_fermion<double2><<<grid, 256, 0, st>>>(g, (const double2 *)src, (double2 *)dst);
-    else k_copy_fermion<float2><<<grid, 256, 0, st>>>(g, (const float2 *)src, (float2 *)dst);
+    if (prec == 0)
+        k_copy_fermion<double2><<<site_grid(g, 12), 256, 0, st>>>(g, (const double2 *)src, (double2 *)dst);
+    else
+        k_copy_fermion<float4><<<site_grid(g, 6), 256, 0, st>>>(g, (const float4 *)src, (float4 *)dst);
     return hipGetLastError();
 }
 

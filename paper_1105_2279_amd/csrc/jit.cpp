@@ -259,16 +259,37 @@ struct spinor { cx c[4][3]; };
 struct link { cx e[3][3]; };
 // the value for direction m of four per-direction values (m run-time, wave-uniform)
 __device__ __forceinline__ int lsel(int m, int a, int b, int c, int d) { return m == 0 ? a : m == 1 ? b : m == 2 ? c : d; }
-// element (component comp, site s) of a structure-of-arrays field with stride S
+typedef real real4 __attribute__((ext_vector_type(4)));
+// element (component comp, site s) of a structure-of-arrays array set with stride S
 __device__ __forceinline__ cx ldc(const real2 *__restrict__ p, long long S, int comp, int s) {
     const real2 v = p[(long long)comp * S + s];
     return cx{v.x, v.y};
 }
+// Dirac fields: component q = 3 spin + colour.  Double: array q of S
+// entries.  Float (PAIRED): components 2k and 2k+1 share the 16-byte entry s
+// of array k, so a spinor is six 16-byte loads.
 __device__ __forceinline__ void ldspinor(const real2 *__restrict__ f, long long S, int s, spinor &r) {
+#if PAIRED
+    const real4 *P = (const real4 *)f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const real4 v = P[(long long)k * S + s];
+        r.c[(2 * k) / 3][(2 * k) % 3] = cx{v.x, v.y};
+        r.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx{v.z, v.w};
+    }
+#else
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) r.c[sp][a] = ldc(f, S, sp * 3 + a, s);
+#endif
+}
+__device__ __forceinline__ void stfermion(real2 *__restrict__ f, long long S, int q, int s, const cx z) {
+#if PAIRED
+    f[((long long)(q >> 1) * S + s) * 2 + (q & 1)] = real2{z.re, z.im};
+#else
+    f[(long long)q * S + s] = real2{z.re, z.im};
+#endif
 }
 // Link (mu, s): direction mu holds 3*NROWS*S complex slots from slot
 // mu*3*NROWS*S on.  Double: one array of S entries per stored element c = 3a+b.
@@ -277,7 +298,6 @@ __device__ __forceinline__ void ldspinor(const real2 *__restrict__ f, long long 
 // four pair arrays.  With NROWS = 2, and for double links (whose stored row 2
 // is that row to rounding for SU(3) links; rows 0 and 1 read, as the
 // hand-written FP64 kernels read them), the third row is conj(row0 x row1).
-typedef real real4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void ldlink(const real2 *__restrict__ U, long long S, int mu, int s, link &u) {
     const real2 *d = U + (long long)mu * 3 * NROWS * S;
 #if PAIRED
@@ -398,7 +418,7 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
            "            const cx z = "
         << res
         << ".c[sp][a];\n"
-           "            out[(long long)(sp * 3 + a) * S + site] = real2{z.re, z.im};\n"
+           "            stfermion(out, S, sp * 3 + a, site, z);\n"
            "            n2 = fma((double)z.re, (double)z.re, fma((double)z.im, (double)z.im, n2));\n"
            "        }\n"
            "    }\n"
@@ -695,13 +715,13 @@ extern "C" int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geo
         return x < y + nb && y < x + na;
     };
     if (overlaps(out, fb, U, lb)) return set_error(QDPX_EALIAS, "qdpx_jit_eval: out overlaps U");
-    const uintptr_t elem = k.prec == QDPX_F64 ? 16 : 8;  // fields are accessed one complex element at a time
-    if ((uintptr_t)out % elem) return set_error(QDPX_EINVAL, "qdpx_jit_eval: out not aligned to its element size");
+    const uintptr_t elem = 16;  // fields are read 16 bytes at a time (FP32 components in pairs)
+    if ((uintptr_t)out % elem) return set_error(QDPX_EINVAL, "qdpx_jit_eval: out not 16-byte aligned");
     if (norm2 && ((uintptr_t)work & 15u)) return set_error(QDPX_EINVAL, "qdpx_jit_eval: workspace not 16-byte aligned");
     for (int i = 0; i < k.n_fields; ++i) {
         if (!fields[i]) return set_error(QDPX_EINVAL, "qdpx_jit_eval: NULL field");
         if ((uintptr_t)fields[i] % elem)
-            return set_error(QDPX_EINVAL, "qdpx_jit_eval: field not aligned to its element size");
+            return set_error(QDPX_EINVAL, "qdpx_jit_eval: field not 16-byte aligned");
         if (overlaps(out, fb, fields[i], fb)) return set_error(QDPX_EALIAS, "qdpx_jit_eval: out overlaps a field");
     }
     if (k.n_scalars && !scalars) return set_error(QDPX_EINVAL, "qdpx_jit_eval: scalars is NULL");

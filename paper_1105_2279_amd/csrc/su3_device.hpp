@@ -350,32 +350,103 @@ template <typename R, int NR> struct LinksWO {
 };
 
 // --------------------------------------------------------- SoA Dirac field
-// Element (spin, colour) of site s is at p[(spin*3 + colour)*S + s].
+// Component q = 3*spin + colour of site s.  FP64: its own array of S double2,
+// p[q*S + s].  FP32: components 2k and 2k+1 share the 16-byte entry s of
+// array k (k = 0..5; q even in the low half), so a whole spinor is six
+// 16-byte loads.
+//
+// The hop kernels split a site group's epilogue over four waves; wave w
+// finalises and stores the components it owns.  FP64: spin w, components
+// 3w + t (t < 3).  FP32: the whole pairs k = w and, for w < 2, k = w + 4
+// (slot t is component 2k + (t & 1) of pair k = w + 4 (t >> 1)), so no
+// 16-byte entry is ever written in halves by two waves.
+template <typename R> struct FermLayout {
+    static constexpr bool kPaired = sizeof(R) == 4;
+    static constexpr int kOwn = kPaired ? 4 : 3;  // component slots per wave
+    // component in slot t of wave w, or -1 where the slot is empty
+    __device__ __forceinline__ static int owned(int w, int t) {
+        if constexpr (kPaired) {
+            const int k = w + 4 * (t >> 1);
+            return k < 6 ? 2 * k + (t & 1) : -1;
+        } else {
+            return 3 * w + t;
+        }
+    }
+};
+
 template <typename R> struct FermRO {
     const vec2_t<R> *__restrict__ p;
     int64_t S;
-    __device__ __forceinline__ Cx<R> ld(int sp, int c, int s) const {
-        const vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
-        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
-        return Cx<R>{v.x, v.y};
+    using Lay = FermLayout<R>;
+    // the whole spinor of site s
+    __device__ __forceinline__ void ld_all(int s, Cx<R> (&e)[4][3]) const {
+        if constexpr (Lay::kPaired) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const char *b = (const char *)sbase((const char *)p + (int64_t)k * S * 16);
+                const nv4_t<R> v = *gptr<nv4_t<R>>(b + voff((uint32_t)s * 16u));
+                e[(2 * k) / 3][(2 * k) % 3] = Cx<R>{v.x, v.y};
+                e[(2 * k + 1) / 3][(2 * k + 1) % 3] = Cx<R>{v.z, v.w};
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const char *b = (const char *)sbase(p + (int64_t)q * S);
+                const nv2_t<R> v = *gptr<nv2_t<R>>(b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
+                e[q / 3][q % 3] = Cx<R>{v.x, v.y};
+            }
+        }
     }
-    // component base, for accesses whose component index is only wave-uniform
-    __device__ __forceinline__ const vec2_t<R> *base(int sp, int c) const { return sbase(p + (int64_t)(sp * 3 + c) * S); }
-    __device__ __forceinline__ Cx<R> ld_at(const vec2_t<R> *b, int s) const {
-        const nv2_t<R> v = *gptr<nv2_t<R>>((const char *)b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
-        return Cx<R>{v.x, v.y};
+    // the components wave w owns at site s; empty slots are left untouched
+    __device__ __forceinline__ void ld_owned(int w, int s, Cx<R> (&z)[Lay::kOwn]) const {
+        if constexpr (Lay::kPaired) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = w + 4 * h;
+                if (k < 6) {  // wave-uniform
+                    const char *b = (const char *)sbase((const char *)p + (int64_t)k * S * 16);
+                    const nv4_t<R> v = *gptr<nv4_t<R>>(b + voff((uint32_t)s * 16u));
+                    z[2 * h] = Cx<R>{v.x, v.y};
+                    z[2 * h + 1] = Cx<R>{v.z, v.w};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const char *b = (const char *)sbase(p + (int64_t)(3 * w + t) * S);
+                const nv2_t<R> v = *gptr<nv2_t<R>>(b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)));
+                z[t] = Cx<R>{v.x, v.y};
+            }
+        }
     }
 };
 template <typename R> struct FermWO {
     vec2_t<R> *__restrict__ p;
     int64_t S;
-    __device__ __forceinline__ void st(int sp, int c, int s, const Cx<R> &z) const {
-        vec2_t<R> *base = sbase(p + (int64_t)(sp * 3 + c) * S);
-        store_stream<R>((char *)base + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), z.re, z.im);
-    }
-    __device__ __forceinline__ vec2_t<R> *base(int sp, int c) const { return sbase(p + (int64_t)(sp * 3 + c) * S); }
-    __device__ __forceinline__ void st_at(vec2_t<R> *b, int s, const Cx<R> &z) const {
-        store_stream<R>((char *)b + voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)), z.re, z.im);
+    using Lay = FermLayout<R>;
+    // the components wave w owns at site s, streamed past the caches
+    __device__ __forceinline__ void st_owned(int w, int s, const Cx<R> (&z)[Lay::kOwn]) const {
+        if constexpr (Lay::kPaired) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = w + 4 * h;
+                if (k < 6) {  // wave-uniform
+                    nv4_t<R> v;
+                    v.x = z[2 * h].re;
+                    v.y = z[2 * h].im;
+                    v.z = z[2 * h + 1].re;
+                    v.w = z[2 * h + 1].im;
+                    char *b = (char *)sbase((char *)p + (int64_t)k * S * 16);
+                    __builtin_nontemporal_store(v, gptr_w<nv4_t<R>>(b + voff((uint32_t)s * 16u)));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                store_stream<R>((char *)sbase(p + (int64_t)(3 * w + t) * S) +
+                                    voff((uint32_t)s * (uint32_t)sizeof(vec2_t<R>)),
+                                z[t].re, z[t].im);
+        }
     }
 };
 

@@ -439,11 +439,11 @@ def test_misaligned_links_rejected():
             with pytest.raises(q.QdpxError) as e:
                 call()
             assert e.value.code == -1 and "aligned" in str(e.value)
-        # Dirac fields: aligned to their complex element (8 bytes F32, 16 F64)
+        # Dirac fields: 16-byte aligned (FP32 components are read in pairs)
         fb = q.qdpx_fermion_bytes(L, prec)
         fbig = q.empty_bytes(3 * fb + 64)
         psi, chi = fbig[:fb], fbig[fb + 64:2 * fb + 64]
-        off = 4 if prec == q.F32 else 8
+        off = 8  # aligned to a complex element in either precision, not to 16 bytes
         bad = fbig[2 * fb + 64 + off:3 * fb + 64 + off - 16]
         shift_ws = q.alloc_workspace(q.OP_SHIFT, L, prec, fmt, 1)
         for call in (lambda: q.qdpx_eval_hop(c, L, prec, fmt, good, bad, chi, 0xF),
