@@ -284,11 +284,17 @@ __device__ __forceinline__ void ldspinor(const real2 *__restrict__ f, long long 
         for (int a = 0; a < 3; ++a) r.c[sp][a] = ldc(f, S, sp * 3 + a, s);
 #endif
 }
-__device__ __forceinline__ void stfermion(real2 *__restrict__ f, long long S, int q, int s, const cx z) {
+__device__ __forceinline__ void stspinor(real2 *__restrict__ f, long long S, int s, const spinor &r) {
 #if PAIRED
-    f[((long long)(q >> 1) * S + s) * 2 + (q & 1)] = real2{z.re, z.im};
+    real4 *P = (real4 *)f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cx a = r.c[(2 * k) / 3][(2 * k) % 3], b = r.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
+        P[(long long)k * S + s] = real4{a.re, a.im, b.re, b.im};
+    }
 #else
-    f[(long long)q * S + s] = real2{z.re, z.im};
+#pragma unroll
+    for (int q = 0; q < 12; ++q) f[(long long)q * S + s] = real2{r.c[q / 3][q % 3].re, r.c[q / 3][q % 3].im};
 #endif
 }
 // Link (mu, s): direction mu holds 3*NROWS*S complex slots from slot
@@ -413,12 +419,12 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
     const std::string c[4] = {"x0", "x1", "x2", "x3"};
     const std::string res = g.emit(root, "site", c);
     src << g.body.str();
-    src << "#pragma unroll\n    for (int sp = 0; sp < 4; ++sp)\n#pragma unroll\n"
+    src << "    stspinor(out, S, site, " << res << ");\n"
+        << "#pragma unroll\n    for (int sp = 0; sp < 4; ++sp)\n#pragma unroll\n"
            "        for (int a = 0; a < 3; ++a) {\n"
            "            const cx z = "
         << res
         << ".c[sp][a];\n"
-           "            stfermion(out, S, sp * 3 + a, site, z);\n"
            "            n2 = fma((double)z.re, (double)z.re, fma((double)z.im, (double)z.im, n2));\n"
            "        }\n"
            "    }\n"
