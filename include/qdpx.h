@@ -413,9 +413,13 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * every link loaded through the caches; 1: each 64-site group's own links,
  * rows 0 and 1, staged in LDS once for the four direction waves; 2: also
  * every site's backward links U_mu(x-mu), columns 0 and 1, which the lower
- * staples of the other three directions read; 0 in every other case: the
- * FP64 step always exchanges backward links through LDS, and the shift, hop
- * and chain kernels meet their per-direction partial sums there).
+ * staples of the other three directions read; 3: also the plane products
+ * U_mu(x+nu) U_nu(x+mu)^dag, which the upper staples of U_mu(x) and U_nu(x)
+ * share, formed by one of the two direction waves and passed to the other
+ * through LDS; 4: the own links and the plane products, the backward links
+ * loaded; 0 in every other case: the FP64 step always exchanges backward
+ * links through LDS, and the shift, hop and chain kernels meet their
+ * per-direction partial sums there).
  * This is the auto-tuning of the thread geometry the paper proposes
  * (sections 5.4 and 9).  Allocates and frees temporary device buffers and
  * synchronises the device, so it returns QDPX_ECAPTURE on a capturing
@@ -425,7 +429,7 @@ int qdpx_jit_eval(qdpx_ctx *ctx, int32_t kernel, const qdpx_geom *geom, const vo
  * (every output pointer of qdpx_tune_get is nullable; *source receives 0
  * for the default geometry, 1 for one read from the launch table, 2 for one
  * qdpx_tune found, 3 for one qdpx_tune_set gave; a launch table written
- * without lds_tile gives the default, 2 for the FP32 APE step, else 0);
+ * without lds_tile gives the default, 4 for the FP32 APE step, else 0);
  * t_window must divide Lt and only matters when Lx is a multiple of 8 and Ly
  * of 8 (or Lx of 16 and Ly of 4).  For QDPX_OP_BATCHED (tuned by
  * qdpx_tune_batched, which qdpx_tune refuses with QDPX_EUNSUPPORTED) block is

@@ -367,9 +367,9 @@ def qdpx_tune_save(ctx, path=None):
 
 
 def qdpx_tune_set(ctx, op, L, prec, fmt, block, sites_per_thread, xcd_map, t_window=1, lds_tile=None):
-    """lds_tile None: the default (2 for the FP32 APE step, else 0)."""
+    """lds_tile None: the default (4 for the FP32 APE step, else 0)."""
     if lds_tile is None:
-        lds_tile = 2 if (op == OP_APE and prec == F32) else 0
+        lds_tile = 4 if (op == OP_APE and prec == F32) else 0
     _check(lib().qdpx_tune_set(ctx.handle, op, ctypes.byref(geom(L)), prec, fmt, int(block),
                                int(sites_per_thread), int(xcd_map), int(t_window), int(lds_tile)), "qdpx_tune_set")
 

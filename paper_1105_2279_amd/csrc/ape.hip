@@ -27,19 +27,23 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     // U_nu(x), the own link of wave nu (24 KB per 512-thread block); LDS = 2
     // adds each site's four backward links U_mu(x-mu) (columns 0 and 1), which
     // the lower staples of the three other directions all read (another
-    // 24 KB).  Staged values are the ones the loads would give: every LDS
-    // level yields the same bits.
+    // 24 KB); LDS = 3 adds four slots per group through which the producer of
+    // each plane passes its upper product to the consumer (staple_sum_rows01_shared,
+    // another 12 KB); LDS = 4 has the own links and the slots but loads the
+    // backward links (24 KB in all).  Staged values are the ones the loads
+    // would give and every level does the same arithmetic: all levels yield
+    // the same bits.
     static_assert(MODE == kApe || sizeof(R) == 8, "FP32 steps take their plaquettes from k_plaquette");
     static_assert(LDS == 0 || (sizeof(R) == 4 && PROJ == 0), "LDS tiles belong to the FP32 row projection");
     // Dynamic LDS, sized at launch: kF64BackPerWave double2 per wave (FP64), or
-    // per group the own links then (LDS = 2) the backward links, 4*3*64
-    // FP32 pairs each.
+    // per group ape_lds_f4_per_group(LDS) FP32 pairs: the own links, then
+    // (LDS >= 2) the backward links, then (LDS = 3) the two product slots.
     extern __shared__ double2 lds_dyn[];
     if constexpr (LDS > 0) {
-        constexpr int kTile = 4 * 3 * 64;
         nv4_t<R> *tiles = reinterpret_cast<nv4_t<R> *>(lds_dyn);
-        nv4_t<R> *mine = tiles + (w >> 2) * LDS * kTile;
-        nv4_t<R> *mine_back = LDS == 2 ? mine + kTile : nullptr;
+        nv4_t<R> *mine = tiles + (w >> 2) * ape_lds_f4_per_group(LDS);
+        nv4_t<R> *mine_back = ape_lds_back(LDS) ? mine + kApeTileF4 : nullptr;
+        nv4_t<R> *mine_slots = ape_lds_slots(LDS) ? mine + (ape_lds_back(LDS) ? 2 : 1) * kApeTileF4 : nullptr;
 #pragma unroll 1
         for (int j = 0; j < NS; ++j) {  // no early exit: every wave meets every barrier
             const int i = (tile * NS + j) * gpb + (w >> 2);
@@ -48,10 +52,12 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
             if (j > 0) __syncthreads();  // the previous group's copies have been read
             if (valid) {
                 stage_own_link(g, U, grp, mu, lane, mine);
-                if constexpr (LDS == 2) stage_back_link(g, U, grp, mu, lane, mine_back);
+                if constexpr (ape_lds_back(LDS)) stage_back_link(g, U, grp, mu, lane, mine_back);
             }
             __syncthreads();
-            if (valid)
+            if constexpr (ape_lds_slots(LDS))  // block barriers inside: every wave takes part
+                ape_group_shared<R, NR>(g, U, out, c1, c2, mask, grp, valid, mu, lane, mine, mine_back, mine_slots);
+            else if (valid)
                 ape_group<R, NR, MODE, PROJ>(g, U, out, c1, c2, mask, partials, grp, mu, lane, mine, nullptr,
                                              mine_back);
         }
@@ -86,7 +92,7 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     const int xcd = launch_order(g, cfg, per_block);
     const int lds_level = (prec != 0 && !proj) ? cfg.lds : 0;
     const size_t lds64 = (prec == 0 && !proj) ? sizeof(double2) * kF64BackPerWave * (cfg.block / 64)
-                                              : (size_t)16 * 4 * 3 * 64 * lds_level * gpb;
+                                              : (size_t)16 * ape_lds_f4_per_group(lds_level) * gpb;
 #define QDPX_APE_LAUNCH(R, NR, NS, M, P, T)                                                                      \
     k_ape_step<R, NR, NS, M, P, T><<<grid, cfg.block, lds64, st>>>(g, LinksRO<R, NR>{(const vec2_t<R> *)Uin, g.S}, \
                                                                 LinksWO<R, NR>{(vec2_t<R> *)Uout, g.S}, c1, c2,   \
@@ -97,6 +103,8 @@ hipError_t launch_ape_step(const Geo &g, int prec, int nrows, const void *Uin, v
     else QDPX_APE_LAUNCH(double, 3, NS, kApe, 0, 0);
 #define QDPX_APE_M32(NR, NS)                                           \
     if (proj) QDPX_APE_LAUNCH(float, NR, NS, kApe, 1, 0);              \
+    else if (lds_level == 4) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 4); \
+    else if (lds_level == 3) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 3); \
     else if (lds_level == 2) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 2); \
     else if (lds_level == 1) QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 1); \
     else QDPX_APE_LAUNCH(float, NR, NS, kApe, 0, 0);

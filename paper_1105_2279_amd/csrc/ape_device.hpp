@@ -302,69 +302,192 @@ template <typename R> __device__ __forceinline__ void back_cols01(const nv4_t<R>
     }
 }
 
-// Staple sum (rows 0 and 1) of link (s, mu) over the planes (mu, nu) with nu
-// in mask (bits 0..3).  own / back: the group's own links and backward links
-// staged in LDS (FP32), or nullptr to load them.
+// ------------------------------------------------ FP32 staple sum by plane
+// The upper staples of U_mu(x) and U_nu(x) share one product: with
+// P = U_mu(x+nu) U_nu(x+mu)^dag the upper staple of U_mu(x) is U_nu(x) P and
+// that of U_nu(x) is U_mu(x) P^dag.  In each plane of a site one of the two
+// directions, the producer d, forms P_d = U_d(x+c) U_c(x+d)^dag (c the other
+// direction, the consumer): rows 0 and 1 as rows 0 and 1 of U_d(x+c) times
+// U_c(x+d)^dag, row 2 rebuilt as conj(row0 x row1), P being SU(3) to
+// rounding.  d is the lower direction in even groups and the higher one in
+// odd groups, so two neighbouring groups form equally many products per
+// direction.  The staple sum of U_mu(x) takes the planes nu = mu^1, mu^2,
+// mu^3 in that order; in each the lower staple is added to the sum and then
+// the upper one, formed on its own: U_c(x) P_d for the producer,
+// U_d(x) P_d^dag for the consumer.  Whether each wave forms the products it
+// needs (staple_sum_rows01) or a plane's product is formed once and passed
+// to the consumer through LDS (staple_sum_rows01_shared), the arithmetic
+// and its order are the same, so every path gives the same bits.
+__device__ __forceinline__ bool plane_producer(int mu, int nu, int grp) { return (mu < nu) != ((grp & 1) != 0); }
+
+// P = U_d(x+c) U_c(x+d)^dag, rows 0 and 1 formed, row 2 rebuilt.
+template <typename R, int NR>
+__device__ __forceinline__ void plane_product(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int d, int c,
+                                              M3<R> &P) {
+    M23<R> B;
+    U.rows01(d, hop_fwd(g, x.s, site_coord<R>(x, c), c), B);
+    M3<R> C;
+    U.full(c, hop_fwd(g, x.s, site_coord<R>(x, d), d), C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Cx<R> t{(R)0, (R)0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_cb(t, B.e[i][k], C.e[j][k]);
+            P.e[i][j] = t;
+        }
+    rebuild_row2(P);
+}
+
+// X = rows 0 and 1 of the upper staple from the plane's product: A P_d for
+// the producer, A P_d^dag for the consumer (A = rows 0 and 1 of U_nu(x)).
+template <typename R>
+__device__ __forceinline__ void upper_staple(const M23<R> &A, const M3<R> &P, bool prod, M23<R> &X) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
+    if (prod) acc_23_33(X, A, P);  // wave-uniform
+    else acc_23_33dag(X, A, P);
+}
+// S += X
+template <typename R> __device__ __forceinline__ void add_23(M23<R> &S, const M23<R> &X) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            S.e[i][j].re += X.e[i][j].re;
+            S.e[i][j].im += X.e[i][j].im;
+        }
+}
+
+// S += rows 0 and 1 of the lower staple U_nu(y)^dag U_mu(y) U_nu(y+mu),
+// y = x - nu.  back: the group's backward links staged in LDS (FP32), or
+// nullptr to load U_nu(y).
+template <typename R, int NR>
+__device__ __forceinline__ void add_lower_staple(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu, int nu,
+                                                 M23<R> &S, const nv4_t<R> *back) {
+    const int y = hop_bwd(g, x.s, site_coord<R>(x, nu), nu);
+    M3<R> A;
+    if (back) back_cols01(back, nu, A);  // wave nu's backward link, staged in LDS
+    else U.full(nu, y, A);
+    M3<R> B;
+    U.full(mu, y, B);
+    M23<R> T;
+    mul_dag23_33(A, B, T);
+    M3<R> C;
+    U.full(nu, hop_fwd(g, y, site_coord<R>(x, mu), mu), C);  // y has the same mu-coordinate as x
+    acc_23_33(S, T, C);
+}
+
+// Staple sum (rows 0 and 1) of link (x, mu) of group grp over the planes
+// (mu, nu) with nu in mask (bits 0..3), every product formed by this wave.
+// own / back: the group's own links and backward links staged in LDS (FP32),
+// or nullptr to load them.
 template <typename R, int NR>
 __device__ __forceinline__ void staple_sum_rows01(const Geo &g, const LinksRO<R, NR> &U, const Site &x, int mu,
-                                                  unsigned mask, M23<R> &S, const nv4_t<R> *own = nullptr,
+                                                  int grp, unsigned mask, M23<R> &S, const nv4_t<R> *own = nullptr,
                                                   const nv4_t<R> *back = nullptr) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
-    const int s = x.s;
-    const int s_mu = hop_fwd(g, s, site_coord<R>(x, mu), mu);
 #pragma unroll 1
-    for (int k = 0; k < 3; ++k) {
-        const int nu = k + (k >= mu);
+    for (int p = 0; p < 3; ++p) {
+        const int nu = mu ^ (p + 1);
         if (!((mask >> nu) & 1u)) continue;  // wave-uniform
-        // upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
-        {
-            M23<R> A;
-            if (own) own_rows01(own, nu, A);  // wave nu's own link, staged in LDS
-            else U.rows01(nu, s, A);
-            M3<R> B;
-            U.full(mu, hop_fwd(g, s, site_coord<R>(x, nu), nu), B);
-            M23<R> T;
-            mul_23_33(A, B, T);
-            M3<R> C;
-            U.full(nu, s_mu, C);
-            if (nu < mu) {
-                // Two wave-uniform code paths (this staple formed on its own,
-                // then added) keep the compiler from scheduling the plane as
-                // one block: 73 registers instead of 96 for LINK12 (six waves
-                // per SIMD instead of five, 3 % faster as measured).
-                M23<R> X;
+        const bool prod = plane_producer(mu, nu, grp);
+        // the upper staple X is formed on its own, the lower one added to S,
+        // then X: in this order the compiler keeps 77 registers (LDS tile 2,
+        // FP32-12) instead of 105 with the lower staple first
+        M3<R> P;
+        plane_product(g, U, x, prod ? mu : nu, prod ? nu : mu, P);
+        M23<R> A;                         // rows 0 and 1 of U_nu(x)
+        if (own) own_rows01(own, nu, A);  // wave nu's own link, staged in LDS
+        else U.rows01(nu, x.s, A);
+        M23<R> X;
+        upper_staple(A, P, prod, X);
+        add_lower_staple(g, U, x, mu, nu, S, back);
+        add_23(S, X);
+    }
+}
+
+// The FP32 step's LDS tile levels: 1 own links, 2 own and backward links,
+// 3 own and backward links and four slots (two per phase, even and odd
+// phases apart) for the products the producers of a phase pass to their
+// consumers, 4 own links and the slots (backward links loaded).  A slot
+// holds 3 entries per lane: rows 0 and 1 of P in pairs; the reader
+// rebuilds row 2 from them exactly as plane_product did.
+constexpr int kApeTileF4 = 4 * 3 * 64;
+constexpr int kApeSlotF4 = 3 * 64;
+__host__ __device__ constexpr bool ape_lds_back(int level) { return level == 2 || level == 3; }
+__host__ __device__ constexpr bool ape_lds_slots(int level) { return level >= 3; }
+// float4 entries per 64-site group: own links, backward links, slots in
+// that order
+__host__ __device__ constexpr int ape_lds_f4_per_group(int level) {
+    return (level >= 1 ? kApeTileF4 : 0) + (ape_lds_back(level) ? kApeTileF4 : 0) +
+           (ape_lds_slots(level) ? 4 * kApeSlotF4 : 0);
+}
+
+// staple_sum_rows01 with each plane's product formed once: in phase p the
+// four waves of the group take the planes (mu, mu ^ (p + 1)); the two
+// producers store rows 0 and 1 of P_d in the plane's LDS slot (slots of
+// even and odd phases apart, so each slot is rewritten only two phases
+// later, after a barrier its readers have passed), both add their lower
+// staples, and after one block barrier the consumers read P_d.  Contains
+// block barriers: every wave of the block calls it, with work false where
+// its group is past the end or its direction is not smeared (it then only
+// meets the barriers).
+template <typename R, int NR>
+__device__ __forceinline__ void staple_sum_rows01_shared(const Geo &g, const LinksRO<R, NR> &U, const Site &x,
+                                                         int mu, int grp, bool work, unsigned mask, M23<R> &S,
+                                                         const nv4_t<R> *own, const nv4_t<R> *back,
+                                                         nv4_t<R> *slots) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) X.e[i][j] = Cx<R>{(R)0, (R)0};
-                acc_23_33dag(X, T, C);
+        for (int j = 0; j < 3; ++j) S.e[i][j] = Cx<R>{(R)0, (R)0};
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) {
+        const int nu = mu ^ (p + 1);
+        const bool act = work && ((mask >> nu) & 1u);  // wave-uniform; the same for both waves of the plane
+        const bool prod = plane_producer(mu, nu, grp);
+        const int lo = mu < nu ? mu : nu;
+        nv4_t<R> *slot = slots + (2 * (p & 1) + (p == 0 ? lo >> 1 : lo)) * kApeSlotF4;  // the phase's two planes
+        if (act) {
+            if (prod) {
+                M3<R> P;
+                plane_product(g, U, x, mu, nu, P);
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        S.e[i][j].re += X.e[i][j].re;
-                        S.e[i][j].im += X.e[i][j].im;
-                    }
-            } else {
-                acc_23_33dag(S, T, C);
+                for (int k = 0; k < 3; ++k) {
+                    const Cx<R> &z0 = P.e[(2 * k) / 3][(2 * k) % 3], &z1 = P.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+                    nv4_t<R> v;
+                    v.x = z0.re;
+                    v.y = z0.im;
+                    v.z = z1.re;
+                    v.w = z1.im;
+                    slot[k * 64 + lane] = v;
+                }
             }
+            add_lower_staple(g, U, x, mu, nu, S, back);
         }
-        // lower: U_nu(y)^dag U_mu(y) U_nu(y+mu), y = x - nu
-        {
-            const int y = hop_bwd(g, s, site_coord<R>(x, nu), nu);
-            M3<R> A;
-            if (back) back_cols01(back, nu, A);  // wave nu's backward link, staged in LDS
-            else U.full(nu, y, A);
-            M3<R> B;
-            U.full(mu, y, B);
-            M23<R> T;
-            mul_dag23_33(A, B, T);
-            M3<R> C;
-            U.full(nu, hop_fwd(g, y, site_coord<R>(x, mu), mu), C);  // y has the same mu-coordinate as x
-            acc_23_33(S, T, C);
+        __syncthreads();  // this phase's products are in LDS
+        if (act) {
+            M3<R> P;  // P_d, re-read by the producer too: the same bits it stored
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const nv4_t<R> v = slot[k * 64 + lane];
+                P.e[(2 * k) / 3][(2 * k) % 3] = Cx<R>{v.x, v.y};
+                P.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = Cx<R>{v.z, v.w};
+            }
+            rebuild_row2(P);
+            M23<R> A;  // rows 0 and 1 of U_nu(x)
+            own_rows01(own, nu, A);
+            M23<R> X;
+            upper_staple(A, P, prod, X);
+            add_23(S, X);
         }
     }
 }
@@ -413,6 +536,27 @@ __device__ __forceinline__ void store_narrowed(const LinksWO<R, NR> &out, int mu
 #pragma unroll
         for (int b = 0; b < 3; ++b) o[a][b] = Cx<R>{(R)v[a][b].re, (R)v[a][b].im};
     out.store(mu, s, o);
+}
+
+// W = c1 U_mu(x) + c2 S (rows 0 and 1, in FP64), projected by rows in FP64
+// and stored in link precision.  own: the group's own links in LDS, or
+// nullptr to load U_mu(x).
+template <typename R, int NR>
+__device__ __forceinline__ void finish_rows01(const LinksRO<R, NR> &U, const LinksWO<R, NR> &out, double c1,
+                                              double c2, int mu, int s, const M23<R> &S, const nv4_t<R> *own) {
+    M23<R> u0;
+    if (own) own_rows01(own, mu, u0);
+    else U.rows01(mu, s, u0);
+    Cx<double> wm[2][3], v[3][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            wm[i][jj].re = fma(c2, (double)S.e[i][jj].re, c1 * (double)u0.e[i][jj].re);
+            wm[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u0.e[i][jj].im);
+        }
+    reunitarise(wm, v);
+    store_narrowed(out, mu, s, v);
 }
 
 // What one (64-site group, direction) wave computes.
@@ -724,20 +868,34 @@ __device__ __forceinline__ void ape_group(const Geo &g, const LinksRO<R, NR> &U,
             polar_project(w, v);
             store_narrowed(out, mu, s, v);
         } else {
-            M23<R> S, u0;
-            staple_sum_rows01<R, NR>(g, U, x, mu, mask, S, own, back);
-            if (own) own_rows01(own, mu, u0);
-            else U.rows01(mu, s, u0);
-            Cx<double> wm[2][3], v[3][3];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) {
-                    wm[i][jj].re = fma(c2, (double)S.e[i][jj].re, c1 * (double)u0.e[i][jj].re);
-                    wm[i][jj].im = fma(c2, (double)S.e[i][jj].im, c1 * (double)u0.e[i][jj].im);
-                }
-            reunitarise(wm, v);
-            store_narrowed(out, mu, s, v);
+            M23<R> S;
+            staple_sum_rows01<R, NR>(g, U, x, mu, grp, mask, S, own, back);
+            finish_rows01<R, NR>(U, out, c1, c2, mu, s, S, own);
+        }
+    }
+}
+
+// ape_group for the FP32 step at LDS tile level 3 (each plane's upper
+// product formed once and passed through LDS).  Contains block barriers:
+// every wave of the block calls it; valid is false for a group past the end.
+template <typename R, int NR>
+__device__ __forceinline__ void ape_group_shared(const Geo &g, const LinksRO<R, NR> &U, const LinksWO<R, NR> &out,
+                                                 double c1, double c2, unsigned mask, int grp, bool valid, int mu,
+                                                 int lane, const nv4_t<R> *own, const nv4_t<R> *back,
+                                                 nv4_t<R> *slots) {
+    Site x;
+    const bool live = valid && group_site(g, grp, lane, x);
+    if (!live) x.init(g, 0);  // padding lanes and groups past the end compute on site 0 and store nothing
+    const bool smear = (mask >> mu) & 1u;
+    M23<R> S;
+    staple_sum_rows01_shared<R, NR>(g, U, x, mu, grp, valid && smear, mask, S, own, back, slots);
+    if (live) {
+        if (!smear) {  // wave-uniform: not smeared
+            M3<R> u;
+            U.full(mu, x.s, u);
+            out.store(mu, x.s, u.e);
+        } else {
+            finish_rows01<R, NR>(U, out, c1, c2, mu, x.s, S, own);
         }
     }
 }

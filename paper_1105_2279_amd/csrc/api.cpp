@@ -106,8 +106,9 @@ static void log_cfg(const char *what, const TuneKey &k, const LaunchCfg &c) {
 }
 
 // LDS tile of the FP32 APE step when nothing chose one: the group's own
-// links and backward links staged.  Every other case has no LDS tile level.
-static const int kDefaultApeLds = 2;
+// links and the plane products staged.  Every other case has no LDS tile
+// level.
+static const int kDefaultApeLds = 4;
 static int default_lds(int op, int prec) { return (op == QDPX_OP_APE && prec == QDPX_F32) ? kDefaultApeLds : 0; }
 
 static bool cfg_valid(qdpx_op op, qdpx_prec prec, const LaunchCfg &c);
@@ -863,8 +864,8 @@ static bool cfg_valid(qdpx_op op, qdpx_prec prec, const LaunchCfg &c) {
     if (c.block < 64 || c.block > 1024 || (c.block % 64)) return false;
     if (c.xcd < 0 || c.xcd > 2) return false;
     if (c.tw != 1 && c.tw != 2 && c.tw != 4 && c.tw != 8 && c.tw != 16) return false;
-    // LDS tile: 0..2 for the FP32 APE step, none (0) elsewhere
-    if (op == QDPX_OP_APE && prec == QDPX_F32 ? (c.lds < 0 || c.lds > 2) : c.lds != 0) return false;
+    // LDS tile: 0..4 for the FP32 APE step, none (0) elsewhere
+    if (op == QDPX_OP_APE && prec == QDPX_F32 ? (c.lds < 0 || c.lds > 4) : c.lds != 0) return false;
     if (op == QDPX_OP_APE) return (c.block == 256 || c.block == 512) && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4);
     if (op == QDPX_OP_SHIFT || op == QDPX_OP_CHAIN || op == QDPX_OP_JACOBI)  // four waves per group, one per direction
         return c.block == 256 && (c.nsite == 1 || c.nsite == 2 || c.nsite == 4 || c.nsite == 8);
@@ -969,7 +970,7 @@ extern "C" int qdpx_tune(qdpx_ctx *ctx, qdpx_op op, const qdpx_geom *geom, qdpx_
             if (op == QDPX_OP_APE) {
                 for (int b : blocks_ape)
                     for (int n : ns_ape)
-                        for (int t = 0; t <= (prec == QDPX_F32 ? 2 : 0); ++t) cands.push_back(LaunchCfg{b, n, x, tw, t});
+                        for (int t = 0; t <= (prec == QDPX_F32 ? 4 : 0); ++t) cands.push_back(LaunchCfg{b, n, x, tw, t});
             } else {
                 for (int n : ns_shift) cands.push_back(LaunchCfg{256, n, x, tw});
             }

@@ -33,8 +33,8 @@
 
 namespace qdpx {
 
-// LDS tile of the FP32 steps (the single-lattice step's levels 1 and 2).
-constexpr int kBatchedLds = 2;
+// LDS tile of the FP32 steps (the single-lattice step's levels 1 to 3).
+constexpr int kBatchedLds = 3;
 
 // Largest number of stage-A values a lattice's plaquette reduction may need
 // (held in LDS): 3*ngroups <= kBatchMaxStage * kFinPerBlock (bounded with 4
@@ -74,17 +74,18 @@ template <typename F> __device__ __forceinline__ int find_lattice(int n_lat, int
 // may then read it (at wave-uniform indices) with scalar loads, as the
 // single-lattice kernels read their geometry from the kernel arguments.
 // GPB 64-site groups are processed at once per block (4 waves each).  FP32:
-// at most 80 registers, six waves per SIMD, what the LDS tile leaves room
-// for (the compiler takes 82 unbounded, five waves; nothing spills).
+// at most 128 registers, four waves per SIMD, what the LDS tile (36 KB per
+// group) leaves room for.
 template <typename R, int NR, int GPB>
-__global__ void __launch_bounds__(256 * GPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1)))
+__global__ void __launch_bounds__(256 * GPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 k_ape_batched(BatchArgs a, const BatchLat *__restrict__ lats) {
     __shared__ unsigned s_ticket;
     __shared__ int s_ok;
     // FP32: the LDS tile of the single-lattice step at level kBatchedLds,
     // each group's own links and (level 2) backward links
     __shared__ nv4_t<R> own[GPB][sizeof(R) == 4 ? 4 * 3 * 64 : 1];
-    __shared__ nv4_t<R> back[GPB][sizeof(R) == 4 && kBatchedLds == 2 ? 4 * 3 * 64 : 1];
+    __shared__ nv4_t<R> back[GPB][sizeof(R) == 4 && ape_lds_back(kBatchedLds) ? kApeTileF4 : 1];
+    __shared__ nv4_t<R> slots[GPB][sizeof(R) == 4 && ape_lds_slots(kBatchedLds) ? 4 * kApeSlotF4 : 1];
     __shared__ double2 back64[sizeof(R) == 8 ? 4 * GPB * kF64BackPerWave : 1];  // FP64: backward links
     // mu is wave-uniform; readfirstlane lets the compiler keep it in an SGPR
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -127,14 +128,17 @@ k_ape_batched(BatchArgs a, const BatchLat *__restrict__ lats) {
                         grp = (L.xcol0[q] + (j - row * ncols)) + L.ncol * row;
                     }
                     if constexpr (sizeof(R) == 4) {  // links staged in LDS, as the single-lattice step
-                        nv4_t<R> *bk = kBatchedLds == 2 ? back[half] : nullptr;
+                        nv4_t<R> *bk = ape_lds_back(kBatchedLds) ? back[half] : nullptr;
                         if (jj > j0) __syncthreads();  // take_ticket's barriers separate items
                         if (valid) {
                             stage_own_link(L.g, U, grp, mu, lane, own[half]);
-                            if constexpr (kBatchedLds == 2) stage_back_link(L.g, U, grp, mu, lane, bk);
+                            if constexpr (ape_lds_back(kBatchedLds)) stage_back_link(L.g, U, grp, mu, lane, bk);
                         }
                         __syncthreads();
-                        if (valid)
+                        if constexpr (ape_lds_slots(kBatchedLds))  // block barriers inside: every wave takes part
+                            ape_group_shared<R, NR>(L.g, U, O, a.c1, a.c2, 0xFu, grp, valid, mu, lane, own[half], bk,
+                                                    slots[half]);
+                        else if (valid)
                             ape_group<R, NR, kApe>(L.g, U, O, a.c1, a.c2, 0xFu, nullptr, grp, mu, lane, own[half],
                                                    nullptr, bk);
                     } else {

@@ -49,7 +49,7 @@ def _key(op, prec, fmt, L):
 
 def default_lds_tile(op, prec):
     """The library's LDS tile for an entry stored without one."""
-    return 2 if (op == "APE" and prec == "F32") else 0
+    return 4 if (op == "APE" and prec == "F32") else 0
 
 
 def read(path=TABLE):

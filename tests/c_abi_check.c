@@ -63,7 +63,7 @@ int main(int argc, char **argv) {
     CHECK(b == 512 && n == 2 && x == 0 && t == 2 && d == 0 && src == 1,
           "stored geometry not read: %d %d %d %d %d source %d", b, n, x, t, d, src);
     CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&
-              src == 0 && b == 256 && d == 2,
+              src == 0 && b == 256 && d == 4,
           "an absent shape is not the default");
     const qdpx_geom g3 = {{16, 8, 4, 8}};
     CHECK(qdpx_tune_get(ctx, QDPX_OP_APE, &g3, QDPX_F32, QDPX_LINK12, &b, &n, &x, &t, &d, &src) == QDPX_OK &&

@@ -66,7 +66,7 @@ def test_launch_table_covers_benchmark_shapes():
     for (op, prec, fmt, L), (block, nsite, xcd, tw, lds) in table.items():
         assert (prec, fmt) in (("F32", "LINK12"), ("F64", "LINK18"), ("F32", "LINK18"))
         assert xcd in (0, 1, 2) and tw in (1, 2, 4, 8, 16) and L[3] % tw == 0
-        assert lds in ((0, 1, 2) if (op, prec) == ("APE", "F32") else (0,))
+        assert lds in ((0, 1, 2, 3, 4) if (op, prec) == ("APE", "F32") else (0,))
         if op == "BATCHED":  # block, groups per ticket
             assert block in (256, 512) and nsite in (1, 2, 4, 8)
         elif op == "APE":

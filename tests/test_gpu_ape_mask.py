@@ -119,15 +119,16 @@ def test_mask_validation():
 @pytest.mark.parametrize("fmt", [q.LINK12, q.LINK18], ids=["f32_12", "f32_18"])
 @pytest.mark.parametrize("mask", [0x7, 0x5])
 def test_masked_links_do_not_depend_on_the_lds_tile(fmt, mask):
-    """The FP32 step's LDS tile (none, own links, own and backward links)
-    changes where links are read from, never a bit of the result, also when
-    only some directions are smeared."""
+    """The FP32 step's LDS tile (none, own links, own and backward links,
+    and each plane's upper product formed once and passed through LDS)
+    changes where links and products come from, never a bit of the result,
+    also when only some directions are smeared."""
     L = (16, 8, 4, 8)
     U = latgen.haar_links(L, 4500 + mask)
     c = q.Context(0)
     res = []
-    for lds in (0, 1, 2):
-        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, fmt, 256, 1, 1, 1, lds)
+    for block, lds in ((256, 0), (256, 1), (256, 2), (256, 3), (512, 3), (256, 4)):
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, fmt, block, 1, 1, 1, lds)
         res.append(run(L, U, q.F32, fmt, 2, mask, context=c))
     for V, _, p in res[1:]:
         assert np.array_equal(V.view(np.float64), res[0][0].view(np.float64))

@@ -303,9 +303,13 @@ def test_geometries_are_bit_identical(L):
     c = ctx()
     results_ape, results_shift = [], []
     # the LDS tile of the FP32 step (0 none, 1 own links, 2 own and backward
-    # links) is one more launch choice that must not change a bit
+    # links, 3 also each plane's upper product passed between its two waves,
+    # 4 own links and the products)
+    # is one more launch choice that must not change a bit
     for block, ns, xcd, tw, lds in [(256, 1, 1, 1, 2), (256, 1, 0, 2, 1), (512, 2, 1, 4, 0), (256, 4, 0, 8, 2),
-                                    (256, 2, 2, 1, 0), (512, 1, 2, 1, 1), (512, 2, 2, 1, 2)]:
+                                    (256, 2, 2, 1, 0), (512, 1, 2, 1, 1), (512, 2, 2, 1, 2), (256, 1, 1, 1, 3),
+                                    (512, 1, 2, 1, 3), (512, 2, 0, 2, 3), (256, 4, 1, 1, 3), (256, 1, 2, 1, 4),
+                                    (512, 2, 1, 1, 4)]:
         if L[3] % tw:
             tw = 2
         q.qdpx_tune_set(c, q.OP_APE, L, q.F32, q.LINK12, block, ns, xcd, tw, lds)
@@ -323,12 +327,33 @@ def test_geometries_are_bit_identical(L):
     q.qdpx_tune_set(c, q.OP_SHIFT, L, q.F64, q.LINK18, 256, 1, 1, 1)
 
 
+@pytest.mark.parametrize("fmt", [q.LINK12, q.LINK18], ids=["f32_12", "f32_18"])
+@pytest.mark.parametrize("L", [(3, 5, 4, 7), (5, 3, 4, 6), (8, 6, 4, 10)], ids=["V420", "V360", "V1920"])
+def test_shared_plane_products_on_ragged_lattices(L, fmt):
+    """LDS tiles 3 and 4 (each plane's upper product formed by one wave and
+    read by the other through LDS, between block barriers) on lattices whose last
+    group is partial or whose group count is odd, so that a 512-thread block
+    also holds a group past the end: the same bits as level 0, and the
+    oracle to 1e-5 after one step."""
+    U = latgen.haar_links(L, 77)
+    c = q.Context(0)
+    res = []
+    for block, lds in ((256, 0), (256, 3), (512, 3), (256, 4), (512, 4)):
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, fmt, block, 1, 0, 1, lds)
+        res.append(ape(L, U, q.F32, fmt, 2, context=c))
+    for V, p in res[1:]:
+        assert np.array_equal(V, res[0][0]) and np.array_equal(p, res[0][1])
+    V1, _ = ape(L, U, q.F32, fmt, 1, context=c)
+    assert link_err(V1, oracle.ape_step(U, 0.5)) < 1e-5
+    c.close()
+
+
 def test_tuner_picks_a_valid_geometry():
     c = q.Context(0)
     L = (8, 8, 8, 8)
     q.qdpx_tune(c, q.OP_APE, L, q.F32, q.LINK12)
     b, n, x, tw, lds = q.qdpx_tune_get(c, q.OP_APE, L, q.F32, q.LINK12)
-    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1, 2) and tw in (1, 2, 4, 8) and lds in (0, 1, 2)
+    assert b in (256, 512) and n in (1, 2, 4) and x in (0, 1, 2) and tw in (1, 2, 4, 8) and lds in (0, 1, 2, 3, 4)
     q.qdpx_tune(c, q.OP_SHIFT, L, q.F64, q.LINK18)
     b, n, x, tw, lds = q.qdpx_tune_get(c, q.OP_SHIFT, L, q.F64, q.LINK18)
     assert b == 256 and n in (1, 2, 4, 8) and x in (0, 1, 2) and tw in (1, 2, 4, 8) and lds == 0
@@ -409,7 +434,7 @@ def test_validation_errors():
     with pytest.raises(q.QdpxError) as e:
         q.qdpx_tune_set(c, q.OP_APE, L, q.F64, q.LINK18, 1024, 1, 1, 1)
     assert e.value.code == -1
-    for op, prec, fmt, lds in ((q.OP_APE, q.F32, q.LINK12, 3), (q.OP_APE, q.F64, q.LINK18, 1),
+    for op, prec, fmt, lds in ((q.OP_APE, q.F32, q.LINK12, 5), (q.OP_APE, q.F64, q.LINK18, 1),
                                (q.OP_SHIFT, q.F32, q.LINK12, 1)):  # LDS tiles only for the FP32 APE step
         with pytest.raises(q.QdpxError) as e:
             q.qdpx_tune_set(c, op, L, prec, fmt, 256, 1, 1, 1, lds)
