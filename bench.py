@@ -37,20 +37,42 @@ ALPHA = 0.5
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.64
 
-# Algorithmic work per link update of one APE step as implemented (rows 0
-# and 1 of the six staples, combination, FP64 projection, and the rebuild of
-# row 2 of the links it reads as rows 0 and 1: the 15 full links of each
-# FP32-12 update, the 10 links each FP64 update reads (one backward link,
-# three per plane)).
-STAPLE_FLOPS = 6 * 2 * 18 * 8  # 6 staples x 2 products x 18 complex FMA x 8 flop
+# Algorithmic work per link update of one APE step as implemented: rows 0
+# and 1 of the six staples (two 2x3 by 3x3 complex products each), the
+# combination, the FP64 projection, and the row-2 rebuilds of the links read
+# as rows 0 and 1.  The FP32 step forms each plane's upper product
+# P = U_mu(x+nu) U_nu(x+mu)^dag (rows 0 and 1, row 2 rebuilt) and the upper
+# staple from it; at LDS tile levels 3 and 4 P is formed once per plane for
+# the two link updates that share it (54 complex FMA per plane instead of
+# 2 x 36), else by each.  Rebuilds per FP32-12 update: 3 per lower staple
+# (2 with the backward links staged, plus 1 for staging), 2 per upper staple
+# formed alone, 6 per plane at levels 3 and 4 from the shared product (4 per
+# plane, 2 per link update: its link, P by the producer, P re-read by
+# producer and consumer).  FP32-18 links are read whole: only P's row 2 is
+# rebuilt (once per upper staple alone, 3 times per shared plane).  FP64
+# update: 10 rebuilds (one backward link, three per plane).
+CMAC_FLOPS = 8
+LOWER_CMAC = 3 * 2 * 18  # three lower staples, two 2x3 by 3x3 products each
+UPPER_CMAC = {False: 3 * 2 * 18, True: 3 * 54 // 2}  # upper staples: each alone / from a shared product
 COMBINE_FLOPS = 12 * 2 * 3
 PROJECT_FLOPS = 126
 REBUILD_FLOPS = 42
-FLOPS_PER_LINK = {
-    "f32_12": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + 15 * REBUILD_FLOPS,
-    "f64_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + 10 * REBUILD_FLOPS,
-    "f32_18": STAPLE_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS,
-}
+
+
+def flops_per_link(name, lds=0):
+    """Flop per link update of the APE step for a link format and LDS tile level."""
+    shared = name != "f64_18" and lds in (3, 4)
+    cmac = LOWER_CMAC + UPPER_CMAC[shared]
+    if name == "f64_18":
+        rebuilds2 = 2 * 10  # twice the rebuilds per link update
+    elif name == "f32_12":
+        staged = lds in (2, 3)
+        rebuilds2 = 2 * (3 * (2 if staged else 3) + (1 if staged else 0)) + 2 * 6
+    else:  # f32_18: only the products' row 2
+        rebuilds2 = 3 * 3 if shared else 2 * 3
+    return cmac * CMAC_FLOPS + COMBINE_FLOPS + PROJECT_FLOPS + rebuilds2 * REBUILD_FLOPS // 2
+
+
 # Compulsory HBM bytes per link update: read the link once (the FP64 step
 # reads rows 0 and 1 only), write it once.
 BYTES_PER_LINK = {"f32_12": 2 * 48, "f64_18": 96 + 144, "f32_18": 2 * 72}
@@ -308,7 +330,8 @@ def main():
 
     def roof(name):
         t_k = kernel[name]
-        flops = FLOPS_PER_LINK[name] * 4 * V
+        fpl = flops_per_link(name, tuned[name]["lds_tile"])
+        flops = fpl * 4 * V
         achieved = flops / t_k / 1e12
         hbm = BYTES_PER_LINK[name] * 4 * V / t_k / 1e9
         return {
@@ -321,7 +344,7 @@ def main():
             "kernel": {"f32_12": "k_ape_step<float,2>", "f64_18": "k_ape_step<double,3>",
                        "f32_18": "k_ape_step<float,3>"}[name],
             "kernel_us": round(t_k * 1e6, 2),
-            "flops_per_link_update": FLOPS_PER_LINK[name],
+            "flops_per_link_update": fpl,
             "hbm_gbs_algorithmic": round(hbm, 1),
             "hbm_frac_algorithmic": round(hbm / PEAK_HBM_GBS, 4),
         }

@@ -73,3 +73,20 @@ def test_launch_table_covers_benchmark_shapes():
             assert block in (256, 512) and nsite in (1, 2, 4)
         else:
             assert op in ("SHIFT", "CHAIN", "JACOBI") and block == 256 and nsite in (1, 2, 4, 8)
+
+
+def test_flops_per_link_update_by_hand():
+    """Flop per APE link update as the kernels do it, counted by hand: 8 per
+    complex FMA, 72 for the combination, 126 for the FP64 projection, 42 per
+    row-2 rebuild.  FP32-12 with every product formed per link: 12 products
+    of 18 complex FMA and 15 rebuilds (three per lower staple, two per upper
+    one); with the backward links staged (LDS tile 2), 13.  With each plane's
+    upper product shared (tiles 3 and 4): the lower staples' 6 products, and
+    per plane 54 complex FMA (P, then the two upper staples) shared by two
+    link updates."""
+    assert bench.flops_per_link("f32_12", 0) == 12 * 18 * 8 + 72 + 126 + 15 * 42
+    assert bench.flops_per_link("f32_12", 2) == 12 * 18 * 8 + 72 + 126 + 13 * 42
+    assert bench.flops_per_link("f32_12", 4) == (6 * 18 + 3 * 54 // 2) * 8 + 72 + 126 + 15 * 42
+    assert bench.flops_per_link("f32_12", 3) == (6 * 18 + 3 * 54 // 2) * 8 + 72 + 126 + 13 * 42
+    assert bench.flops_per_link("f64_18", 0) == 12 * 18 * 8 + 72 + 126 + 10 * 42
+    assert bench.flops_per_link("f32_18", 2) == 12 * 18 * 8 + 72 + 126 + 3 * 42
