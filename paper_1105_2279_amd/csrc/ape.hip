@@ -54,7 +54,10 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
                 stage_own_link(g, U, grp, mu, lane, mine);
                 if constexpr (ape_lds_back(LDS)) stage_back_link(g, U, grp, mu, lane, mine_back);
             }
-            __syncthreads();
+            // the copies are read after this barrier; at level 4 the first
+            // barrier of the staple sum comes before any read of the own
+            // links (its phases read them after their barrier), so it serves
+            if constexpr (LDS != 4) __syncthreads();
             if constexpr (ape_lds_slots(LDS))  // block barriers inside: every wave takes part
                 ape_group_shared<R, NR>(g, U, out, c1, c2, mask, grp, valid, mu, lane, mine, mine_back, mine_slots);
             else if (valid)
