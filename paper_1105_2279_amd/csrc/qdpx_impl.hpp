@@ -18,7 +18,8 @@ struct LaunchCfg {
     int nsite = 1;    // consecutive 64-site groups handled per wave
     int xcd = 1;      // 0: identity, 1: XCD-contiguous tile ranges, 2: XCD slab walk
     int tw = 1;       // t planes walked together (brick mapping only; must divide Lt)
-    int lds = 0;      // LDS tile of the FP32 APE step: 0 none, 1 own links, 2 own and backward links
+    int lds = 0;      // LDS tile of the FP32 APE step: 0 none, 1 own links, 2 also backward links,
+                      // 3 also the plane products, 4 own links and plane products
 };
 
 // Threads per block of the fixed-shape reduction kernels (plaquette,
