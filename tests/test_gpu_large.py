@@ -25,7 +25,7 @@ import torch
 import latgen
 import oracle
 import paper_1105_2279_amd as q
-from gpuhelp import ctx, dev, need_gpu, tol
+from gpuhelp import assert_bench_geometry, bench_ctx, ctx, dev, need_gpu, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +92,8 @@ def samples(seed):
 @pytest.mark.parametrize("kind", ["haar", "near_unit"])
 def test_one_step_sampled(request, kind, prec, fmt):
     U = request.getfixturevalue(kind)
-    c = ctx()
+    c = bench_ctx()  # the launch geometry the benchmark times at this shape
+    assert_bench_geometry("APE", q.OP_APE, L, prec, fmt)
     Ud = q.links_to_device(c, L, U, prec, fmt, dev())
     out = smear(c, Ud, prec, fmt, 1)
     sites, mus = samples(11)
@@ -117,9 +118,10 @@ def test_unit_links_fixed_point_20_steps():
 
 
 def test_20_steps_fp32_12_against_fp64_path(haar):
-    c = ctx()
+    c = bench_ctx()  # the launch geometry the benchmark times at this shape
     res = {}
     for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        assert_bench_geometry("APE", q.OP_APE, L, prec, fmt)
         Ud = q.links_to_device(c, L, haar, prec, fmt, dev())
         plaq = torch.zeros(3 * 21, dtype=torch.float64, device=dev())
         out = smear(c, Ud, prec, fmt, 20, plaq)
@@ -186,8 +188,9 @@ def test_chain_pure_gauge_plane_wave_closed_form():
         coef = h * alpha + a * beta
         norms.append(abs(coef) ** 2 * n0)
         alpha = alpha - cc * coef
-    c = ctx()
+    c = bench_ctx()  # the launch geometry the benchmark times at this shape
     for prec, fmt in ((q.F64, q.LINK18), (q.F32, q.LINK12)):
+        assert_bench_geometry("CHAIN", q.OP_CHAIN, L, prec, fmt)
         Ud = q.links_to_device(c, L, U, prec, fmt, dev())
         pd = q.fermion_to_device(c, L, psi0, prec, dev())
         fd = q.fermion_to_device(c, L, beta * psi0, prec, dev())
