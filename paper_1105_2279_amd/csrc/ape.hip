@@ -37,7 +37,8 @@ __global__ void __launch_bounds__(512) k_ape_step(Geo g, LinksRO<R, NR> U, Links
     static_assert(LDS == 0 || (sizeof(R) == 4 && PROJ == 0), "LDS tiles belong to the FP32 row projection");
     // Dynamic LDS, sized at launch: kF64BackPerWave double2 per wave (FP64), or
     // per group ape_lds_f4_per_group(LDS) FP32 pairs: the own links, then
-    // (LDS >= 2) the backward links, then (LDS = 3) the two product slots.
+    // (LDS 2 and 3) the backward links, then (LDS 3 and 4) the four product
+    // slots.
     extern __shared__ double2 lds_dyn[];
     if constexpr (LDS > 0) {
         nv4_t<R> *tiles = reinterpret_cast<nv4_t<R> *>(lds_dyn);
