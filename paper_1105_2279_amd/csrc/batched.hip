@@ -33,7 +33,9 @@
 
 namespace qdpx {
 
-// LDS tile of the FP32 steps (the single-lattice step's levels 1 to 3).
+// LDS tile of the FP32 steps, a level of the single-lattice step's: 3, the
+// own and backward links and the plane products (levels 2 and 4 measured the
+// same for 12-real links and slower for 18-real ones).
 constexpr int kBatchedLds = 3;
 
 // Largest number of stage-A values a lattice's plaquette reduction may need
@@ -82,7 +84,7 @@ k_ape_batched(BatchArgs a, const BatchLat *__restrict__ lats) {
     __shared__ unsigned s_ticket;
     __shared__ int s_ok;
     // FP32: the LDS tile of the single-lattice step at level kBatchedLds,
-    // each group's own links and (level 2) backward links
+    // each group's own links, backward links and plane-product slots
     __shared__ nv4_t<R> own[GPB][sizeof(R) == 4 ? 4 * 3 * 64 : 1];
     __shared__ nv4_t<R> back[GPB][sizeof(R) == 4 && ape_lds_back(kBatchedLds) ? kApeTileF4 : 1];
     __shared__ nv4_t<R> slots[GPB][sizeof(R) == 4 && ape_lds_slots(kBatchedLds) ? 4 * kApeSlotF4 : 1];
