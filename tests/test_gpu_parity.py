@@ -333,13 +333,14 @@ def test_shared_plane_products_on_ragged_lattices(L, fmt):
     """LDS tiles 3 and 4 (each plane's upper product formed by one wave and
     read by the other through LDS, between block barriers) on lattices whose last
     group is partial or whose group count is odd, so that a 512-thread block
-    also holds a group past the end: the same bits as level 0, and the
-    oracle to 1e-5 after one step."""
+    also holds a group past the end (also with two or four groups per wave):
+    the same bits as level 0, and the oracle to 1e-5 after one step."""
     U = latgen.haar_links(L, 77)
     c = q.Context(0)
     res = []
-    for block, lds in ((256, 0), (256, 3), (512, 3), (256, 4), (512, 4)):
-        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, fmt, block, 1, 0, 1, lds)
+    for block, ns, lds in ((256, 1, 0), (256, 1, 3), (512, 1, 3), (256, 1, 4), (512, 1, 4), (512, 2, 4),
+                           (256, 4, 3)):
+        q.qdpx_tune_set(c, q.OP_APE, L, q.F32, fmt, block, ns, 0, 1, lds)
         res.append(ape(L, U, q.F32, fmt, 2, context=c))
     for V, p in res[1:]:
         assert np.array_equal(V, res[0][0]) and np.array_equal(p, res[0][1])
