@@ -10,8 +10,9 @@
 //   (sum MASK E)        sum over the directions in MASK (hex) of E, the
 //                       direction variable m standing for each in turn
 //
-// The generator writes one HIP kernel per expression (one site per lane;
-// each node becomes straight-line code on a 12-component spinor, a shift
+// The generator writes one HIP kernel per expression (one site per lane,
+// blocks of 256 sites, in FP32 taken so that each XCD walks one contiguous
+// range; each node becomes straight-line code on a 12-component spinor, a shift
 // moves the site index and coordinates, a sum becomes a loop over its
 // directions that is not unrolled), compiles it with
 // hipRTC for the device's architecture with packed FP32 disabled, and keeps
@@ -406,9 +407,22 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
     src << ", double *__restrict__ partials) {\n";
     src << "    const int V = L0 * L1 * L2 * L3;\n"
            "    const int st0 = 1, st1 = L0, st2 = L0 * L1, st3 = L0 * L1 * L2;\n"
-           "    (void)st0;\n"
-           "    const int site = blockIdx.x * 256 + threadIdx.x;\n"
-           "    double n2 = 0.0;\n"
+           "    (void)st0;\n";
+    if (prec == QDPX_F32) {
+        // Blocks reach the 8 XCDs round-robin: block b takes tile
+        // (b mod 8) q + min(b mod 8, r) + b div 8 (nb = 8q + r blocks), a
+        // bijection that gives each XCD one contiguous range of sites, so the
+        // z and t neighbours a block reads were mostly fetched into its own
+        // XCD's L2 by the blocks before it (the FP32 hop 3 % faster at
+        // 32^3x64; the FP64 one, with twice the bytes per site, 12 % slower,
+        // so FP64 kernels keep the plain order).
+        src << "    const int nblk = (int)gridDim.x, blk = (int)blockIdx.x;\n"
+               "    const int xcq = nblk >> 3, xcr = nblk & 7, xcb = blk & 7;\n"
+               "    const int site = (xcb * xcq + min(xcb, xcr) + (blk >> 3)) * 256 + (int)threadIdx.x;\n";
+    } else {
+        src << "    const int site = blockIdx.x * 256 + threadIdx.x;\n";
+    }
+    src << "    double n2 = 0.0;\n"
            "    if (site < V) {\n"
            "    int r = site;\n"
            "    int x0 = r % L0; r /= L0;\n"
@@ -428,10 +442,12 @@ std::string generate(const Node &root, int prec, int nrows, int n_fields, int n_
            "            n2 = fma((double)z.re, (double)z.re, fma((double)z.im, (double)z.im, n2));\n"
            "        }\n"
            "    }\n"
+           // a wave whose first site is past the end has no partial (there
+           // are ceil(V / 64))
            "    if (partials) {  // |out|^2 of each 64-site group, fixed butterfly\n"
            "#pragma unroll\n"
            "        for (int off = 32; off >= 1; off >>= 1) n2 += __shfl_xor(n2, off, 64);\n"
-           "        if ((threadIdx.x & 63) == 0) partials[site >> 6] = n2;\n"
+           "        if ((threadIdx.x & 63) == 0 && site < V) partials[site >> 6] = n2;\n"
            "    }\n"
            "}\n";
     return src.str();
